@@ -1,0 +1,28 @@
+"""Build the FP64 CPU oracle (test infrastructure) into oracle/liboracle.so.
+
+The oracle is plain C++17 compiled by the host compiler with floating-point
+contraction switched off, so that its FP32 contact decisions are the IEEE
+single-precision operations written in the source.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "vmas_oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-Wall", "-o", LIB + ".tmp", SRC, "-lpthread"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

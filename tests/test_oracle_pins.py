@@ -1,0 +1,532 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it follows. The oracle is never compared with
+itself: expected values come from closed forms of the discrete scheme
+(Eq. 1, Eq. 3), invariants that the exact step must satisfy, brute force
+over densely sampled geometry, or textbook special cases.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+from oracle import oracle as O
+from paper_2207_03530_amd import workloads as W
+
+SPH, BOX, LIN = W.SPHERE, W.BOX, W.LINE
+ALL = W.MOVABLE | W.ROTATABLE | W.COLLIDABLE
+
+
+def make(entities, n_agents=None, envs=None, **kw):
+    """World from a list of (shape, d0, d1, x, y, theta, vx, vy, omega, mass, flags)."""
+    N = len(entities)
+    envs = envs or [N]
+    off = np.zeros(len(envs) + 1, np.int32)
+    off[1:] = np.cumsum(envs)
+    st = np.zeros((6, N), np.float32)
+    shape = np.zeros(N, np.uint8)
+    dims = np.zeros((N, 2), np.float32)
+    mass = np.ones(N, np.float32)
+    flags = np.full(N, ALL, np.uint8)
+    for i, e in enumerate(entities):
+        e = dict(e)
+        shape[i] = e.get("shape", SPH)
+        dims[i] = (e.get("d0", 0.05), e.get("d1", 0.0))
+        st[:, i] = (e.get("x", 0), e.get("y", 0), e.get("vx", 0), e.get("vy", 0),
+                    e.get("th", 0), e.get("om", 0))
+        mass[i] = e.get("m", 1.0)
+        flags[i] = e.get("flags", ALL)
+    na = np.array(n_agents if n_agents is not None else [0] * len(envs), np.int32)
+    w = W.World(env_offset=off, n_agents=na, shape=shape, dims=dims, mass=mass, flags=flags,
+                state0=st)
+    for k, v in kw.items():
+        setattr(w, k, v)
+    return w
+
+
+# ------------------------------------------------------------ Eq. 1 / Eq. 3 --
+
+@pytest.mark.parametrize("drag", [0.0, 0.25])
+def test_free_body_closed_form(drag):
+    """Eq. (1) with a constant action force and gravity, no contacts:
+    v_t = a^t v0 + b (1 - a^t)/zeta, x_t = x0 + dt [v0 S + (b/zeta)(t - S)],
+    S = a (1 - a^t)/zeta, a = 1 - zeta, b = (f + m g) dt / m; and the zeta = 0
+    limit v_t = v0 + t b, x_t = x0 + dt (t v0 + b t (t + 1) / 2)."""
+    m, dt, T = 2.0, 0.1, 37
+    g = np.array([0.5, -1.25])
+    f = np.array([0.75, 0.25])
+    w = make([dict(x=0.25, y=-0.5, vx=0.5, vy=-0.25, m=m)], n_agents=[1], dt=dt, drag=drag,
+             gravity=tuple(g))
+    ow = O.OracleWorld(w)
+    act = np.tile(f.astype(np.float32), (T, 1, 1))
+    st, _, tr = ow.rollout(w.state0, act, traj=True)
+    x0 = np.array([0.25, -0.5])
+    v0 = np.array([0.5, -0.25])
+    b = (f + m * g) * dt / m
+    for t in (1, 2, 10, T):
+        if drag == 0.0:
+            v = v0 + t * b
+            x = x0 + dt * (t * v0 + b * t * (t + 1) / 2)
+        else:
+            a = 1 - drag
+            S = a * (1 - a ** t) / drag
+            v = a ** t * v0 + b * (1 - a ** t) / drag
+            x = x0 + dt * (v0 * S + (b / drag) * (t - S))
+        np.testing.assert_allclose(tr[t, 2:4, 0], v, rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(tr[t, 0:2, 0], x, rtol=1e-12, atol=1e-14)
+
+
+def test_angular_free_rotation_closed_form():
+    """Eq. (3) with no torque: omega_t = (1 - zeta)^t omega0 and
+    theta_t = theta0 + dt omega0 a (1 - a^t) / zeta."""
+    drag, dt, T = 0.25, 0.1, 20
+    w = make([dict(shape=BOX, d0=0.1, d1=0.3, th=0.3, om=2.0)], dt=dt, drag=drag)
+    st, _, tr = O.OracleWorld(w).rollout(w.state0, np.zeros((T, 0, 2), np.float32), traj=True)
+    a = 1 - drag
+    for t in (1, 5, T):
+        np.testing.assert_allclose(tr[t, 5, 0], a ** t * 2.0, rtol=1e-13)
+        np.testing.assert_allclose(tr[t, 4, 0], float(np.float32(0.3)) + dt * 2.0 * a * (1 - a ** t) / drag,
+                                   rtol=1e-13)
+
+
+def test_max_speed_saturates_along_force():
+    """Max speed (Sec. 3 'Core'): with a cap the speed saturates at exactly
+    v_max along the force direction; before saturation the closed form holds."""
+    dt, drag, vmax = 0.1, 0.0, 0.3
+    f = np.array([0.6, 0.8], np.float32).astype(np.float64)
+    w = make([dict()], n_agents=[1], dt=dt, drag=drag, max_speed=np.array([vmax], np.float32))
+    T = 12
+    act = np.tile(f.astype(np.float32), (T, 1, 1))
+    st, _, tr = O.OracleWorld(w).rollout(w.state0, act, traj=True)
+    b = f * dt
+    for t in range(1, T + 1):
+        v = t * b
+        sp = np.linalg.norm(v)
+        vm = float(np.float32(vmax))
+        expect = v if sp <= vm else v / sp * vm
+        np.testing.assert_allclose(tr[t, 2:4, 0], expect, rtol=1e-12, atol=1e-15)
+    assert abs(np.linalg.norm(tr[T, 2:4, 0]) - float(np.float32(vmax))) < 1e-12
+
+
+def test_immovable_and_nonrotatable_are_frozen():
+    """Flags (Sec. 3 'Core'): an immovable entity keeps x, v; a non-rotatable
+    one keeps theta, omega, whatever the forces."""
+    w = make([dict(x=0.0, flags=W.COLLIDABLE | W.ROTATABLE, th=0.1, om=0.5, shape=BOX, d0=0.1,
+                   d1=0.3),
+              dict(x=0.04, y=0.01, flags=W.COLLIDABLE | W.MOVABLE, vx=0.1)],
+             n_agents=[0], gravity=(0.0, -9.81))
+    st, mask, _ = O.OracleWorld(w).step(w.state0, np.zeros((0, 2)))
+    assert mask[0] == 1
+    assert np.all(st[0:4, 0] == w.state0[0:4, 0])
+    assert np.all(st[4:6, 1] == w.state0[4:6, 1])
+    assert st[5, 0] != np.float32(0.5) * 0.75  # a torque acted on the rotatable box
+
+
+# ------------------------------------------------------------------- Eq. 2 --
+
+def _two_spheres(d, r=0.25, c=100.0, k=1e-3, m=(1.0, 3.0), dt=0.1):
+    w = make([dict(x=0.0, d0=r, m=m[0]), dict(x=d, d0=r, m=m[1])], dt=dt, drag=0.0,
+             contact_force=c, contact_margin=k)
+    return w
+
+
+def test_contact_force_at_touching_is_ck_ln2():
+    """Eq. (2) at |x_ij| = d_min (inclusive): magnitude c k log 2."""
+    c, k, dt = 100.0, 1e-3, 0.1
+    w = _two_spheres(0.5, c=c, k=k, dt=dt)   # centres 0.5 apart, r = 0.25 each
+    st, mask, forces = O.OracleWorld(w).step(w.state0, np.zeros((0, 2)), want_forces=True)
+    assert mask[0] == 1
+    F = c * k * math.log(2.0)
+    np.testing.assert_allclose(forces[0, 0], -F, rtol=1e-14)  # sphere 0 pushed to -x
+    np.testing.assert_allclose(forces[0, 1], +F, rtol=1e-14)
+    np.testing.assert_allclose(st[2, 0], -F * dt / 1.0, rtol=1e-14)
+    np.testing.assert_allclose(st[2, 1], +F * dt / 3.0, rtol=1e-14)
+
+
+def test_no_force_just_beyond_d_min():
+    """Eq. (2) 'otherwise' branch: one FP32 ulp beyond d_min there is no force."""
+    d = np.nextafter(np.float32(0.5), np.float32(1.0))
+    w = _two_spheres(float(d))
+    st, mask, forces = O.OracleWorld(w).step(w.state0, np.zeros((0, 2)), want_forces=True)
+    assert mask[0] == 0
+    assert np.all(forces == 0)
+
+
+@pytest.mark.parametrize("pen", [1e-4, 3e-3, 0.05, 0.2])
+def test_contact_force_penetration_closed_form(pen):
+    """Eq. (2) with penetration p = d_min - |x_ij|: k log(1 + e^{p/k}) rewritten
+    as p + k log1p(e^{-p/k}), so F = c p + c k log1p(e^{-p/k}); one step from
+    rest changes the velocities by +-F dt / m along the line of centres."""
+    c, k, dt, r = 100.0, 1e-3, 0.1, 0.25
+    d = float(np.float32(2 * r - pen))
+    p = 2 * r - d
+    w = _two_spheres(d, r=r, c=c, k=k, dt=dt)
+    st, mask, forces = O.OracleWorld(w).step(w.state0, np.zeros((0, 2)), want_forces=True)
+    F = c * p + c * k * math.log1p(math.exp(-p / k))
+    np.testing.assert_allclose(-forces[0, 0], F, rtol=1e-12)
+    np.testing.assert_allclose(st[2, 0], -F * dt / 1.0, rtol=1e-12)
+    np.testing.assert_allclose(st[2, 1], F * dt / 3.0, rtol=1e-12)
+    np.testing.assert_allclose(st[0, 1], d + F * dt / 3.0 * dt, rtol=1e-12)
+
+
+def test_coincident_spheres_fallback_normal():
+    """Zero-length x_ij: the deterministic fallback pushes i along +x, j along -x."""
+    w = _two_spheres(0.0)
+    _, _, forces = O.OracleWorld(w).step(w.state0, np.zeros((0, 2)), want_forces=True)
+    assert forces[0, 0] > 0 and forces[0, 1] < 0
+    assert forces[1, 0] == 0 and forces[1, 1] == 0
+
+
+def test_sphere_mask_matches_exact_predicate():
+    """Contact mask between spheres against the exact predicate
+    dx^2 + dy^2 <= (ri + rj)^2 in rational arithmetic (inputs are FP32-exact),
+    away from a 1e-6 relative band where the FP32 decision may round either way."""
+    from fractions import Fraction
+    w = W.spread(64, seed=3)
+    ow = O.OracleWorld(w)
+    _, mask, _ = ow.step(w.state0, w.actions(1)[0])
+    slot, checked = 0, 0
+    for b in range(w.n_envs):
+        o = w.env_offset[b]
+        n = w.env_offset[b + 1] - o
+        for a in range(n):
+            for c in range(a + 1, n):
+                i, j = o + a, o + c
+                fi, fj = w.flags[i], w.flags[j]
+                eligible = bool((fi | fj) & (W.MOVABLE | W.ROTATABLE))
+                dx = Fraction(float(w.state0[0, i])) - Fraction(float(w.state0[0, j]))
+                dy = Fraction(float(w.state0[1, i])) - Fraction(float(w.state0[1, j]))
+                rr = (Fraction(float(w.dims[i, 0])) + Fraction(float(w.dims[j, 0]))) ** 2
+                s = dx * dx + dy * dy
+                if abs(float(s - rr)) > 1e-6 * float(rr):
+                    assert mask[slot] == (1 if (eligible and s <= rr) else 0)
+                    checked += 1
+                slot += 1
+    assert checked > 0.99 * slot
+
+
+# ---------------------------------------------------------- invariants -----
+
+def _dense_world(seed=0, n_envs=6, joints=True):
+    """Mixed shapes crowded into a small box so that every pair type touches."""
+    w = W.mixed(n_envs, n_spheres=5, n_boxes=3, n_lines=4, radius=0.08, joints=joints, seed=seed)
+    w.state0[0:2] *= 0.35
+    w.state0[2:4] = W.draw_sym(seed, 9, np.arange(2 * w.n_entities)).reshape(2, -1) * 0.3
+    w.state0[5] = W.draw_sym(seed, 10, np.arange(w.n_entities)) * 0.5
+    return w
+
+
+def _momentum(w, st):
+    return np.array([np.sum(w.mass * st[2]), np.sum(w.mass * st[3])])
+
+
+def _ang_momentum(w, ow, st):
+    I = np.array([O.default_inertia(int(w.shape[i]), float(w.mass[i]), float(w.dims[i, 0]),
+                                    float(w.dims[i, 1])) for i in range(w.n_entities)])
+    return np.sum(w.mass * (st[0] * st[3] - st[1] * st[2]) + I * st[5])
+
+
+@pytest.mark.parametrize("drag", [0.0, 0.25])
+def test_linear_momentum_recurrence(drag):
+    """Pair forces of Eq. (2) and the joints are equal and opposite, so with
+    every entity movable P_{t+1} = (1 - zeta) P_t + dt (sum f^a + sum m g)
+    exactly (up to FP64 rounding) for any contacts."""
+    w = _dense_world()
+    w.drag = drag
+    w.gravity = (0.3, -0.7)
+    ow = O.OracleWorld(w)
+    act = w.actions(15)
+    st = w.state0.astype(np.float64)
+    contacts = 0
+    for t in range(15):
+        P0 = _momentum(w, st)
+        st2, mask, _ = ow.step(st, act[t])
+        contacts += int(mask.sum())
+        P1 = _momentum(w, st2)
+        ext = act[t].astype(np.float64).sum(0) + np.sum(w.mass) * np.array(w.gravity)
+        np.testing.assert_allclose(P1, (1 - drag) * P0 + w.dt * ext, rtol=0, atol=1e-11)
+        st = st2
+    assert contacts > 20
+
+
+@pytest.mark.parametrize("drag", [0.0, 0.25])
+def test_angular_momentum_recurrence(drag):
+    """Signed torque with arm (contact point - centre), Eq. (3): for each pair
+    (p_i - p_j) is parallel to f, so L = sum(m x cross v + I omega) obeys
+    L_{t+1} = (1 - zeta) L_t + dt sum x_i cross (f^a_i + m_i g) exactly.
+    A norm (unsigned) torque or a wrong arm breaks it."""
+    w = _dense_world(seed=1)
+    w.drag = drag
+    w.gravity = (0.2, -0.5)
+    ow = O.OracleWorld(w)
+    act = w.actions(15)
+    st = w.state0.astype(np.float64)
+    agents = w.agent_ids()
+    torques = 0.0
+    for t in range(15):
+        L0 = _ang_momentum(w, ow, st)
+        st2, mask, forces = ow.step(st, act[t], want_forces=True)
+        torques += np.abs(forces[2]).sum()
+        fa = np.zeros((2, w.n_entities))
+        fa[:, agents] = act[t].T
+        fe = fa + w.mass[None, :] * np.array(w.gravity)[:, None]
+        ext = np.sum(st[0] * fe[1] - st[1] * fe[0])
+        L1 = _ang_momentum(w, ow, st2)
+        np.testing.assert_allclose(L1, (1 - drag) * L0 + w.dt * ext, rtol=0, atol=1e-11)
+        st = st2
+    assert torques > 1.0
+
+
+def test_rigid_motion_equivariance():
+    """Rotating and translating a whole environment rotates the forces and
+    leaves the torques and (away from the threshold) the mask unchanged."""
+    w = _dense_world(seed=2, n_envs=3)
+    ow = O.OracleWorld(w)
+    act = np.zeros((w.n_agents_total, 2))
+    st = w.state0.astype(np.float64)
+    _, m1, f1 = ow.step(st, act, want_forces=True)
+    phi, tx, ty = 0.7, 0.3, -0.2
+    R = np.array([[math.cos(phi), -math.sin(phi)], [math.sin(phi), math.cos(phi)]])
+    st2 = st.copy()
+    st2[0:2] = R @ st[0:2] + np.array([[tx], [ty]])
+    st2[2:4] = R @ st[2:4]
+    st2[4] = st[4] + phi
+    _, m2, f2 = ow.step(st2, act, want_forces=True)
+    np.testing.assert_allclose(f2[0:2], R @ f1[0:2], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(f2[2], f1[2], rtol=0, atol=1e-9)
+    assert (m1 != m2).sum() <= 1
+
+
+# ------------------------------------------------------ narrow phase ------
+
+def _boundary_points(shape, d0, d1, pose, n=10000):
+    """Dense samples of the core of a shape: the centre of a sphere, the
+    segment of a line, the outline of a box."""
+    x, y, th = pose
+    c, s = math.cos(th), math.sin(th)
+    if shape == SPH:
+        loc = np.zeros((1, 2))
+    elif shape == LIN:
+        t = np.linspace(-d0 / 2, d0 / 2, n)
+        loc = np.stack([t, np.zeros_like(t)], 1)
+    else:
+        hx, hy = d0 / 2, d1 / 2
+        t = np.linspace(-1, 1, n)
+        loc = np.concatenate([np.stack([hx * np.ones_like(t), hy * t], 1),
+                              np.stack([-hx * np.ones_like(t), hy * t], 1),
+                              np.stack([hx * t, hy * np.ones_like(t)], 1),
+                              np.stack([hx * t, -hy * np.ones_like(t)], 1)])
+    R = np.array([[c, -s], [s, c]])
+    return loc @ R.T + np.array([x, y])
+
+
+def _vertices(shape, d0, d1, pose):
+    x, y, th = pose
+    c, s = math.cos(th), math.sin(th)
+    if shape == SPH:
+        loc = np.zeros((1, 2))
+    elif shape == LIN:
+        loc = np.array([[-d0 / 2, 0], [d0 / 2, 0]])
+    else:
+        hx, hy = d0 / 2, d1 / 2
+        loc = np.array([[hx, hy], [-hx, hy], [-hx, -hy], [hx, -hy]])
+    return loc @ np.array([[c, -s], [s, c]]).T + np.array([x, y])
+
+
+def _penetration_depth(Vi, Vj, ndir=3600):
+    """Minimum translation distance of two convex sets by brute force over
+    directions: min_s h_j(s) + h_i(-s) (support functions of the vertices),
+    on 3600 directions, then refined around the best coarse minima on a
+    1e-7 rad grid (the function has a kink at its minimum)."""
+    def overlap(ang):
+        S = np.stack([np.cos(ang), np.sin(ang)], 1)
+        return (Vj @ S.T).max(0) + (-(Vi @ S.T)).max(0)
+    step = 2 * math.pi / ndir
+    ang = np.arange(ndir) * step
+    o = overlap(ang)
+    best = np.inf
+    for q in np.argsort(o)[:8]:
+        fine = ang[q] + np.linspace(-2 * step, 2 * step, 70001)
+        best = min(best, overlap(fine).min())
+    return best
+
+
+def _inside(shape, d0, d1, pose, p):
+    x, y, th = pose
+    c, s = math.cos(th), math.sin(th)
+    u = np.array([c * (p[0] - x) + s * (p[1] - y), -s * (p[0] - x) + c * (p[1] - y)])
+    if shape == BOX:
+        return abs(u[0]) <= d0 / 2 + 1e-9 and abs(u[1]) <= d1 / 2 + 1e-9
+    if shape == LIN:
+        return abs(u[1]) <= 1e-9 and abs(u[0]) <= d0 / 2 + 1e-9
+    return np.hypot(*u) <= 1e-9
+
+
+SHAPES = [(SPH, 0.05, 0.0), (BOX, 0.1, 0.3), (LIN, 0.5, 0.0), (BOX, 0.4, 0.2), (LIN, 0.3, 0.0)]
+
+
+def _random_pairs(seed, n):
+    rng = np.random.default_rng(seed)
+    for _ in range(n):
+        a = SHAPES[rng.integers(len(SHAPES))]
+        b = SHAPES[rng.integers(len(SHAPES))]
+        pa = (rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), rng.uniform(-math.pi, math.pi))
+        pb = (rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), rng.uniform(-math.pi, math.pi))
+        yield a, pa, b, pb
+
+
+def test_narrow_phase_separated_brute_force():
+    """Closest points (Eq. 2, 'closest points on the shapes'): for separated
+    cores, d equals the brute-force minimum distance between densely sampled
+    cores, n is the unit vector p_j -> p_i, and the points lie on the cores."""
+    seen = set()
+    for (a, pa, b, pb) in _random_pairs(0, 120):
+        d, n, pi, pj = O.pair(a[0], a[1:], pa, b[0], b[1:], pb)
+        if d <= 0:
+            continue
+        seen.add((a[0], b[0]))
+        Pi = _boundary_points(a[0], a[1], a[2], pa)
+        Pj = _boundary_points(b[0], b[1], b[2], pb)
+        brute = cKDTree(Pi).query(Pj)[0].min()
+        pitch = 2 * max(a[1], a[2], b[1], b[2]) / 10000 * 2
+        assert d <= brute + 1e-12
+        assert brute - d <= pitch
+        np.testing.assert_allclose(np.linalg.norm(pi - pj), d, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(n, (pi - pj) / d, rtol=1e-9, atol=1e-9)
+        assert np.min(np.linalg.norm(Pi - pi, axis=1)) <= pitch + 1e-12
+        assert np.min(np.linalg.norm(Pj - pj, axis=1)) <= pitch + 1e-12
+    assert len(seen) >= 8
+
+
+def test_narrow_phase_overlap_penetration_depth():
+    """Overlapping cores: -d equals the brute-force minimum translation
+    distance (3600 directions, support functions), and the sign of d agrees
+    with an independent point-in-shape / crossing predicate."""
+    seen = set()
+    for (a, pa, b, pb) in _random_pairs(1, 1500):
+        if a[0] == SPH and b[0] == SPH:
+            continue
+        if (a[0] == SPH and b[0] == LIN) or (a[0] == LIN and b[0] == SPH):
+            continue  # a point and a segment never overlap with positive depth
+        d, n, pi, pj = O.pair(a[0], a[1:], pa, b[0], b[1:], pb)
+        if d >= 0:
+            continue
+        seen.add((a[0], b[0]))
+        Vi = _vertices(a[0], a[1], a[2], pa)
+        Vj = _vertices(b[0], b[1], b[2], pb)
+        pd = _penetration_depth(Vi, Vj)
+        assert -1e-12 <= pd - (-d) <= 1e-7   # sampled minimum is never below the true one
+        # moving i by -d along n separates the supports along n
+        hj = (Vj @ n).max()
+        li = (Vi @ n).min()
+        np.testing.assert_allclose(hj - li, -d, rtol=1e-9, atol=1e-12)
+        if a[0] == SPH:
+            assert _inside(b[0], b[1], b[2], pb, np.array(pa[:2]))
+        if b[0] == SPH:
+            assert _inside(a[0], a[1], a[2], pa, np.array(pb[:2]))
+    assert len(seen) >= 6
+
+
+def test_narrow_phase_swap_symmetry():
+    """Evaluating (j, i) gives the same d, the opposite normal and the
+    swapped contact points."""
+    for (a, pa, b, pb) in _random_pairs(2, 400):
+        d1, n1, pi1, pj1 = O.pair(a[0], a[1:], pa, b[0], b[1:], pb)
+        d2, n2, pi2, pj2 = O.pair(b[0], b[1:], pb, a[0], a[1:], pa)
+        np.testing.assert_allclose(d1, d2, rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(n1, -n2, rtol=1e-9, atol=1e-9)
+        if d1 > 1e-9:
+            np.testing.assert_allclose(pi1, pj2, atol=1e-9)
+            np.testing.assert_allclose(pj1, pi2, atol=1e-9)
+
+
+@pytest.mark.parametrize("other", [(LIN, 0.5, 0.0), (BOX, 0.1, 0.3)])
+def test_narrow_phase_continuous_through_touching(other):
+    """Sweeping a line through another line or a box: d is continuous across
+    the change of branch (distance <-> overlap) and n does not flip."""
+    ys = np.linspace(0.4, -0.4, 8001)
+    prev = None
+    for y in ys:
+        d, n, _, _ = O.pair(LIN, (0.3, 0.0), (0.05, y, 0.2), other[0], other[1:],
+                            (0.0, 0.0, 0.05))
+        if prev is not None:
+            assert abs(d - prev[0]) < 5e-4
+            if abs(d) < 0.02 and abs(prev[1]) < 0.02:
+                assert np.dot(n, prev[2]) > 0.5
+        prev = (d, d, n)
+
+
+def test_default_inertia_by_quadrature():
+    """Default moments of inertia equal the integral of r^2 dm over a uniform
+    disc, rectangle and thin rod (midpoint quadrature)."""
+    m = 2.0
+    g = (np.arange(400) + 0.5) / 400
+    X, Y = np.meshgrid(g * 2 - 1, g * 2 - 1)
+    disc = (X ** 2 + Y ** 2 <= 1)
+    r = 0.3
+    I_disc = m * np.sum((X[disc] ** 2 + Y[disc] ** 2) * r ** 2) / disc.sum()
+    assert abs(O.default_inertia(SPH, m, r) - I_disc) / I_disc < 1e-3
+    lx, ly = 0.1, 0.3
+    I_rect = m * np.mean((X * lx / 2) ** 2 + (Y * ly / 2) ** 2)
+    assert abs(O.default_inertia(BOX, m, lx, ly) - I_rect) / I_rect < 1e-3
+    L = 0.5
+    I_rod = m * np.mean((g * L - L / 2) ** 2)
+    assert abs(O.default_inertia(LIN, m, L) - I_rod) / I_rod < 1e-3
+
+
+# ------------------------------------------------------------------ joints --
+
+@pytest.mark.parametrize("drag", [0.0, 0.25])
+def test_joint_affine_recurrence(drag):
+    """Two free bodies on the x axis joined at their centres, no actions:
+    the step is the affine map s_{t+1} = M s_t + q on (xa, va, xb, vb), so
+    s_t = M^t s_0 (+ the affine part), evaluated as a 5x5 matrix power."""
+    cj, dt, L0, ma, mb = 40.0, 0.05, 0.3, 1.0, 2.5
+    w = make([dict(x=0.45, vx=0.1, m=ma, d0=0.01), dict(x=0.0, vx=-0.2, m=mb, d0=0.01)],
+             dt=dt, drag=drag, joint_stiffness=cj,
+             joint_a=np.array([0], np.int32), joint_b=np.array([1], np.int32),
+             anchor_a=np.zeros((1, 2), np.float32), anchor_b=np.zeros((1, 2), np.float32),
+             joint_rest=np.array([L0], np.float32))
+    T = 40
+    st, _, tr = O.OracleWorld(w).rollout(w.state0, np.zeros((T, 0, 2), np.float32), traj=True)
+    a = 1 - drag
+    L0f = float(np.float32(L0))
+    # velocity rows use positions at t, position rows use the new velocity
+    Va = np.array([-cj * dt / ma, a, cj * dt / ma, 0.0, cj * dt / ma * L0f])
+    Vb = np.array([cj * dt / mb, 0.0, -cj * dt / mb, a, -cj * dt / mb * L0f])
+    M = np.zeros((5, 5))
+    M[1] = Va
+    M[0] = np.eye(5)[0] + dt * Va
+    M[3] = Vb
+    M[2] = np.eye(5)[2] + dt * Vb
+    M[4, 4] = 1
+    s0 = np.array([w.state0[0, 0], w.state0[2, 0], w.state0[0, 1], w.state0[2, 1], 1.0],
+                  np.float64)
+    for t in (1, 7, T):
+        s = np.linalg.matrix_power(M, t) @ s0
+        np.testing.assert_allclose([tr[t, 0, 0], tr[t, 2, 0], tr[t, 0, 1], tr[t, 2, 1]], s[:4],
+                                   rtol=1e-10, atol=1e-12)
+        assert tr[t, 0, 0] > tr[t, 0, 1]
+
+
+# ------------------------------------------------------------------ energy --
+
+def test_head_on_collision_exchanges_velocities():
+    """Elastic-like collisions (Sec. 1): head-on equal spheres, zeta = 0,
+    dt = 1e-3, +-0.5 m/s: after separation the velocities are exchanged within
+    3 %, kinetic energy within 3 %, momentum exactly."""
+    r = 0.05
+    w = make([dict(x=-0.2, vx=0.5, d0=r), dict(x=0.2, vx=-0.5, d0=r)], dt=1e-3, drag=0.0,
+             contact_force=100.0, contact_margin=1e-3)
+    T = 900
+    st, _, tr = O.OracleWorld(w).rollout(w.state0, np.zeros((T, 0, 2), np.float32), traj=True)
+    gap = tr[:, 0, 1] - tr[:, 0, 0]
+    assert gap.min() < 2 * r            # they did touch
+    assert gap[-1] > 2 * r              # and separated again
+    v0, v1 = st[2, 0], st[2, 1]
+    assert abs(v0 - (-0.5)) < 0.015 and abs(v1 - 0.5) < 0.015
+    ke0 = 0.5 * (0.5 ** 2 + 0.5 ** 2)
+    ke1 = 0.5 * (v0 ** 2 + v1 ** 2)
+    assert 0.97 <= ke1 / ke0 <= 1.03
+    assert abs(v0 + v1) < 1e-12
