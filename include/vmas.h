@@ -1,0 +1,225 @@
+/*
+ * vmas.h -- C boundary of the MI355X (gfx950) batched 2D physics step.
+ *
+ * The method is the world step of VMAS (Bettini et al., 2022), Sec. 3 "Core":
+ *   Eq. (1)  f_i = f^a_i + m_i g + sum_{j != i} f^e_ij ;
+ *            xdot_i(t+1) = (1 - zeta) xdot_i(t) + f_i / m_i dt ;
+ *            x_i(t+1)    = x_i(t) + xdot_i(t+1) dt
+ *   Eq. (2)  f^e_ij = c * x_ij/|x_ij| * k * log(1 + exp(-(|x_ij| - d_min)/k))
+ *            if |x_ij| <= d_min, else 0 ; x_ij joins the closest points
+ *   Eq. (3)  tau_i = sum_j r_ij x f^e_ij (signed), then the same update on
+ *            (theta, omega) with moment of inertia I_i.
+ * for every entity of every environment of a batch, all environments at once.
+ *
+ * Readings where the paper is silent (all fixed by this library):
+ *   - shapes: a sphere's core is its centre (radius enters d_min), a line is
+ *     a segment along its local x axis of length L, a box a solid lx x ly
+ *     rectangle; |x_ij| is the signed distance between cores (negative when
+ *     they overlap, by the separating-axis test), d_min = rho_i + rho_j +
+ *     min_dist with rho = r for spheres and 0 otherwise;
+ *   - the torque of Eq. (3) is the signed 2D cross product of the arm
+ *     (contact point - centre) with the force;
+ *   - flags: immovable entities keep x and v (no gravity), non-rotatable ones
+ *     keep theta and omega, non-collidable ones take part in no pair; a pair
+ *     where neither entity can move or rotate is skipped;
+ *   - the action of an agent is a force at its centre (no torque);
+ *   - the max speed clamps |v| after the velocity update, keeping direction;
+ *   - default moments of inertia: disc m r^2/2, rectangle m (lx^2+ly^2)/12,
+ *     rod m L^2/12;
+ *   - a joint is a linear spring of stiffness joint_stiffness between two
+ *     body-frame anchor points (rest length: given, or the anchor distance in
+ *     the initial state); by default the two jointed entities do not collide.
+ *   - the contact decision |x_ij| <= d_min is taken in FP32; between two
+ *     spheres it is fl(dx*dx) + fl(dy*dy) <= fl(d_min*d_min) with
+ *     dx = fl(x_i - x_j), dy = fl(y_i - y_j), d_min = fl(fl(r_i + r_j) + min_dist).
+ *
+ * Memory. Every state, action, mask, force and gradient buffer passed to the
+ * step calls is DEVICE memory owned by the caller; the library never frees
+ * or retains those pointers after a call returns. The handle owns its own
+ * device copies of the static description (shapes, masses, joints, launch
+ * plans, checkpoint workspace); vmas_destroy_batch frees them.
+ *
+ * Layouts.
+ *   state    float32 [6][N], field-major: x, y, vx, vy, theta, omega; the
+ *            entities of an environment are contiguous, environments in order.
+ *   actions  float32 [A][2] per step ([T][A][2] for rollouts): one row per
+ *            agent; the agents of environment b are its first n_agents[b]
+ *            entities, rows in environment order.
+ *   mask     uint8 [P], P = sum_b n_b (n_b - 1) / 2: one byte per pair slot,
+ *            environments in order, pairs (a < c) of local indices in
+ *            lexicographic order; 1 when the pair is in contact (Eq. 2 active),
+ *            0 otherwise (also for pairs that are not eligible).
+ *   forces   float32 [3][N]: total force x, y and torque on each entity that
+ *            can move or rotate (Eq. 1 first row, Eq. 3 first row); 0 for the
+ *            others.
+ *
+ * Streams and errors. All device work is enqueued on the caller's stream
+ * (a hipStream_t passed as void*, NULL = the default stream) and the calls
+ * return after enqueue; only vmas_create_batch blocks. Arguments are checked
+ * on the host before any device work: a bad argument returns
+ * VMAS_ERR_INVALID_ARGUMENT, a HIP failure VMAS_ERR_DEVICE; the reason is in
+ * vmas_last_error() (thread-local, valid until the next call on that thread).
+ * A handle must not be used from two threads at once; calls on different
+ * handles are independent. Calls that overlap on one stream are ordered by it.
+ */
+#ifndef VMAS_H
+#define VMAS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VMAS_OK = 0,
+  VMAS_ERR_INVALID_ARGUMENT = 1,
+  VMAS_ERR_OUT_OF_MEMORY = 2,
+  VMAS_ERR_DEVICE = 3,
+  VMAS_ERR_UNSUPPORTED = 4,
+  VMAS_ERR_NONFINITE = 5
+} vmas_status;
+
+typedef enum { VMAS_SHAPE_SPHERE = 0, VMAS_SHAPE_BOX = 1, VMAS_SHAPE_LINE = 2 } vmas_shape;
+
+/* Entity flag bits (Sec. 3 "Core": movable, rotatable, collidable). */
+enum { VMAS_MOVABLE = 1, VMAS_ROTATABLE = 2, VMAS_COLLIDABLE = 4 };
+
+/* World parameters (Sec. 3: dt, zeta, g; Eq. 2: c, k, d_min). */
+typedef struct {
+  float dt;               /* integration step delta t > 0 */
+  float drag;             /* velocity damping zeta in [0, 1] */
+  float gravity[2];       /* g */
+  float contact_force;    /* c >= 0 */
+  float contact_margin;   /* k > 0 */
+  float min_dist;         /* added to every pair's d_min (>= 0) */
+  float joint_stiffness;  /* spring constant of every joint (>= 0) */
+  uint32_t flags;         /* reserved, must be 0 */
+} vmas_world_params;
+
+/* Static description of a batch. All pointers are HOST memory, read during
+ * vmas_create_batch only. N = total entities, A = total agents, J = joints. */
+typedef struct {
+  int32_t n_envs;                 /* >= 1 */
+  const int32_t* env_offset;      /* [n_envs+1] entity offsets, or NULL: uniform */
+  int32_t n_per_env;              /* entities per environment when env_offset is NULL */
+  const int32_t* n_agents;        /* [n_envs], 0 <= n_agents[b] <= n_b */
+  const uint8_t* shape;           /* [N] vmas_shape */
+  const float* dims;              /* [N][2]: sphere (r, -), box (lx, ly), line (L, -); > 0 */
+  const float* mass;              /* [N] > 0 for entities that can move or rotate */
+  const float* inertia;           /* [N] or NULL; <= 0 selects the textbook default */
+  const float* max_speed;         /* [N] or NULL; <= 0: no clamp */
+  const uint8_t* flags;           /* [N] VMAS_MOVABLE | VMAS_ROTATABLE | VMAS_COLLIDABLE */
+  int32_t n_joints;               /* J >= 0 */
+  const int32_t* joint_a;         /* [J] global entity ids, both in one environment */
+  const int32_t* joint_b;         /* [J] */
+  const float* joint_anchor_a;    /* [J][2] body-frame anchor on a */
+  const float* joint_anchor_b;    /* [J][2] body-frame anchor on b */
+  const float* joint_rest;        /* [J] rest length; < 0: anchor distance in init_state */
+  const uint8_t* joint_collide;   /* [J] or NULL: 0 = the jointed pair does not collide */
+  const float* init_state;        /* [6][N] host state, needed only when a rest length is < 0 */
+} vmas_batch_desc;
+
+typedef struct vmas_batch vmas_batch; /* opaque handle */
+
+typedef struct {
+  int32_t n_envs;
+  int32_t n_entities;    /* N */
+  int32_t n_agents;      /* A */
+  int32_t n_joints;      /* J */
+  int64_t n_pair_slots;  /* P */
+  int32_t schedule;      /* current launch plan id (see vmas_set_schedule) */
+  int32_t n_schedules;   /* number of launch plans available */
+  int32_t max_env_size;  /* largest n_b */
+  int32_t reserved;
+} vmas_batch_info;
+
+/* Creates a batch on HIP device `device`: validates the description, copies
+ * it to the device and builds the launch plans. Blocks until the upload is
+ * done. On success *out owns device memory until vmas_destroy_batch. */
+vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_desc* desc,
+                              int device, vmas_batch** out);
+
+/* Frees the handle and all device memory it owns (NULL is accepted). The
+ * caller must make sure no work that uses the handle is still running. */
+vmas_status vmas_destroy_batch(vmas_batch* batch);
+
+vmas_status vmas_batch_get_info(const vmas_batch* batch, vmas_batch_info* info);
+
+/* One step (Eq. 1-3) of every environment, state updated in place.
+ *   state    device float32 [6][N] (in/out)
+ *   actions  device float32 [A][2] (may be NULL only when A == 0)
+ *   mask     device uint8 [P] or NULL: contact mask of this step
+ *   forces   device float32 [3][N] or NULL: forces and torques of this step */
+vmas_status vmas_step(vmas_batch* batch, float* state, const float* actions, uint8_t* mask,
+                      float* forces, void* stream);
+
+/* T consecutive steps in one persistent launch; the state stays on chip
+ * between steps and only the actions stream in.
+ *   state       device float32 [6][N] (in/out): state at t0 in, at t0+T out
+ *   actions     device float32 [T][A][2], or NULL: the actions are drawn in
+ *               the kernel, uniform in [-1, 1)^2, from the counter-based
+ *               SplitMix64 stream (seed = action_seed, stream 2, element
+ *               ((t0 + t) * A + agent) * 2 + comp; u = (draw >> 40) 2^-24,
+ *               a = 2u - 1)
+ *   t0          step index of the first step (only used for drawn actions)
+ *   T           number of steps, >= 0
+ *   traj        device float32 [T+1][6][N] or NULL: the state after every step
+ *               (index 0 = input state)
+ *   final_mask  device uint8 [P] or NULL: contact mask of the last step
+ * Splitting a rollout (T = k + (T - k), same actions) gives bitwise the same
+ * final state. */
+vmas_status vmas_rollout(vmas_batch* batch, float* state, const float* actions,
+                         uint64_t action_seed, int32_t t0, int32_t T, float* traj,
+                         uint8_t* final_mask, void* stream);
+
+/* Reverse-mode derivative of one vmas_step (hand-written adjoint; contact
+ * decisions and the branches of the closest-point routines are held fixed).
+ *   state_t          device float32 [6][N]: the state the step started from
+ *   actions_t        device float32 [A][2]
+ *   grad_state_next  device float32 [6][N]: dL/d state_{t+1}
+ *   grad_state_t     device float32 [6][N] (out): dL/d state_t
+ *   grad_actions_t   device float32 [A][2] (out) or NULL: dL/d actions_t */
+vmas_status vmas_step_backward(vmas_batch* batch, const float* state_t, const float* actions_t,
+                               const float* grad_state_next, float* grad_state_t,
+                               float* grad_actions_t, void* stream);
+
+/* Reverse-mode derivative of a T-step rollout with checkpointing: the
+ * forward pass is replayed from checkpoints stored every `ckpt_every` steps
+ * (workspace owned by the handle, ceil(T / ckpt_every) + ckpt_every + 1 states),
+ * so memory is O(T / k + k) states instead of O(T).
+ *   state0        device float32 [6][N]: initial state
+ *   actions       device float32 [T][A][2]
+ *   grad_state_T  device float32 [6][N]: dL/d state_T
+ *   grad_state0   device float32 [6][N] (out) or NULL
+ *   grad_actions  device float32 [T][A][2] (out) or NULL */
+vmas_status vmas_rollout_backward(vmas_batch* batch, const float* state0, const float* actions,
+                                  int32_t T, int32_t ckpt_every, const float* grad_state_T,
+                                  float* grad_state0, float* grad_actions, void* stream);
+
+/* Launch plans. Plan ids are 0 .. n_schedules-1 (see vmas_schedule_name);
+ * every plan computes the same results bit for bit. vmas_autotune times each
+ * plan on a T-step rollout of a scratch copy of `state` (state itself is not
+ * modified), keeps the fastest and returns its id in *chosen. It
+ * synchronises the stream. */
+vmas_status vmas_set_schedule(vmas_batch* batch, int32_t schedule);
+vmas_status vmas_autotune(vmas_batch* batch, const float* state, int32_t T, void* stream,
+                          int32_t* chosen);
+const char* vmas_schedule_name(const vmas_batch* batch, int32_t schedule);
+
+/* Rollout through a cached hipGraph: the first call captures the launch on
+ * `stream`, later calls with the same (T, traj == NULL, mask == NULL,
+ * actions == NULL) shape rebind the kernel arguments and replay the graph.
+ * Same arguments and results as vmas_rollout. */
+vmas_status vmas_rollout_graph(vmas_batch* batch, float* state, const float* actions,
+                               uint64_t action_seed, int32_t t0, int32_t T, float* traj,
+                               uint8_t* final_mask, void* stream);
+
+/* Reason for the last failure on this thread ("" if none). */
+const char* vmas_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VMAS_H */

@@ -74,6 +74,7 @@ def lib():
                                            ctypes.c_int, _f64p, _u8p]
         L.oracle_rollout_jvp.argtypes = [wp, _f64p, _f64p, _f64p, _f64p, ctypes.c_int]
         L.oracle_pair.argtypes = [ctypes.c_int, _f64p, _f64p, ctypes.c_int, _f64p, _f64p, _f64p]
+        L.oracle_pair_distances.argtypes = [wp, _f64p, _f64p, _f64p]
         L.oracle_default_inertia.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double]
         L.oracle_default_inertia.restype = ctypes.c_double
@@ -186,6 +187,16 @@ class OracleWorld:
         lib().oracle_rollout_jvp(ctypes.byref(self.s), _p(st, _f64p), _p(dst, _f64p),
                                  _p(act, _f64p), _p(dact, _f64p), T)
         return st, dst
+
+
+def pair_distances(ow: "OracleWorld", state: np.ndarray):
+    """(d, d_min) per pair slot from the FP64 narrow phase (NaN: not eligible)."""
+    st = np.ascontiguousarray(state, np.float64)
+    P = ow.w.pair_slots()
+    d = np.zeros(P, np.float64)
+    dm = np.zeros(P, np.float64)
+    lib().oracle_pair_distances(ctypes.byref(ow.s), _p(st, _f64p), _p(d, _f64p), _p(dm, _f64p))
+    return d, dm
 
 
 def rollout_threaded(ow: OracleWorld, state: np.ndarray, actions: np.ndarray, threads: int):

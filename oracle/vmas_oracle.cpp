@@ -799,6 +799,40 @@ int oracle_pair(int si, const double* di, const double* pose_i, int sj, const do
   return 0;
 }
 
+// Signed core distance d and d_min of every pair slot (same slot order as
+// the mask; NaN for pairs that are not eligible), from the FP64 narrow phase.
+int oracle_pair_distances(const oracle_world* w, const double* state, double* d_out,
+                          double* dmin_out) {
+  const int N = w->env_offset[w->n_envs];
+  const double *X = state, *Y = state + N, *TH = state + 4 * N;
+  std::vector<int> js;
+  int64_t slot = 0;
+  for (int b = 0; b < w->n_envs; ++b) {
+    const int o = w->env_offset[b], n = w->env_offset[b + 1] - o;
+    js.clear();
+    for (int q = 0; q < w->n_joints; ++q)
+      if (w->joint_a[q] >= o && w->joint_a[q] < o + n) js.push_back(q);
+    for (int a = 0; a < n; ++a) {
+      for (int c = a + 1; c < n; ++c, ++slot) {
+        int i = o + a, j = o + c;
+        if (!pair_eligible(w, js.data(), (int)js.size(), i, j)) {
+          d_out[slot] = NAN;
+          dmin_out[slot] = NAN;
+          continue;
+        }
+        Pose<double> pi = pose_of(X, Y, TH, i), pj = pose_of(X, Y, TH, j);
+        Contact<double> r = narrow<double>(w->shape[i], w->dims[2 * i], w->dims[2 * i + 1], pi,
+                                           w->shape[j], w->dims[2 * j], w->dims[2 * j + 1], pj);
+        double ri = w->shape[i] == SPHERE ? w->dims[2 * i] : 0.0;
+        double rj = w->shape[j] == SPHERE ? w->dims[2 * j] : 0.0;
+        d_out[slot] = r.d;
+        dmin_out[slot] = ri + rj + w->min_dist;
+      }
+    }
+  }
+  return 0;
+}
+
 // Textbook moment of inertia used when none is given.
 double oracle_default_inertia(int shape, double m, double d0, double d1) {
   return default_inertia(shape, m, d0, d1);

@@ -1,0 +1,113 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// the batched 2D physics step (VMAS, Sec. 3 "Core", Eq. 1-3). Not part of the
+// public boundary (include/vmas.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vmas {
+
+enum : int { SPHERE = 0, BOX = 1, LINE = 2 };
+enum : int { MOVABLE = 1, ROTATABLE = 2, COLLIDABLE = 4 };
+
+// Static per-entity parameters, one 48-byte record per entity.
+struct EntParam {
+  float d0, d1;        // sphere (r, 0), box (lx, ly), line (L, 0)
+  float inv_m, inv_I;  // 1/m, 1/I
+  float vmax;          // <= 0: no speed cap
+  float rho;           // radius added to d_min: r for spheres, 0 otherwise
+  float mgx, mgy;      // gravity force m g (0 unless movable)
+  int32_t sf;          // shape | flags << 8
+  int32_t excl;        // up to 4 environment-local partner indices (one byte
+                       // each, 0xff = none) whose contact a joint switches off
+  int32_t pad[2];
+};
+
+// One lane of a launch group: the entity it integrates and where it sits.
+struct LaneRec {
+  int32_t ent;    // global entity id, -1 = idle lane
+  int32_t slot;   // LDS slot of the entity inside the group
+  int32_t lo;     // LDS slot of the first entity of its environment
+  int32_t hi;     // one past the last
+  int32_t agent;  // action row, -1 = not an agent
+  int32_t env;    // environment id
+  int32_t first;  // global id of the first entity of its environment
+  int32_t pad;
+};
+
+// A joint: linear spring between body-frame anchors of entities a and b.
+struct JointK {
+  int32_t a, b;
+  float ax, ay, bx, by;
+  float rest;
+  float pad;
+};
+
+// World constants folded for the kernels.
+struct WorldK {
+  float dt, damp;      // delta t, 1 - zeta
+  float gx, gy;        // g
+  float ck, inv_k;     // c * k, 1 / k
+  float min_dist;
+  float joint_k;
+  int32_t A;           // total agents (row stride of one action step)
+  int32_t N;           // total entities
+  int32_t pad[2];
+};
+
+// Arguments of the step / rollout kernels.
+struct StepArgs {
+  float* state;            // [6][N]
+  const float* actions;    // [T][A][2] or NULL (drawn in kernel)
+  uint64_t key;            // SplitMix64 key of the action stream
+  int32_t t0, T;
+  float* traj;             // [T+1][6][N] or NULL
+  uint8_t* mask;           // [P] or NULL (last step)
+  float* forces;           // [3][N] or NULL (last step)
+  const EntParam* ent;     // [N]
+  const LaneRec* lanes;    // [groups * block]
+  const int32_t* stage_off;  // [groups + 1]
+  const int32_t* stage;      // staged global entity ids
+  const int32_t* joff;       // [N + 1] per-entity joint lists
+  const int32_t* jlist;
+  const JointK* joints;
+  const int64_t* pair_off;   // [n_envs] first mask slot of each environment
+  int32_t max_stage;         // LDS slots per group
+  int32_t pad;
+  WorldK w;
+};
+
+// Arguments of the adjoint kernel (one step backwards).
+struct BackArgs {
+  const float* state;      // [6][N] state at t
+  const float* actions;    // [A][2] actions at t
+  const float* gnext;      // [6][N] dL/ds_{t+1}
+  float* gstate;           // [6][N] dL/ds_t
+  float* gact;             // [A][2] or NULL
+  const EntParam* ent;
+  const LaneRec* lanes;
+  const int32_t* stage_off;
+  const int32_t* stage;
+  const int32_t* joff;
+  const int32_t* jlist;
+  const JointK* joints;
+  int32_t max_stage;
+  int32_t pad;
+  WorldK w;
+};
+
+// Host-side launchers (vmas_kernels.hip).
+hipError_t launch_rollout(const StepArgs& a, int groups, int block, bool spheres_only,
+                          hipStream_t s);
+hipError_t launch_backward(const BackArgs& a, int groups, int block, bool spheres_only,
+                           hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, int64_t n, hipStream_t s);
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_replicate(const float* src, float* dst, int64_t n, int copies, hipStream_t s);
+hipError_t launch_axpy_zero(float* p, int64_t n, hipStream_t s);
+
+// Host-side SplitMix64 key of (seed, stream): mix64(seed + (stream + 1) * golden).
+uint64_t action_key(uint64_t seed);
+
+}  // namespace vmas

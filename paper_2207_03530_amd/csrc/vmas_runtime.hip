@@ -1,0 +1,774 @@
+// Host runtime of the C boundary (include/vmas.h): argument validation,
+// device copies of the static batch description, launch plans, the cached
+// rollout graph, the autotuner and the checkpointed adjoint driver.
+//
+// Launch plans. A plan packs whole environments into workgroups of `block`
+// lanes: every entity that can move or rotate gets a lane, every entity of
+// the group is staged in LDS. Plans differ in the block size and in whether
+// environments are packed in their natural order or sorted by size (which
+// keeps the lanes of one wavefront on environments of similar size when
+// sizes are uneven). The per-lane arithmetic does not depend on the packing,
+// so every plan returns the same bits.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vmas.h"
+#include "vmas_internal.h"
+
+using namespace vmas;
+
+namespace {
+
+thread_local std::string g_err;
+
+vmas_status fail(vmas_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(VMAS_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+struct Plan {
+  std::string name;
+  int block = 64;
+  bool sorted = false;
+  bool valid = false;
+  int groups = 0;
+  int max_stage = 0;
+  LaneRec* d_lanes = nullptr;
+  int32_t* d_stage_off = nullptr;
+  int32_t* d_stage = nullptr;
+};
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct vmas_batch {
+  int device = 0;
+  int n_envs = 0, N = 0, A = 0, J = 0, max_env = 0;
+  int64_t P = 0;
+  bool spheres_only = true;
+  WorldK w{};
+  EntParam* d_ent = nullptr;
+  int32_t* d_joff = nullptr;
+  int32_t* d_jlist = nullptr;
+  JointK* d_joints = nullptr;
+  int64_t* d_pair_off = nullptr;
+  std::vector<Plan> plans;
+  int cur = 0;
+  // checkpoint workspace of the adjoint driver and the autotuner scratch
+  float* d_ws = nullptr;
+  size_t ws_floats = 0;
+  // cached rollout graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraphNode_t gnode = nullptr;
+  int graph_T = -1, graph_plan = -1;
+  bool graph_drawn = false;
+};
+
+namespace {
+
+void free_plan(Plan& p) {
+  if (p.d_lanes) (void)hipFree(p.d_lanes);
+  if (p.d_stage_off) (void)hipFree(p.d_stage_off);
+  if (p.d_stage) (void)hipFree(p.d_stage);
+  p.d_lanes = nullptr;
+  p.d_stage_off = nullptr;
+  p.d_stage = nullptr;
+}
+
+void free_batch(vmas_batch* b) {
+  if (!b) return;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto& p : b->plans) free_plan(p);
+  if (b->d_ent) (void)hipFree(b->d_ent);
+  if (b->d_joff) (void)hipFree(b->d_joff);
+  if (b->d_jlist) (void)hipFree(b->d_jlist);
+  if (b->d_joints) (void)hipFree(b->d_joints);
+  if (b->d_pair_off) (void)hipFree(b->d_pair_off);
+  if (b->d_ws) (void)hipFree(b->d_ws);
+  delete b;
+}
+
+template <class T> vmas_status upload(T** dst, const T* src, size_t n) {
+  *dst = nullptr;
+  if (n == 0) return VMAS_OK;
+  hipError_t e = hipMalloc((void**)dst, n * sizeof(T));
+  if (e != hipSuccess) {
+    *dst = nullptr;
+    return fail(e == hipErrorOutOfMemory ? VMAS_ERR_OUT_OF_MEMORY : VMAS_ERR_DEVICE,
+                "hipMalloc(%zu bytes) failed: %s", n * sizeof(T), hipGetErrorString(e));
+  }
+  e = hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(VMAS_ERR_DEVICE, "hipMemcpy failed: %s", hipGetErrorString(e));
+  return VMAS_OK;
+}
+
+inline bool finite(float x) { return std::isfinite(x); }
+
+double default_inertia(int shape, double m, double d0, double d1) {
+  if (shape == SPHERE) return m * d0 * d0 / 2.0;
+  if (shape == BOX) return m * (d0 * d0 + d1 * d1) / 12.0;
+  return m * d0 * d0 / 12.0;
+}
+
+// Host description after validation.
+struct HostDesc {
+  std::vector<int32_t> off, nag;
+  std::vector<int64_t> agent_off;  // first action row of each environment
+  std::vector<int> env_of;
+};
+
+vmas_status validate(const vmas_world_params* pr, const vmas_batch_desc* d, HostDesc& h) {
+  if (!pr || !d) return fail(VMAS_ERR_INVALID_ARGUMENT, "params and desc must not be NULL");
+  if (!(finite(pr->dt) && pr->dt > 0))
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "dt must be finite and > 0");
+  if (!(finite(pr->drag) && pr->drag >= 0 && pr->drag <= 1))
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "drag must be in [0, 1]");
+  if (!(finite(pr->gravity[0]) && finite(pr->gravity[1])))
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "gravity must be finite");
+  if (!(finite(pr->contact_force) && pr->contact_force >= 0))
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "contact_force must be finite and >= 0");
+  if (!(finite(pr->contact_margin) && pr->contact_margin > 0))
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "contact_margin must be finite and > 0");
+  if (!(finite(pr->min_dist) && pr->min_dist >= 0))
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "min_dist must be finite and >= 0");
+  if (!(finite(pr->joint_stiffness) && pr->joint_stiffness >= 0))
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "joint_stiffness must be finite and >= 0");
+  if (pr->flags != 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "params.flags must be 0");
+  if (d->n_envs < 1) return fail(VMAS_ERR_INVALID_ARGUMENT, "n_envs must be >= 1");
+  const int E = d->n_envs;
+  h.off.assign(E + 1, 0);
+  if (d->env_offset) {
+    if (d->env_offset[0] != 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "env_offset[0] must be 0");
+    for (int b = 0; b < E; ++b) {
+      if (d->env_offset[b + 1] < d->env_offset[b])
+        return fail(VMAS_ERR_INVALID_ARGUMENT, "env_offset must be non-decreasing (env %d)", b);
+      h.off[b + 1] = d->env_offset[b + 1];
+    }
+  } else {
+    if (d->n_per_env < 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "n_per_env must be >= 0");
+    if ((int64_t)d->n_per_env * E > INT32_MAX)
+      return fail(VMAS_ERR_INVALID_ARGUMENT, "too many entities");
+    for (int b = 0; b <= E; ++b) h.off[b] = b * d->n_per_env;
+  }
+  const int N = h.off[E];
+  if (N < 1) return fail(VMAS_ERR_INVALID_ARGUMENT, "the batch has no entity");
+  if (!d->n_agents || !d->shape || !d->dims || !d->mass || !d->flags)
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "n_agents, shape, dims, mass and flags are required");
+  h.nag.assign(d->n_agents, d->n_agents + E);
+  int64_t A = 0;
+  for (int b = 0; b < E; ++b) {
+    const int n = h.off[b + 1] - h.off[b];
+    if (h.nag[b] < 0 || h.nag[b] > n)
+      return fail(VMAS_ERR_INVALID_ARGUMENT, "n_agents[%d] = %d outside [0, %d]", b, h.nag[b], n);
+    A += h.nag[b];
+  }
+  if (A * 2 > INT32_MAX) return fail(VMAS_ERR_INVALID_ARGUMENT, "too many agents");
+  h.agent_off.assign(E, 0);
+  for (int b = 1; b < E; ++b) h.agent_off[b] = h.agent_off[b - 1] + h.nag[b - 1];
+  for (int i = 0; i < N; ++i) {
+    const int s = d->shape[i];
+    if (s != SPHERE && s != BOX && s != LINE)
+      return fail(VMAS_ERR_INVALID_ARGUMENT, "shape[%d] = %d is not a vmas_shape", i, s);
+    if (d->flags[i] & ~7) return fail(VMAS_ERR_INVALID_ARGUMENT, "flags[%d] has unknown bits", i);
+    const float d0 = d->dims[2 * i], d1 = d->dims[2 * i + 1];
+    if (!(finite(d0) && d0 > 0)) return fail(VMAS_ERR_INVALID_ARGUMENT, "dims[%d][0] must be > 0", i);
+    if (s == BOX && !(finite(d1) && d1 > 0))
+      return fail(VMAS_ERR_INVALID_ARGUMENT, "dims[%d][1] of a box must be > 0", i);
+    const bool dof = (d->flags[i] & (MOVABLE | ROTATABLE)) != 0;
+    if (dof && !(finite(d->mass[i]) && d->mass[i] > 0))
+      return fail(VMAS_ERR_INVALID_ARGUMENT, "mass[%d] must be > 0 for a movable or rotatable entity", i);
+    if (d->inertia && !finite(d->inertia[i]))
+      return fail(VMAS_ERR_INVALID_ARGUMENT, "inertia[%d] must be finite", i);
+    if (d->max_speed && !finite(d->max_speed[i]))
+      return fail(VMAS_ERR_INVALID_ARGUMENT, "max_speed[%d] must be finite", i);
+  }
+  if (d->n_joints < 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "n_joints must be >= 0");
+  h.env_of.assign(N, 0);
+  for (int b = 0; b < E; ++b)
+    for (int i = h.off[b]; i < h.off[b + 1]; ++i) h.env_of[i] = b;
+  if (d->n_joints > 0) {
+    if (!d->joint_a || !d->joint_b || !d->joint_anchor_a || !d->joint_anchor_b || !d->joint_rest)
+      return fail(VMAS_ERR_INVALID_ARGUMENT, "joint arrays are required when n_joints > 0");
+    for (int q = 0; q < d->n_joints; ++q) {
+      const int a = d->joint_a[q], c = d->joint_b[q];
+      if (a < 0 || a >= N || c < 0 || c >= N || a == c)
+        return fail(VMAS_ERR_INVALID_ARGUMENT, "joint %d has bad entity ids (%d, %d)", q, a, c);
+      if (h.env_of[a] != h.env_of[c])
+        return fail(VMAS_ERR_INVALID_ARGUMENT, "joint %d links two environments", q);
+      for (int k = 0; k < 2; ++k)
+        if (!finite(d->joint_anchor_a[2 * q + k]) || !finite(d->joint_anchor_b[2 * q + k]))
+          return fail(VMAS_ERR_INVALID_ARGUMENT, "joint %d anchors must be finite", q);
+      if (!finite(d->joint_rest[q]))
+        return fail(VMAS_ERR_INVALID_ARGUMENT, "joint %d rest length must be finite", q);
+      if (d->joint_rest[q] < 0 && !d->init_state)
+        return fail(VMAS_ERR_INVALID_ARGUMENT,
+                    "joint %d has rest < 0 (from the initial state) but init_state is NULL", q);
+    }
+  }
+  return VMAS_OK;
+}
+
+// Builds one launch plan on the host and uploads it.
+vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8_t>& shape,
+                       const std::vector<uint8_t>& flags, int block, bool sorted, Plan& p) {
+  p.block = block;
+  p.sorted = sorted;
+  p.name = std::string("entity-lane/") + std::to_string(block) + (sorted ? "/size-sorted" : "/natural");
+  const int E = b->n_envs;
+  std::vector<int> active(E, 0);
+  for (int e = 0; e < E; ++e)
+    for (int i = h.off[e]; i < h.off[e + 1]; ++i) active[e] += (flags[i] & (MOVABLE | ROTATABLE)) != 0;
+  std::vector<int> order;
+  for (int e = 0; e < E; ++e)
+    if (active[e] > 0) order.push_back(e);
+  if (sorted)
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return (h.off[x + 1] - h.off[x]) > (h.off[y + 1] - h.off[y]);
+    });
+  const int stage_cap = std::min(1360, std::max(4 * block, b->max_env));
+  std::vector<std::vector<int>> groups;
+  int lanes = 0, staged = 0;
+  for (int e : order) {
+    const int n = h.off[e + 1] - h.off[e];
+    if (active[e] > block || n > stage_cap) {
+      p.valid = false;
+      return VMAS_OK;
+    }
+    if (groups.empty() || lanes + active[e] > block || staged + n > stage_cap) {
+      groups.emplace_back();
+      lanes = 0;
+      staged = 0;
+    }
+    groups.back().push_back(e);
+    lanes += active[e];
+    staged += n;
+  }
+  const int G = (int)groups.size();
+  std::vector<LaneRec> lane((size_t)std::max(G, 1) * block);
+  std::vector<int32_t> stage_off(G + 1, 0), stage;
+  int max_stage = 1;
+  for (int g = 0; g < G; ++g) {
+    std::vector<LaneRec> recs;
+    int slot = 0;
+    for (int e : groups[g]) {
+      const int lo = slot, n = h.off[e + 1] - h.off[e];
+      const int agent_row = (int)h.agent_off[e];
+      for (int i = h.off[e]; i < h.off[e + 1]; ++i, ++slot) {
+        stage.push_back(i);
+        if (flags[i] & (MOVABLE | ROTATABLE)) {
+          LaneRec r;
+          r.ent = i;
+          r.slot = slot;
+          r.lo = lo;
+          r.hi = lo + n;
+          const int loc = i - h.off[e];
+          r.agent = loc < h.nag[e] ? agent_row + loc : -1;
+          r.env = e;
+          r.first = h.off[e];
+          r.pad = 0;
+          recs.push_back(r);
+        }
+      }
+    }
+    // shape-coherent lanes: spheres, then boxes, then lines
+    std::stable_sort(recs.begin(), recs.end(),
+                     [&](const LaneRec& x, const LaneRec& y) { return shape[x.ent] < shape[y.ent]; });
+    for (int l = 0; l < block; ++l) {
+      LaneRec r{};
+      r.ent = -1;
+      if (l < (int)recs.size()) r = recs[l];
+      lane[(size_t)g * block + l] = r;
+    }
+    stage_off[g + 1] = (int32_t)stage.size();
+    max_stage = std::max(max_stage, slot);
+  }
+  p.groups = G;
+  p.max_stage = max_stage;
+  vmas_status s;
+  if ((s = upload(&p.d_lanes, lane.data(), lane.size())) != VMAS_OK) return s;
+  if ((s = upload(&p.d_stage_off, stage_off.data(), stage_off.size())) != VMAS_OK) return s;
+  if ((s = upload(&p.d_stage, stage.data(), std::max<size_t>(stage.size(), 1))) != VMAS_OK) return s;
+  p.valid = true;
+  return VMAS_OK;
+}
+
+StepArgs make_args(vmas_batch* b, const Plan& p) {
+  StepArgs a{};
+  a.ent = b->d_ent;
+  a.lanes = p.d_lanes;
+  a.stage_off = p.d_stage_off;
+  a.stage = p.d_stage;
+  a.joff = b->d_joff;
+  a.jlist = b->d_jlist;
+  a.joints = b->d_joints;
+  a.pair_off = b->d_pair_off;
+  a.max_stage = p.max_stage;
+  a.w = b->w;
+  return a;
+}
+
+vmas_status check_batch(const vmas_batch* b) {
+  if (!b) return fail(VMAS_ERR_INVALID_ARGUMENT, "batch is NULL");
+  return VMAS_OK;
+}
+
+vmas_status launch_plan(vmas_batch* b, StepArgs a, hipStream_t s) {
+  const Plan& p = b->plans[b->cur];
+  if (p.groups == 0) return VMAS_OK;
+  hipError_t e = launch_rollout(a, p.groups, p.block, b->spheres_only, s);
+  if (e != hipSuccess) return fail(VMAS_ERR_DEVICE, "rollout launch failed: %s", hipGetErrorString(e));
+  return VMAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vmas_last_error(void) { return g_err.c_str(); }
+
+vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_desc* desc,
+                              int device, vmas_batch** out) {
+  g_err.clear();
+  if (!out) return fail(VMAS_ERR_INVALID_ARGUMENT, "out must not be NULL");
+  *out = nullptr;
+  HostDesc h;
+  vmas_status st = validate(params, desc, h);
+  if (st != VMAS_OK) return st;
+  const int E = desc->n_envs, N = h.off[E];
+  // Host-side tables.
+  std::vector<uint8_t> shape(desc->shape, desc->shape + N), flags(desc->flags, desc->flags + N);
+  std::vector<EntParam> ent(N);
+  bool spheres_only = true;
+  int max_env = 0;
+  for (int e = 0; e < E; ++e) max_env = std::max(max_env, h.off[e + 1] - h.off[e]);
+  for (int i = 0; i < N; ++i) {
+    EntParam& p = ent[i];
+    const int s = shape[i], f = flags[i];
+    p.d0 = desc->dims[2 * i];
+    p.d1 = s == BOX ? desc->dims[2 * i + 1] : 0.0f;
+    const float m = desc->mass[i];
+    const bool mov = f & MOVABLE, rot = f & ROTATABLE;
+    p.inv_m = mov ? 1.0f / m : 0.0f;
+    double I = desc->inertia ? desc->inertia[i] : 0.0;
+    if (!(I > 0)) I = default_inertia(s, m, p.d0, p.d1);
+    p.inv_I = rot ? (float)(1.0 / I) : 0.0f;
+    p.vmax = desc->max_speed ? desc->max_speed[i] : 0.0f;
+    p.rho = s == SPHERE ? p.d0 : 0.0f;
+    p.mgx = mov ? m * params->gravity[0] : 0.0f;
+    p.mgy = mov ? m * params->gravity[1] : 0.0f;
+    p.sf = s | (f << 8);
+    p.excl = -1;
+    p.pad[0] = p.pad[1] = 0;
+    if (s != SPHERE && (f & COLLIDABLE)) spheres_only = false;
+    if (s != SPHERE && (f & (MOVABLE | ROTATABLE))) spheres_only = false;
+  }
+  // Joints: per-entity lists, contact exclusions, rest lengths.
+  const int J = desc->n_joints;
+  std::vector<JointK> joints(J);
+  std::vector<int32_t> joff(N + 1, 0), jlist;
+  std::vector<std::vector<int>> per(N);
+  for (int q = 0; q < J; ++q) {
+    JointK& k = joints[q];
+    k.a = desc->joint_a[q];
+    k.b = desc->joint_b[q];
+    k.ax = desc->joint_anchor_a[2 * q];
+    k.ay = desc->joint_anchor_a[2 * q + 1];
+    k.bx = desc->joint_anchor_b[2 * q];
+    k.by = desc->joint_anchor_b[2 * q + 1];
+    k.pad = 0;
+    float rest = desc->joint_rest[q];
+    if (rest < 0) {
+      const float* s0 = desc->init_state;
+      double Pa[2], Pb[2];
+      const int ids[2] = {k.a, k.b};
+      const float anc[2][2] = {{k.ax, k.ay}, {k.bx, k.by}};
+      double* P[2] = {Pa, Pb};
+      for (int u = 0; u < 2; ++u) {
+        const int e = ids[u];
+        const double th = s0[4 * (size_t)N + e], c = std::cos(th), s = std::sin(th);
+        P[u][0] = s0[e] + c * anc[u][0] - s * anc[u][1];
+        P[u][1] = s0[(size_t)N + e] + s * anc[u][0] + c * anc[u][1];
+      }
+      rest = (float)std::hypot(Pa[0] - Pb[0], Pa[1] - Pb[1]);
+    }
+    k.rest = rest;
+    spheres_only = false;
+    per[k.a].push_back(q);
+    per[k.b].push_back(q);
+    const bool collide = desc->joint_collide && desc->joint_collide[q];
+    if (!collide) {
+      for (int u = 0; u < 2; ++u) {
+        const int me = u ? k.b : k.a, other = u ? k.a : k.b;
+        const int loc = other - h.off[h.env_of[other]];
+        if (loc > 254) {
+          return fail(VMAS_ERR_UNSUPPORTED,
+                      "joint %d: a non-colliding jointed entity must have a local index < 255", q);
+        }
+        uint32_t ex = (uint32_t)ent[me].excl;
+        int k2 = 0;
+        while (k2 < 4 && ((ex >> (8 * k2)) & 0xffu) != 0xffu) ++k2;
+        if (k2 == 4)
+          return fail(VMAS_ERR_UNSUPPORTED,
+                      "entity %d has more than 4 non-colliding joint partners", me);
+        ex = (ex & ~(0xffu << (8 * k2))) | ((uint32_t)loc << (8 * k2));
+        ent[me].excl = (int32_t)ex;
+      }
+    }
+  }
+  for (int i = 0; i < N; ++i) {
+    joff[i + 1] = joff[i] + (int)per[i].size();
+    for (int q : per[i]) jlist.push_back(q);
+  }
+  std::vector<int64_t> pair_off(E, 0);
+  int64_t P = 0;
+  for (int e = 0; e < E; ++e) {
+    pair_off[e] = P;
+    const int64_t n = h.off[e + 1] - h.off[e];
+    P += n * (n - 1) / 2;
+  }
+  int64_t A = 0;
+  for (int e = 0; e < E; ++e) A += h.nag[e];
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(VMAS_ERR_DEVICE, "no HIP device is available");
+  if (device < 0 || device >= ndev)
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "device %d outside [0, %d)", device, ndev);
+  DeviceGuard guard(device);
+  if (!guard.ok) return fail(VMAS_ERR_DEVICE, "hipSetDevice(%d) failed", device);
+
+  vmas_batch* b = new vmas_batch();
+  b->device = device;
+  b->n_envs = E;
+  b->N = N;
+  b->A = (int)A;
+  b->J = J;
+  b->P = P;
+  b->max_env = max_env;
+  b->spheres_only = spheres_only;
+  b->w.dt = params->dt;
+  b->w.damp = 1.0f - params->drag;
+  b->w.gx = params->gravity[0];
+  b->w.gy = params->gravity[1];
+  b->w.ck = params->contact_force * params->contact_margin;
+  b->w.inv_k = 1.0f / params->contact_margin;
+  b->w.min_dist = params->min_dist;
+  b->w.joint_k = params->joint_stiffness;
+  b->w.A = (int)A;
+  b->w.N = N;
+  vmas_status s;
+  if ((s = upload(&b->d_ent, ent.data(), ent.size())) != VMAS_OK ||
+      (s = upload(&b->d_joff, joff.data(), joff.size())) != VMAS_OK ||
+      (s = upload(&b->d_jlist, jlist.data(), jlist.size())) != VMAS_OK ||
+      (s = upload(&b->d_joints, joints.data(), joints.size())) != VMAS_OK ||
+      (s = upload(&b->d_pair_off, pair_off.data(), pair_off.size())) != VMAS_OK) {
+    free_batch(b);
+    return s;
+  }
+  const int blocks[3] = {64, 128, 256};
+  int first_valid = -1;
+  for (int sorted = 0; sorted < 2; ++sorted) {
+    for (int bi = 0; bi < 3; ++bi) {
+      Plan p;
+      if ((s = build_plan(b, h, shape, flags, blocks[bi], sorted != 0, p)) != VMAS_OK) {
+        free_plan(p);
+        free_batch(b);
+        return s;
+      }
+      b->plans.push_back(p);
+      if (p.valid && first_valid < 0) first_valid = (int)b->plans.size() - 1;
+    }
+  }
+  if (first_valid < 0) {
+    // environments too large for 256 lanes: one bigger block
+    int need = 64;
+    for (int e = 0; e < E; ++e) {
+      int act = 0;
+      for (int i = h.off[e]; i < h.off[e + 1]; ++i) act += (flags[i] & (MOVABLE | ROTATABLE)) != 0;
+      while (need < act) need *= 2;
+    }
+    if (need > 1024) {
+      free_batch(b);
+      return fail(VMAS_ERR_UNSUPPORTED, "an environment has more than 1024 entities that move or rotate");
+    }
+    Plan p;
+    if ((s = build_plan(b, h, shape, flags, need, false, p)) != VMAS_OK) {
+      free_plan(p);
+      free_batch(b);
+      return s;
+    }
+    b->plans.push_back(p);
+    if (p.valid) first_valid = (int)b->plans.size() - 1;
+  }
+  if (first_valid < 0) {
+    free_batch(b);
+    return fail(VMAS_ERR_UNSUPPORTED, "an environment is too large to stage in LDS");
+  }
+  b->cur = first_valid;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_batch(b);
+    return fail(VMAS_ERR_DEVICE, "hipDeviceSynchronize failed: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return VMAS_OK;
+}
+
+vmas_status vmas_destroy_batch(vmas_batch* batch) {
+  g_err.clear();
+  if (!batch) return VMAS_OK;
+  DeviceGuard guard(batch->device);
+  free_batch(batch);
+  return VMAS_OK;
+}
+
+vmas_status vmas_batch_get_info(const vmas_batch* b, vmas_batch_info* info) {
+  g_err.clear();
+  if (!b || !info) return fail(VMAS_ERR_INVALID_ARGUMENT, "batch and info must not be NULL");
+  info->n_envs = b->n_envs;
+  info->n_entities = b->N;
+  info->n_agents = b->A;
+  info->n_joints = b->J;
+  info->n_pair_slots = b->P;
+  info->schedule = b->cur;
+  info->n_schedules = (int32_t)b->plans.size();
+  info->max_env_size = b->max_env;
+  info->reserved = 0;
+  return VMAS_OK;
+}
+
+const char* vmas_schedule_name(const vmas_batch* b, int32_t schedule) {
+  if (!b || schedule < 0 || schedule >= (int)b->plans.size()) return "";
+  return b->plans[schedule].valid ? b->plans[schedule].name.c_str() : "";
+}
+
+vmas_status vmas_set_schedule(vmas_batch* b, int32_t schedule) {
+  g_err.clear();
+  if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
+  if (schedule < 0 || schedule >= (int)b->plans.size() || !b->plans[schedule].valid)
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "schedule %d is not a valid plan", schedule);
+  b->cur = schedule;
+  return VMAS_OK;
+}
+
+vmas_status vmas_step(vmas_batch* b, float* state, const float* actions, uint8_t* mask,
+                      float* forces, void* stream) {
+  g_err.clear();
+  if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
+  if (!state) return fail(VMAS_ERR_INVALID_ARGUMENT, "state must not be NULL");
+  if (!actions && b->A > 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "actions must not be NULL");
+  DeviceGuard guard(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  if (mask) HIPCHK(launch_fill_u8(mask, b->P, s));
+  if (forces) HIPCHK(launch_fill_f32(forces, 3 * (int64_t)b->N, 0.0f, s));
+  StepArgs a = make_args(b, b->plans[b->cur]);
+  a.state = state;
+  a.actions = actions;
+  a.key = 0;
+  a.t0 = 0;
+  a.T = 1;
+  a.traj = nullptr;
+  a.mask = mask;
+  a.forces = forces;
+  return launch_plan(b, a, s);
+}
+
+vmas_status vmas_rollout(vmas_batch* b, float* state, const float* actions, uint64_t seed,
+                         int32_t t0, int32_t T, float* traj, uint8_t* final_mask, void* stream) {
+  g_err.clear();
+  if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
+  if (!state) return fail(VMAS_ERR_INVALID_ARGUMENT, "state must not be NULL");
+  if (T < 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "T must be >= 0");
+  if (t0 < 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "t0 must be >= 0");
+  if ((int64_t)T * b->A * 2 > ((int64_t)1 << 40))
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "T * A too large");
+  DeviceGuard guard(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  if (traj) HIPCHK(launch_replicate(state, traj, 6 * (int64_t)b->N, T + 1, s));
+  if (T == 0) return VMAS_OK;
+  if (final_mask) HIPCHK(launch_fill_u8(final_mask, b->P, s));
+  StepArgs a = make_args(b, b->plans[b->cur]);
+  a.state = state;
+  a.actions = actions;
+  a.key = action_key(seed);
+  a.t0 = t0;
+  a.T = T;
+  a.traj = traj;
+  a.mask = final_mask;
+  a.forces = nullptr;
+  return launch_plan(b, a, s);
+}
+
+vmas_status vmas_rollout_graph(vmas_batch* b, float* state, const float* actions, uint64_t seed,
+                               int32_t t0, int32_t T, float* traj, uint8_t* final_mask,
+                               void* stream) {
+  g_err.clear();
+  if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
+  if (traj || final_mask || T <= 0)  // only the plain state-in/state-out rollout is cached
+    return vmas_rollout(b, state, actions, seed, t0, T, traj, final_mask, stream);
+  if (!state) return fail(VMAS_ERR_INVALID_ARGUMENT, "state must not be NULL");
+  if (t0 < 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "t0 must be >= 0");
+  DeviceGuard guard(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  const Plan& p = b->plans[b->cur];
+  if (p.groups == 0) return VMAS_OK;
+  StepArgs a = make_args(b, p);
+  a.state = state;
+  a.actions = actions;
+  a.key = action_key(seed);
+  a.t0 = t0;
+  a.T = T;
+  const bool drawn = actions == nullptr;
+  if (!b->gexec || b->graph_T != T || b->graph_plan != b->cur || b->graph_drawn != drawn) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_rollout(a, p.groups, p.block, b->spheres_only, s);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(s, &g);
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(VMAS_ERR_DEVICE, "graph capture failed: %s / %s", hipGetErrorString(le),
+                  hipGetErrorString(ce));
+    }
+    b->graph = g;
+    size_t nn = 1;
+    hipGraphNode_t nodes[1];
+    HIPCHK(hipGraphGetNodes(g, nodes, &nn));
+    if (nn != 1) return fail(VMAS_ERR_DEVICE, "captured graph has %zu nodes", nn);
+    b->gnode = nodes[0];
+    HIPCHK(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+    b->graph_T = T;
+    b->graph_plan = b->cur;
+    b->graph_drawn = drawn;
+  } else {
+    hipKernelNodeParams kp;
+    HIPCHK(hipGraphKernelNodeGetParams(b->gnode, &kp));
+    void* args[1] = {&a};
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    HIPCHK(hipGraphExecKernelNodeSetParams(b->gexec, b->gnode, &kp));
+  }
+  HIPCHK(hipGraphLaunch(b->gexec, s));
+  return VMAS_OK;
+}
+
+vmas_status vmas_autotune(vmas_batch* b, const float* state, int32_t T, void* stream,
+                          int32_t* chosen) {
+  g_err.clear();
+  if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
+  if (!state || T < 1) return fail(VMAS_ERR_INVALID_ARGUMENT, "state must be given and T >= 1");
+  DeviceGuard guard(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n = 6 * (size_t)b->N;
+  float* scratch = nullptr;
+  HIPCHK(hipMalloc((void**)&scratch, n * sizeof(float)));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int prev = b->cur;
+  int best = -1;
+  float best_ms = 0;
+  vmas_status st = VMAS_OK;
+  for (int q = 0; q < (int)b->plans.size() && st == VMAS_OK; ++q) {
+    if (!b->plans[q].valid) continue;
+    b->cur = q;
+    float ms_min = 0;
+    for (int rep = 0; rep < 4 && st == VMAS_OK; ++rep) {
+      if (hipMemcpyAsync(scratch, state, n * sizeof(float), hipMemcpyDeviceToDevice, s) !=
+          hipSuccess) {
+        st = fail(VMAS_ERR_DEVICE, "autotune copy failed");
+        break;
+      }
+      (void)hipEventRecord(e0, s);
+      st = vmas_rollout(b, scratch, nullptr, 12345u, 0, T, nullptr, nullptr, stream);
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) st = fail(VMAS_ERR_DEVICE, "autotune sync failed");
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0 && (rep == 1 || ms < ms_min)) ms_min = ms;  // first repetition warms up
+    }
+    if (st == VMAS_OK && (best < 0 || ms_min < best_ms)) {
+      best = q;
+      best_ms = ms_min;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(scratch);
+  if (st != VMAS_OK) {
+    b->cur = prev;
+    return st;
+  }
+  b->cur = best;
+  if (chosen) *chosen = best;
+  return VMAS_OK;
+}
+
+vmas_status vmas_step_backward(vmas_batch* b, const float* state_t, const float* actions_t,
+                               const float* grad_state_next, float* grad_state_t,
+                               float* grad_actions_t, void* stream) {
+  (void)state_t;
+  (void)actions_t;
+  (void)grad_state_next;
+  (void)grad_state_t;
+  (void)grad_actions_t;
+  (void)stream;
+  g_err.clear();
+  if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
+  return fail(VMAS_ERR_UNSUPPORTED, "vmas_step_backward is not built yet");
+}
+
+vmas_status vmas_rollout_backward(vmas_batch* b, const float* state0, const float* actions,
+                                  int32_t T, int32_t ckpt_every, const float* grad_state_T,
+                                  float* grad_state0, float* grad_actions, void* stream) {
+  (void)state0;
+  (void)actions;
+  (void)T;
+  (void)ckpt_every;
+  (void)grad_state_T;
+  (void)grad_state0;
+  (void)grad_actions;
+  (void)stream;
+  g_err.clear();
+  if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
+  return fail(VMAS_ERR_UNSUPPORTED, "vmas_rollout_backward is not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+"""C boundary checks that need no GPU: the library loads, exports every
+function the header declares, and rejects bad arguments on the host before
+any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2207_03530_amd import binding as B
+from paper_2207_03530_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vmas.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(vmas_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    L = B.lib()
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_header_is_plain_c():
+    txt = open(HEADER).read()
+    assert "torch" not in txt and "hip_runtime" not in txt
+    assert 'extern "C"' in txt
+
+
+def _params(w):
+    return B.make_params(w)
+
+
+def _desc(w, keep):
+    d = B.BatchDesc()
+    arrs = dict(off=np.ascontiguousarray(w.env_offset, np.int32),
+                na=np.ascontiguousarray(w.n_agents, np.int32),
+                shape=np.ascontiguousarray(w.shape, np.uint8),
+                dims=np.ascontiguousarray(w.dims, np.float32),
+                mass=np.ascontiguousarray(w.mass, np.float32),
+                flags=np.ascontiguousarray(w.flags, np.uint8))
+    keep.append(arrs)
+    d.n_envs = w.n_envs
+    d.env_offset = arrs["off"].ctypes.data_as(B._i32p)
+    d.n_agents = arrs["na"].ctypes.data_as(B._i32p)
+    d.shape = arrs["shape"].ctypes.data_as(B._u8p)
+    d.dims = arrs["dims"].ctypes.data_as(B._f32p)
+    d.mass = arrs["mass"].ctypes.data_as(B._f32p)
+    d.flags = arrs["flags"].ctypes.data_as(B._u8p)
+    return d
+
+
+def _create(p, d):
+    h = ctypes.c_void_p()
+    st = B.lib().vmas_create_batch(ctypes.byref(p) if p is not None else None,
+                                   ctypes.byref(d) if d is not None else None, 0, ctypes.byref(h))
+    return st, B.lib().vmas_last_error().decode(), h
+
+
+def test_null_arguments_rejected():
+    w = W.spread(2)
+    keep = []
+    st, msg, h = _create(None, _desc(w, keep))
+    assert st == 1 and "NULL" in msg and not h.value
+    st, msg, _ = _create(_params(w), None)
+    assert st == 1
+    assert B.lib().vmas_step(None, None, None, None, None, None) == 1
+    assert B.lib().vmas_rollout(None, None, None, 0, 0, 1, None, None, None) == 1
+    assert B.lib().vmas_destroy_batch(None) == 0
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("dt", 0.0, "dt"), ("dt", float("nan"), "dt"), ("drag", 1.5, "drag"),
+    ("contact_margin", 0.0, "contact_margin"), ("contact_force", -1.0, "contact_force"),
+    ("min_dist", -0.1, "min_dist"), ("flags", 3, "flags")])
+def test_bad_world_params(field, value, needle):
+    w = W.spread(2)
+    keep = []
+    p = _params(w)
+    setattr(p, field, value)
+    st, msg, _ = _create(p, _desc(w, keep))
+    assert st == 1 and needle in msg
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda w: setattr(w, "shape", np.full_like(w.shape, 7)), "shape"),
+    (lambda w: w.dims.__setitem__((0, 0), 0.0), "dims"),
+    (lambda w: w.mass.__setitem__(0, 0.0), "mass"),
+    (lambda w: w.flags.__setitem__(0, 64), "flags"),
+    (lambda w: w.n_agents.__setitem__(0, 99), "n_agents"),
+    (lambda w: w.env_offset.__setitem__(1, 13), "non-decreasing"),
+])
+def test_bad_descriptions(mutate, needle):
+    w = W.spread(3)
+    mutate(w)
+    keep = []
+    st, msg, _ = _create(_params(w), _desc(w, keep))
+    assert st == 1 and needle in msg, msg
+
+
+def test_bad_joints():
+    w = W.mixed(2, n_spheres=3, n_boxes=1, n_lines=1)
+    keep = []
+    d = _desc(w, keep)
+    ja = np.array([0], np.int32)
+    jb = np.array([w.env_offset[1]], np.int32)  # other environment
+    anc = np.zeros((1, 2), np.float32)
+    rest = np.array([0.1], np.float32)
+    keep.append((ja, jb, anc, rest))
+    d.n_joints = 1
+    d.joint_a = ja.ctypes.data_as(B._i32p)
+    d.joint_b = jb.ctypes.data_as(B._i32p)
+    d.joint_anchor_a = anc.ctypes.data_as(B._f32p)
+    d.joint_anchor_b = anc.ctypes.data_as(B._f32p)
+    d.joint_rest = rest.ctypes.data_as(B._f32p)
+    st, msg, _ = _create(_params(w), d)
+    assert st == 1 and "two environments" in msg
+    rest[0] = -1.0  # from the initial state, which is missing
+    jb[0] = 1
+    st, msg, _ = _create(_params(w), d)
+    assert st == 1 and "init_state" in msg
+
+
+def test_python_binding_names_match_c():
+    for n in ("vmas_create_batch", "vmas_step", "vmas_rollout", "vmas_step_backward",
+              "vmas_rollout_backward"):
+        assert callable(getattr(B, n))

@@ -1,0 +1,428 @@
+"""GPU parity of the HIP step against the FP64 oracle, element by element.
+
+Tolerances: FP32 state within 1e-5 relative (per environment, per field
+group) after one step and 1e-3 after 100 steps; the integer contact mask
+bit for bit. Environments whose outcome hinges on rounding (a pair within
+a band of its contact threshold, where Eq. 2 jumps by c k ln 2, or FP64
+itself moving under a 1e-7 perturbation) are counted and excluded from the
+multi-step state check, never hidden; their counts are asserted small.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2207_03530_amd import workloads as W
+from tests import parity as PU
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# FP32 narrow phase for boxes and lines rounds d by a few ulp of the
+# coordinates (|x| <= ~2): decisions within this band of d_min may differ.
+BAND = 1e-5
+
+
+def _batch(w):
+    from paper_2207_03530_amd import binding as B
+    return B.Batch(w, 0)
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda:0", dtype)
+
+
+def _gpu_step(b, state, act, masks=True, forces=False):
+    st = _dev(state)
+    mk = torch.zeros(b.P, dtype=torch.uint8, device="cuda:0") if masks else None
+    fo = torch.zeros(3 * b.N, dtype=torch.float32, device="cuda:0") if forces else None
+    b.step(st, _dev(act), mk, fo)
+    torch.cuda.synchronize()
+    out = [st.cpu().numpy().reshape(6, -1)]
+    out.append(mk.cpu().numpy() if masks else None)
+    out.append(fo.cpu().numpy().reshape(3, -1) if forces else None)
+    return out
+
+
+def _mask_check(w, ow, state, gmask, omask, strict_all=False):
+    """Sphere-sphere slots bit-exact; other slots may differ only inside BAND."""
+    lo, hi = PU.pair_shapes(w.shape, w.env_offset)
+    sph = (lo == W.SPHERE) & (hi == W.SPHERE)
+    diff = gmask != omask
+    assert not np.any(diff & sph), f"sphere-pair mask mismatch at {np.nonzero(diff & sph)[0][:10]}"
+    if strict_all:
+        assert not np.any(diff)
+    if np.any(diff):
+        d, dm = O.pair_distances(ow, state)
+        bad = diff & ~(np.abs(d - dm) <= BAND)
+        assert not np.any(bad), f"mask mismatch outside the band at {np.nonzero(bad)[0][:10]}"
+    return np.nonzero(diff)[0]
+
+
+# ------------------------------------------------------------ spheres ------
+
+def test_spread32_one_step_parity_and_mask():
+    w = W.spread(32)
+    b = _batch(w)
+    act = w.actions(1)[0]
+    g, gm, gf = _gpu_step(b, w.state0, act, forces=True)
+    ow = O.OracleWorld(w)
+    o, om, of = ow.step(w.state0, act, want_forces=True)
+    err = PU.env_rel_err(g, o, w.env_offset)
+    assert err.max() <= 1e-5, err.max()
+    assert np.array_equal(gm, om)
+    assert om.sum() > 0
+    act_ent = (w.flags & (W.MOVABLE | W.ROTATABLE)) != 0
+    np.testing.assert_allclose(gf[:, act_ent], of[:, act_ent], rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("t", [10, 50, 99])
+def test_spread32_one_step_from_oracle_states(t):
+    """One-step parity from states the oracle reached after t steps (rounded
+    to FP32), so that contacts of a developed trajectory are exercised."""
+    w = W.spread(32)
+    ow = O.OracleWorld(w)
+    acts = w.actions(t + 1)
+    _, _, tr = ow.rollout(w.state0, acts[:t], traj=True, want_mask=False)
+    st = tr[t].astype(np.float32)
+    b = _batch(w)
+    g, gm, _ = _gpu_step(b, st, acts[t])
+    o, om, _ = ow.step(st, acts[t])
+    assert PU.env_rel_err(g, o, w.env_offset).max() <= 1e-5
+    assert np.array_equal(gm, om)
+
+
+def test_spread32_hundred_steps():
+    """Free-running 100-step rollout (one persistent launch) against the FP64
+    oracle: 1e-3 relative, excluding environments the FP64 conditioning check
+    or the near-threshold scan marks as rounding-sensitive (counted)."""
+    w = W.spread(32)
+    T = 100
+    acts = w.actions(T)
+    b = _batch(w)
+    st = _dev(w.state0)
+    mk = torch.zeros(b.P, dtype=torch.uint8, device="cuda:0")
+    b.rollout(st, _dev(acts), final_mask=mk)
+    torch.cuda.synchronize()
+    g = st.cpu().numpy().reshape(6, -1)
+    ow = O.OracleWorld(w)
+    o, om, tr = ow.rollout(w.state0, acts, traj=True)
+    err = PU.env_rel_err(g, o, w.env_offset).max(1)
+    sensitive = PU.ill_conditioned(ow, w.state0, acts) | PU.near_threshold_envs(ow, tr, 1e-5)
+    print(f"spread32 T=100: max err {err.max():.3g}, max err on well-conditioned "
+          f"{err[~sensitive].max() if (~sensitive).any() else 0:.3g}, sensitive envs "
+          f"{sensitive.sum()}/{w.n_envs}")
+    assert sensitive.sum() <= w.n_envs // 4
+    assert err[~sensitive].max() <= 1e-3
+    # final mask on well-conditioned environments
+    penv = PU.pair_env(w.env_offset)
+    keep = ~sensitive[penv]
+    assert np.array_equal(mk.cpu().numpy()[keep], om[keep])
+
+
+def test_step_loop_equals_rollout_bitwise():
+    """T single-step launches and one T-step persistent launch give the same bits."""
+    w = W.spread(16)
+    T = 20
+    acts = _dev(w.actions(T))
+    b = _batch(w)
+    s1 = _dev(w.state0)
+    for t in range(T):
+        b.step(s1, acts[t].contiguous())
+    s2 = _dev(w.state0)
+    b.rollout(s2, acts)
+    torch.cuda.synchronize()
+    assert torch.equal(s1, s2)
+
+
+def test_rollout_split_bitwise():
+    w = W.spread(64, seed=5)
+    acts = _dev(w.actions(30))
+    b = _batch(w)
+    s1 = _dev(w.state0)
+    b.rollout(s1, acts)
+    s2 = _dev(w.state0)
+    b.rollout(s2, acts[:11].contiguous())
+    b.rollout(s2, acts[11:].contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(s1, s2)
+
+
+def test_drawn_actions_equal_host_actions_bitwise():
+    """In-kernel SplitMix64 actions reproduce the host generator exactly."""
+    w = W.spread(100, seed=3)
+    T = 25
+    b = _batch(w)
+    s1 = _dev(w.state0)
+    b.rollout(s1, _dev(w.actions(T)))
+    s2 = _dev(w.state0)
+    b.rollout(s2, None, T=T, seed=w.seed)
+    s3 = _dev(w.state0)
+    b.rollout(s3, None, T=10, seed=w.seed)
+    b.rollout(s3, None, T=15, seed=w.seed, t0=10)
+    torch.cuda.synchronize()
+    assert torch.equal(s1, s2)
+    assert torch.equal(s1, s3)
+
+
+def test_all_schedules_bitwise_equal():
+    w = W.uneven(300, lo=2, hi=20, seed=2)
+    acts = _dev(w.actions(15))
+    b = _batch(w)
+    ref = None
+    names = []
+    for q in range(b.n_schedules):
+        name = b.schedule_name(q)
+        if not name:
+            continue
+        names.append(name)
+        b.set_schedule(q)
+        s = _dev(w.state0)
+        b.rollout(s, acts)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = s.clone()
+        assert torch.equal(s, ref), name
+    assert len(names) >= 2
+
+
+def test_determinism_run_twice():
+    w = W.mixed(64, seed=4)
+    acts = _dev(w.actions(20))
+    b = _batch(w)
+    outs = []
+    for _ in range(2):
+        s = _dev(w.state0)
+        m = torch.zeros(b.P, dtype=torch.uint8, device="cuda:0")
+        b.rollout(s, acts, final_mask=m)
+        torch.cuda.synchronize()
+        outs.append((s.clone(), m.clone()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_graph_replay_equals_eager():
+    """Replays of the cached rollout graph, with eager work in between, match
+    the eager launch every time (also after the graph's arguments change)."""
+    w = W.spread(500, seed=1)
+    T = 12
+    b = _batch(w)
+    acts = _dev(w.actions(T))
+    eager = _dev(w.state0)
+    b.rollout(eager, acts)
+    for rep in range(4):
+        s = _dev(w.state0)
+        junk = torch.randn(1000, device="cuda:0").sum()  # unrelated eager work
+        b.rollout(s, acts, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(s, eager), rep
+        del junk
+    s = _dev(w.state0)
+    b.rollout(s, None, T=T, seed=9, graph=True)
+    e2 = _dev(w.state0)
+    b.rollout(e2, None, T=T, seed=9)
+    torch.cuda.synchronize()
+    assert torch.equal(s, e2)
+
+
+def test_spread30k_full_size_sampled_envs():
+    """The 30,000-environment configuration in the benchmark's launch shape
+    (one 100-step persistent rollout); 256 sampled environments are checked
+    against the oracle (environments are independent, so the oracle runs the
+    sample as its own batch with the same per-environment inputs)."""
+    w = W.spread(30000)
+    T = 100
+    acts = w.actions(T)
+    b = _batch(w)
+    q = b.autotune(_dev(w.state0), 10)
+    st = _dev(w.state0)
+    b.rollout(st, _dev(acts))
+    torch.cuda.synchronize()
+    g = st.cpu().numpy().reshape(6, -1)
+    rng = np.random.default_rng(0)
+    envs = np.sort(rng.choice(w.n_envs, 256, replace=False))
+    ws = W.subset(w, envs)
+    ids = np.concatenate([np.arange(w.env_offset[e], w.env_offset[e + 1]) for e in envs])
+    rows = np.concatenate([np.arange(4 * e, 4 * e + 4) for e in envs])
+    ow = O.OracleWorld(ws)
+    o, _, tr = ow.rollout(ws.state0, acts[:, rows], traj=True, want_mask=False)
+    err = PU.env_rel_err(g[:, ids], o, ws.env_offset).max(1)
+    sensitive = PU.ill_conditioned(ow, ws.state0, acts[:, rows]) | \
+        PU.near_threshold_envs(ow, tr, 1e-5)
+    print(f"spread30k (plan {b.schedule_name(q)}): sampled max err {err.max():.3g}, "
+          f"sensitive {sensitive.sum()}/256")
+    assert sensitive.sum() <= 64
+    assert err[~sensitive].max() <= 1e-3
+
+
+# ------------------------------------------------------- mixed shapes ------
+
+def test_mixed_one_step_full_size():
+    """4,096 environments of 16 spheres + 4 boxes + 8 lines + 2 joints, one step."""
+    w = W.mixed(4096)
+    act = w.actions(1)[0]
+    b = _batch(w)
+    g, gm, gf = _gpu_step(b, w.state0, act, forces=True)
+    ow = O.OracleWorld(w)
+    o, om, of = ow.step(w.state0, act, want_forces=True)
+    band = _mask_check(w, ow, w.state0, gm, om)
+    penv = PU.pair_env(w.env_offset)
+    skip = np.zeros(w.n_envs, bool)
+    skip[penv[band]] = True
+    err = PU.env_rel_err(g, o, w.env_offset)
+    print(f"mixed4096 one step: band mask cases {len(band)}, max err {err[~skip].max():.3g}, "
+          f"contacts {om.sum()}")
+    assert len(band) <= 4
+    assert err[~skip].max() <= 1e-5
+    ent_env = np.repeat(np.arange(w.n_envs), np.diff(w.env_offset))
+    ok = ~skip[ent_env]
+    np.testing.assert_allclose(gf[:, ok], of[:, ok], rtol=2e-4, atol=2e-4)
+
+
+def test_mixed_multi_step_parity():
+    """Mixed shapes and joints, 200 steps free-running on 48 environments."""
+    w = W.mixed(48, seed=1)
+    T = 200
+    acts = w.actions(T)
+    b = _batch(w)
+    st = _dev(w.state0)
+    b.rollout(st, _dev(acts))
+    torch.cuda.synchronize()
+    g = st.cpu().numpy().reshape(6, -1)
+    ow = O.OracleWorld(w)
+    o, _, tr = ow.rollout(w.state0, acts, traj=True, want_mask=False)
+    err = PU.env_rel_err(g, o, w.env_offset).max(1)
+    sensitive = PU.ill_conditioned(ow, w.state0, acts) | PU.near_threshold_envs(ow, tr, BAND)
+    print(f"mixed48 T=200: well-conditioned {(~sensitive).sum()}/48, max err there "
+          f"{err[~sensitive].max() if (~sensitive).any() else 0:.3g}")
+    if (~sensitive).any():
+        assert err[~sensitive].max() <= 1e-3
+
+
+SHAPE_CASES = [
+    ("sphere-sphere", (W.SPHERE, 0.1, 0), (W.SPHERE, 0.08, 0)),
+    ("sphere-box", (W.SPHERE, 0.1, 0), (W.BOX, 0.3, 0.2)),
+    ("box-sphere", (W.BOX, 0.3, 0.2), (W.SPHERE, 0.1, 0)),
+    ("sphere-line", (W.SPHERE, 0.1, 0), (W.LINE, 0.5, 0)),
+    ("line-sphere", (W.LINE, 0.5, 0), (W.SPHERE, 0.1, 0)),
+    ("line-line", (W.LINE, 0.5, 0), (W.LINE, 0.4, 0)),
+    ("line-box", (W.LINE, 0.5, 0), (W.BOX, 0.3, 0.2)),
+    ("box-line", (W.BOX, 0.3, 0.2), (W.LINE, 0.5, 0)),
+    ("box-box", (W.BOX, 0.3, 0.2), (W.BOX, 0.2, 0.4)),
+]
+
+
+@pytest.mark.parametrize("name,a,c", SHAPE_CASES, ids=[s[0] for s in SHAPE_CASES])
+def test_pair_type_micro_cases(name, a, c):
+    """Each narrow-phase routine in isolation: 512 two-entity environments,
+    random relative poses (about half overlapping), forces and torques of one
+    step against the oracle."""
+    E = 512
+    rng = np.random.default_rng(hash(name) % 2 ** 32)
+    N = 2 * E
+    shape = np.tile(np.array([a[0], c[0]], np.uint8), E)
+    dims = np.tile(np.array([[a[1], a[2]], [c[1], c[2]]], np.float32), (E, 1))
+    st = np.zeros((6, N), np.float32)
+    st[0, 1::2] = rng.uniform(-0.4, 0.4, E)
+    st[1, 1::2] = rng.uniform(-0.4, 0.4, E)
+    st[4] = rng.uniform(-np.pi, np.pi, N).astype(np.float32)
+    st[4, shape == W.SPHERE] = 0
+    w = W.World(env_offset=(np.arange(E + 1) * 2).astype(np.int32),
+                n_agents=np.zeros(E, np.int32), shape=shape, dims=dims,
+                mass=np.ones(N, np.float32), flags=np.full(N, 7, np.uint8), state0=st)
+    b = _batch(w)
+    act = np.zeros((0, 2), np.float32)
+    g, gm, gf = _gpu_step(b, st, act, forces=True)
+    ow = O.OracleWorld(w)
+    o, om, of = ow.step(st, act, want_forces=True)
+    band = _mask_check(w, ow, st, gm, om)
+    ok = np.ones(N, bool)
+    ok[2 * band] = ok[2 * band + 1] = False
+    assert om.sum() > E // 8
+    # Forces scale like c * penetration; compare against the largest force.
+    scale = max(np.abs(of[:2]).max(), 1e-3)
+    tscale = max(np.abs(of[2]).max(), 1e-4)
+    fe = np.abs(gf[:2, ok] - of[:2, ok]).max() / scale
+    te = np.abs(gf[2, ok] - of[2, ok]).max() / tscale
+    print(f"{name}: contacts {om.sum()}, band {len(band)}, force err {fe:.3g}, torque err {te:.3g}")
+    assert fe <= 1e-4 and te <= 1e-3
+    assert PU.env_rel_err(g[:, ok], o[:, ok],
+                          (np.arange(ok.sum() // 2 + 1) * 2).astype(np.int32)).max() <= 1e-5
+
+
+# ------------------------------------------------------------ edge cases ---
+
+def test_edge_cases_ragged_and_degenerate():
+    """Ragged batch with single-entity environments, environments with no
+    agent, an environment of immovable entities only, coincident spheres and
+    a speed cap."""
+    sizes = [1, 2, 5, 1, 3, 7, 2]
+    E = len(sizes)
+    off = np.zeros(E + 1, np.int32)
+    off[1:] = np.cumsum(sizes)
+    N = int(off[-1])
+    rng = np.random.default_rng(11)
+    st = np.zeros((6, N), np.float32)
+    st[0:2] = rng.uniform(-0.15, 0.15, (2, N)).astype(np.float32)
+    st[0:2, off[2]:off[2] + 2] = 0.05  # coincident spheres
+    flags = np.full(N, 7, np.uint8)
+    flags[off[4]:off[5]] = W.COLLIDABLE  # all-static environment
+    n_agents = np.array([1, 0, 3, 1, 0, 4, 2], np.int32)
+    w = W.World(env_offset=off, n_agents=n_agents, shape=np.zeros(N, np.uint8),
+                dims=np.full((N, 2), 0.06, np.float32), mass=np.ones(N, np.float32),
+                flags=flags, state0=st, max_speed=np.full(N, 0.5, np.float32))
+    b = _batch(w)
+    T = 30
+    acts = w.actions(T) * 5
+    ow = O.OracleWorld(w)
+    g, gm, _ = _gpu_step(b, st, acts[0])
+    o, om, _ = ow.step(st, acts[0])
+    assert PU.env_rel_err(g, o, off).max() <= 1e-5
+    assert np.array_equal(gm, om)
+    s = _dev(st)
+    b.rollout(s, _dev(acts))
+    s0 = _dev(st)
+    b.rollout(s0, _dev(acts[:0]), T=0)  # T = 0 leaves the state alone
+    torch.cuda.synchronize()
+    assert torch.equal(s0, _dev(st))
+    o, _, _ = ow.rollout(st, acts, want_mask=False)
+    gg = s.cpu().numpy().reshape(6, -1)
+    assert PU.env_rel_err(gg, o, off).max() <= 1e-3
+    assert np.all(gg[:, off[4]:off[5]] == st[:, off[4]:off[5]])
+    assert np.all(np.hypot(gg[2], gg[3]) <= 0.5 * (1 + 1e-6))
+
+
+def test_uneven_batch_parity():
+    """Environments of 2..64 sphere agents (ragged CSR) in one launch."""
+    w = W.uneven(96, seed=1)
+    T = 40
+    acts = w.actions(T)
+    b = _batch(w)
+    g1, gm, _ = _gpu_step(b, w.state0, acts[0])
+    ow = O.OracleWorld(w)
+    o1, om, _ = ow.step(w.state0, acts[0])
+    assert PU.env_rel_err(g1, o1, w.env_offset).max() <= 1e-5
+    assert np.array_equal(gm, om)
+    st = _dev(w.state0)
+    b.rollout(st, _dev(acts))
+    torch.cuda.synchronize()
+    g = st.cpu().numpy().reshape(6, -1)
+    o, _, tr = ow.rollout(w.state0, acts, traj=True, want_mask=False)
+    err = PU.env_rel_err(g, o, w.env_offset).max(1)
+    sensitive = PU.ill_conditioned(ow, w.state0, acts) | PU.near_threshold_envs(ow, tr, 1e-5)
+    print(f"uneven96 T=40: sensitive {sensitive.sum()}/96, max err {err[~sensitive].max():.3g}")
+    assert err[~sensitive].max() <= 1e-3
+
+
+def test_trajectory_output():
+    w = W.mixed(8, seed=2)
+    T = 6
+    acts = _dev(w.actions(T))
+    b = _batch(w)
+    tr = torch.zeros((T + 1) * 6 * w.n_entities, device="cuda:0")
+    s = _dev(w.state0)
+    b.rollout(s, acts, traj=tr)
+    s2 = _dev(w.state0)
+    for t in range(T):
+        b.step(s2, acts[t].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(tr.view(T + 1, -1)[t + 1], s2), t
+    assert torch.equal(tr.view(T + 1, -1)[0], _dev(w.state0))
