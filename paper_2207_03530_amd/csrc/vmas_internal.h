@@ -102,6 +102,9 @@ hipError_t launch_rollout(const StepArgs& a, int groups, int block, bool spheres
                           hipStream_t s);
 hipError_t launch_backward(const BackArgs& a, int groups, int block, bool spheres_only,
                            hipStream_t s);
+// Device function of the rollout kernel launched by launch_rollout (for
+// explicit graph construction); dynamic LDS is max_stage * 48 bytes.
+const void* rollout_kernel(bool spheres_only, int block);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_replicate(const float* src, float* dst, int64_t n, int copies, hipStream_t s);

@@ -60,36 +60,11 @@ struct Hit {
   V2 n, plo, phi;
 };
 
-// Closest point to p on segment [a, b].
-__device__ __forceinline__ V2 seg_closest(V2 p, V2 a, V2 b) {
-  V2 ab = vsub(b, a);
-  float l2 = vdot(ab, ab);
-  if (l2 == 0.0f) return a;
-  float t = vdot(vsub(p, a), ab) / l2;
-  t = fminf(fmaxf(t, 0.0f), 1.0f);
-  return V2{fmaf(ab.x, t, a.x), fmaf(ab.y, t, a.y)};
-}
-
 __device__ __forceinline__ void line_ends(const Geo& g, V2* a, V2* b) {
   float h = 0.5f * g.d0;
   V2 u = V2{g.cs * h, g.sn * h};
   *a = vsub(g.c, u);
   *b = vadd(g.c, u);
-}
-
-// sphere centre c against a line segment: Hit with lo = sphere, hi = line.
-__device__ Hit sphere_line(V2 c, const Geo& l) {
-  V2 a, b;
-  line_ends(l, &a, &b);
-  V2 q = seg_closest(c, a, b);
-  V2 dl = vsub(c, q);
-  Hit h;
-  h.d = sqrtf(vdot(dl, dl));
-  if (h.d == 0.0f) h.n = V2{-l.sn, l.cs};
-  else h.n = vscl(dl, 1.0f / h.d);
-  h.plo = c;
-  h.phi = q;
-  return h;
 }
 
 // sphere centre c against a solid box: Hit with lo = sphere, hi = box.
@@ -126,38 +101,81 @@ __device__ Hit sphere_box(V2 c, const Geo& bx) {
 
 __device__ __forceinline__ int fsign(float x) { return (x > 0.0f) - (x < 0.0f); }
 
-// Running minimum over vertex-versus-edge candidates (squared distances,
-// first strict minimum wins).
+// Running minimum over vertex-versus-edge candidates (first strict minimum
+// of the squared distance wins). A candidate is worked out in the frame of
+// the edge p0 + s u, 0 <= s <= len (u unit): when the foot is interior the
+// separation direction is the edge normal itself, so the normal stays exact
+// to rounding of (cos, sin) however close the vertex is; only a foot at an
+// end of the edge uses the (vertex - end) vector.
 struct Closest {
-  float d2;
-  V2 e, q;
-  bool of_lo;
+  float d2, d;
+  V2 e, q, dir;  // vertex, foot, unit direction from the foot to the vertex
+  bool exact;    // dir already known (interior foot)
+  bool of_lo;    // the vertex belongs to lo
 };
 
-__device__ __forceinline__ void consider(Closest& b, V2 e, V2 q, bool of_lo) {
-  V2 dl = vsub(e, q);
-  float d2 = vdot(dl, dl);
-  if (d2 < b.d2) {
-    b.d2 = d2;
-    b.e = e;
-    b.q = q;
-    b.of_lo = of_lo;
+__device__ __forceinline__ void consider(Closest& b, V2 e, V2 p0, V2 u, float len, bool of_lo) {
+  const V2 r = vsub(e, p0);
+  const float st = vdot(r, u);
+  if (st > 0.0f && st < len) {
+    const float sn = vcross(u, r);  // offset along the left normal (-u.y, u.x)
+    const float d2 = sn * sn;
+    if (d2 < b.d2) {
+      b.d2 = d2;
+      b.d = fabsf(sn);
+      b.e = e;
+      b.q = V2{fmaf(u.x, st, p0.x), fmaf(u.y, st, p0.y)};
+      b.dir = sn >= 0.0f ? V2{-u.y, u.x} : V2{u.y, -u.x};
+      b.exact = true;
+      b.of_lo = of_lo;
+    }
+  } else {
+    const V2 q = st <= 0.0f ? p0 : V2{fmaf(u.x, len, p0.x), fmaf(u.y, len, p0.y)};
+    const V2 w = vsub(e, q);
+    const float d2 = vdot(w, w);
+    if (d2 < b.d2) {
+      b.d2 = d2;
+      b.d = -1.0f;
+      b.e = e;
+      b.q = q;
+      b.exact = false;
+      b.of_lo = of_lo;
+    }
   }
 }
 
+// fb_lo / fb_hi: the normal of lo used at zero distance when the vertex
+// belongs to lo / to hi.
 __device__ __forceinline__ Hit finish_closest(const Closest& b, V2 fb_lo, V2 fb_hi) {
   Hit h;
-  h.d = sqrtf(b.d2);
-  if (b.of_lo) {  // vertex e of lo, foot q on hi: lo pushed from q to e
-    h.n = h.d == 0.0f ? fb_lo : vscl(vsub(b.e, b.q), 1.0f / h.d);
+  V2 dir;
+  if (b.exact) {
+    h.d = b.d;
+    dir = b.dir;
+  } else {
+    h.d = sqrtf(b.d2);
+    dir = h.d == 0.0f ? (b.of_lo ? fb_lo : vneg(fb_hi)) : vscl(vsub(b.e, b.q), 1.0f / h.d);
+  }
+  if (b.of_lo) {  // vertex of lo, foot on hi: lo pushed from the foot to the vertex
+    h.n = dir;
     h.plo = b.e;
     h.phi = b.q;
-  } else {        // vertex e of hi, foot q on lo: lo pushed from e to q
-    h.n = h.d == 0.0f ? fb_hi : vscl(vsub(b.q, b.e), 1.0f / h.d);
+  } else {        // vertex of hi, foot on lo: lo pushed the other way
+    h.n = vneg(dir);
     h.plo = b.q;
     h.phi = b.e;
   }
   return h;
+}
+
+// sphere centre c against a line segment: Hit with lo = sphere, hi = line.
+__device__ Hit sphere_line(V2 c, const Geo& l) {
+  V2 a, bb;
+  line_ends(l, &a, &bb);
+  Closest b;
+  b.d2 = INFINITY;
+  consider(b, c, a, V2{l.cs, l.sn}, l.d0, true);
+  return finish_closest(b, V2{-l.sn, l.cs}, V2{-l.sn, l.cs});
 }
 
 // Two segments: orientation-sign crossing test; apart -> exact distance,
@@ -183,10 +201,11 @@ __device__ Hit line_line(const Geo& I, const Geo& J) {
   if (!crossing) {
     Closest b;
     b.d2 = INFINITY;
-    consider(b, ai, seg_closest(ai, aj, bj), true);
-    consider(b, bi, seg_closest(bi, aj, bj), true);
-    consider(b, aj, seg_closest(aj, ai, bi), false);
-    consider(b, bj, seg_closest(bj, ai, bi), false);
+    const V2 ti = V2{I.cs, I.sn}, tj = V2{J.cs, J.sn};
+    consider(b, ai, aj, tj, J.d0, true);
+    consider(b, bi, aj, tj, J.d0, true);
+    consider(b, aj, ai, ti, I.d0, false);
+    consider(b, bj, ai, ti, I.d0, false);
     return finish_closest(b, nj, vneg(ni));
   }
   // Endpoints in order ai, bi (against line J), aj, bj (against line I).
@@ -218,6 +237,8 @@ struct Poly {
   int nv, ne, na;
   V2 v[4];
   V2 ax[2];
+  V2 eu[4];    // unit direction of edge k (from v[k] to v[k+1])
+  float el[4]; // its length
 };
 
 __device__ __forceinline__ void make_poly(const Geo& g, Poly& p) {
@@ -232,6 +253,14 @@ __device__ __forceinline__ void make_poly(const Geo& g, Poly& p) {
     p.v[3] = vadd(g.c, vrot(g.cs, g.sn, V2{hx, -hy}));
     p.ax[0] = V2{g.cs, g.sn};
     p.ax[1] = V2{-g.sn, g.cs};
+    p.eu[0] = V2{-g.cs, -g.sn};
+    p.eu[1] = V2{g.sn, -g.cs};
+    p.eu[2] = V2{g.cs, g.sn};
+    p.eu[3] = V2{-g.sn, g.cs};
+    p.el[0] = g.d0;
+    p.el[1] = g.d1;
+    p.el[2] = g.d0;
+    p.el[3] = g.d1;
   } else {
     p.nv = 2;
     p.ne = 1;
@@ -241,6 +270,10 @@ __device__ __forceinline__ void make_poly(const Geo& g, Poly& p) {
     p.v[3] = p.v[0];
     p.ax[0] = V2{-g.sn, g.cs};
     p.ax[1] = p.ax[0];
+    p.eu[0] = V2{g.cs, g.sn};
+    p.el[0] = g.d0;
+    p.eu[1] = p.eu[2] = p.eu[3] = p.eu[0];
+    p.el[1] = p.el[2] = p.el[3] = p.el[0];
   }
 }
 
@@ -292,7 +325,7 @@ __device__ Hit poly_poly(const Geo& I, const Geo& J) {
       if (q < A.nv) {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (e < B.ne) consider(b, A.v[q], seg_closest(A.v[q], B.v[e], B.v[(e + 1) & 3]), true);
+          if (e < B.ne) consider(b, A.v[q], B.v[e], B.eu[e], B.el[e], true);
       }
     }
 #pragma unroll
@@ -300,7 +333,7 @@ __device__ Hit poly_poly(const Geo& I, const Geo& J) {
       if (q < B.nv) {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (e < A.ne) consider(b, B.v[q], seg_closest(B.v[q], A.v[e], A.v[(e + 1) & 3]), false);
+          if (e < A.ne) consider(b, B.v[q], A.v[e], A.eu[e], A.el[e], false);
       }
     }
     return finish_closest(b, V2{1.0f, 0.0f}, V2{1.0f, 0.0f});
@@ -643,6 +676,12 @@ hipError_t launch_rollout(const StepArgs& a, int groups, int block, bool spheres
       hipLaunchKernelGGL((k_rollout<false, 1024>), dim3(groups), dim3(block), shm, s, a);
   }
   return hipGetLastError();
+}
+
+const void* rollout_kernel(bool spheres_only, int block) {
+  if (block <= 256)
+    return spheres_only ? (const void*)k_rollout<true, 256> : (const void*)k_rollout<false, 256>;
+  return spheres_only ? (const void*)k_rollout<true, 1024> : (const void*)k_rollout<false, 1024>;
 }
 
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, hipStream_t s) {

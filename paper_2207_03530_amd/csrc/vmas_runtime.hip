@@ -653,36 +653,28 @@ vmas_status vmas_rollout_graph(vmas_batch* b, float* state, const float* actions
   a.t0 = t0;
   a.T = T;
   const bool drawn = actions == nullptr;
+  void* args[1] = {&a};
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(rollout_kernel(b->spheres_only, p.block));
+  kp.gridDim = dim3(p.groups);
+  kp.blockDim = dim3(p.block);
+  kp.sharedMemBytes = (unsigned)((size_t)p.max_stage * 3 * sizeof(float4));
+  kp.kernelParams = args;
+  kp.extra = nullptr;
   if (!b->gexec || b->graph_T != T || b->graph_plan != b->cur || b->graph_drawn != drawn) {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->gexec = nullptr;
     b->graph = nullptr;
-    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t le = launch_rollout(a, p.groups, p.block, b->spheres_only, s);
-    hipGraph_t g = nullptr;
-    hipError_t ce = hipStreamEndCapture(s, &g);
-    if (le != hipSuccess || ce != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      return fail(VMAS_ERR_DEVICE, "graph capture failed: %s / %s", hipGetErrorString(le),
-                  hipGetErrorString(ce));
-    }
-    b->graph = g;
-    size_t nn = 1;
-    hipGraphNode_t nodes[1];
-    HIPCHK(hipGraphGetNodes(g, nodes, &nn));
-    if (nn != 1) return fail(VMAS_ERR_DEVICE, "captured graph has %zu nodes", nn);
-    b->gnode = nodes[0];
-    HIPCHK(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+    // The graph holds the single rollout kernel node; it is built explicitly
+    // (no stream capture), so any stream, the default one included, works.
+    HIPCHK(hipGraphCreate(&b->graph, 0));
+    HIPCHK(hipGraphAddKernelNode(&b->gnode, b->graph, nullptr, 0, &kp));
+    HIPCHK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
     b->graph_T = T;
     b->graph_plan = b->cur;
     b->graph_drawn = drawn;
   } else {
-    hipKernelNodeParams kp;
-    HIPCHK(hipGraphKernelNodeGetParams(b->gnode, &kp));
-    void* args[1] = {&a};
-    kp.kernelParams = args;
-    kp.extra = nullptr;
     HIPCHK(hipGraphExecKernelNodeSetParams(b->gexec, b->gnode, &kp));
   }
   HIPCHK(hipGraphLaunch(b->gexec, s));

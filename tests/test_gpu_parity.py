@@ -1,11 +1,12 @@
 """GPU parity of the HIP step against the FP64 oracle, element by element.
 
-Tolerances: FP32 state within 1e-5 relative (per environment, per field
-group) after one step and 1e-3 after 100 steps; the integer contact mask
-bit for bit. Environments whose outcome hinges on rounding (a pair within
-a band of its contact threshold, where Eq. 2 jumps by c k ln 2, or FP64
-itself moving under a 1e-7 perturbation) are counted and excluded from the
-multi-step state check, never hidden; their counts are asserted small.
+Tolerances: FP32 state within 1e-5 relative after one step and 1e-3 after
+100 steps (normwise per field group, tests/parity.py); the integer contact
+mask bit for bit, except where FP32 and FP64 legitimately decide a pair
+within rounding of its threshold (sphere pairs: never, both sides apply the
+same FP32 rule; other pairs: inside a band of 1e-5 around d_min). Every
+exclusion (ill-conditioned environment, valid trajectory fork) is counted,
+printed and bounded.
 """
 import numpy as np
 import pytest
@@ -43,19 +44,79 @@ def _gpu_step(b, state, act, masks=True, forces=False):
     return out
 
 
-def _mask_check(w, ow, state, gmask, omask, strict_all=False):
+def _gpu_run(b, state0, acts, ids=None, slots=None):
+    """Step loop on the GPU: states [T+1, 6, n] and masks [T, p] (restricted
+    to entity ids / pair slots when given)."""
+    T = acts.shape[0]
+    s = _dev(state0)
+    a = _dev(acts)
+    mk = torch.zeros(b.P, dtype=torch.uint8, device="cuda:0")
+    ids_t = None if ids is None else torch.as_tensor(ids, device="cuda:0")
+    sl_t = None if slots is None else torch.as_tensor(slots, device="cuda:0")
+    trs, mks = [], []
+    pick = (lambda x: x.view(6, -1)) if ids_t is None else (lambda x: x.view(6, -1)[:, ids_t])
+    trs.append(pick(s).cpu().numpy())
+    for t in range(T):
+        b.step(s, a[t], mk)
+        trs.append(pick(s).cpu().numpy())
+        mks.append((mk if sl_t is None else mk[sl_t]).cpu().numpy())
+    return s, np.stack(trs), np.stack(mks)
+
+
+def _mask_check(w, ow, state, gmask, omask):
     """Sphere-sphere slots bit-exact; other slots may differ only inside BAND."""
     lo, hi = PU.pair_shapes(w.shape, w.env_offset)
     sph = (lo == W.SPHERE) & (hi == W.SPHERE)
     diff = gmask != omask
     assert not np.any(diff & sph), f"sphere-pair mask mismatch at {np.nonzero(diff & sph)[0][:10]}"
-    if strict_all:
-        assert not np.any(diff)
     if np.any(diff):
         d, dm = O.pair_distances(ow, state)
         bad = diff & ~(np.abs(d - dm) <= BAND)
         assert not np.any(bad), f"mask mismatch outside the band at {np.nonzero(bad)[0][:10]}"
     return np.nonzero(diff)[0]
+
+
+def _one_step_check(w, ow, st, act, g, o, name, skip=None, max_ill_frac=0.02):
+    err = PU.env_err(g, o, w.env_offset)
+    ill = PU.ill_conditioned_step(ow, st, act)
+    if skip is not None:
+        ill = ill | skip
+    loc = PU.env_rel_err_local(g, o, w.env_offset)
+    good = ~ill
+    print(f"{name}: max err {err.max():.3g}, on well-conditioned {err[good].max():.3g}, "
+          f"ill-conditioned {ill.sum()}/{w.n_envs}, per-env-relative on well-conditioned "
+          f"median {np.median(loc[good].max(1)):.3g}")
+    assert ill.sum() <= max(1, int(max_ill_frac * w.n_envs))
+    assert err[good].max() <= 1e-5, f"{name}: worst env {np.argmax(np.where(good, err.max(1), 0))}"
+    return err
+
+
+def _free_run_check(w, ow, gtraj, gmasks, acts, name, tol=1e-3, min_full=0.75, min_steps=None):
+    """Free-running comparison up to each environment's cutoff: the first
+    valid mask fork or the FP64 predictability horizon, whichever comes
+    first. Every step up to the cutoff must agree within `tol`; at least a
+    fraction `min_full` of the environments must be comparable for
+    `min_steps` steps (default: all T)."""
+    ora, fork, invalid = PU.fork_compare(ow, gtraj, gmasks, w.state0, acts)
+    assert not invalid, f"{name}: mask forks outside the deviation band: {invalid[:5]}"
+    T = acts.shape[0]
+    hor = PU.horizon(ow, w.state0, acts, tol=tol)
+    cut = np.minimum(fork, hor)
+    worst = 0.0
+    for t in range(1, T + 1):
+        live = cut >= t
+        if not live.any():
+            break
+        e = PU.env_err(gtraj[t], ora[t], w.env_offset, PU.group_scale(ora[t])).max(1)
+        worst = max(worst, e[live].max())
+        assert e[live].max() <= tol, f"{name}: step {t}: err {e[live].max():.3g}"
+    need = T if min_steps is None else min_steps
+    full = (cut >= need).mean()
+    print(f"{name}: forks {(fork < T).sum()}, FP64 horizon < T {(hor < T).sum()}, "
+          f"median cutoff {np.median(cut):.0f}/{T}, comparable >= {need} steps {full:.2f}, "
+          f"max err up to cutoffs {worst:.3g}")
+    assert full >= min_full
+    return ora
 
 
 # ------------------------------------------------------------ spheres ------
@@ -67,8 +128,7 @@ def test_spread32_one_step_parity_and_mask():
     g, gm, gf = _gpu_step(b, w.state0, act, forces=True)
     ow = O.OracleWorld(w)
     o, om, of = ow.step(w.state0, act, want_forces=True)
-    err = PU.env_rel_err(g, o, w.env_offset)
-    assert err.max() <= 1e-5, err.max()
+    _one_step_check(w, ow, w.state0, act, g, o, "spread32 step")
     assert np.array_equal(gm, om)
     assert om.sum() > 0
     act_ent = (w.flags & (W.MOVABLE | W.ROTATABLE)) != 0
@@ -87,41 +147,29 @@ def test_spread32_one_step_from_oracle_states(t):
     b = _batch(w)
     g, gm, _ = _gpu_step(b, st, acts[t])
     o, om, _ = ow.step(st, acts[t])
-    assert PU.env_rel_err(g, o, w.env_offset).max() <= 1e-5
+    _one_step_check(w, ow, st, acts[t], g, o, f"spread32 step from t={t}")
     assert np.array_equal(gm, om)
 
 
 def test_spread32_hundred_steps():
-    """Free-running 100-step rollout (one persistent launch) against the FP64
-    oracle: 1e-3 relative, excluding environments the FP64 conditioning check
-    or the near-threshold scan marks as rounding-sensitive (counted)."""
+    """Free-running 100 steps against the FP64 oracle, per-step masks compared
+    (forks only where valid), final state at 1e-3."""
     w = W.spread(32)
     T = 100
     acts = w.actions(T)
     b = _batch(w)
-    st = _dev(w.state0)
-    mk = torch.zeros(b.P, dtype=torch.uint8, device="cuda:0")
-    b.rollout(st, _dev(acts), final_mask=mk)
+    s, gtraj, gmasks = _gpu_run(b, w.state0, acts)
+    s2 = _dev(w.state0)
+    b.rollout(s2, _dev(acts))  # the persistent launch gives the same bits
     torch.cuda.synchronize()
-    g = st.cpu().numpy().reshape(6, -1)
+    assert torch.equal(s, s2)
     ow = O.OracleWorld(w)
-    o, om, tr = ow.rollout(w.state0, acts, traj=True)
-    err = PU.env_rel_err(g, o, w.env_offset).max(1)
-    sensitive = PU.ill_conditioned(ow, w.state0, acts) | PU.near_threshold_envs(ow, tr, 1e-5)
-    print(f"spread32 T=100: max err {err.max():.3g}, max err on well-conditioned "
-          f"{err[~sensitive].max() if (~sensitive).any() else 0:.3g}, sensitive envs "
-          f"{sensitive.sum()}/{w.n_envs}")
-    assert sensitive.sum() <= w.n_envs // 4
-    assert err[~sensitive].max() <= 1e-3
-    # final mask on well-conditioned environments
-    penv = PU.pair_env(w.env_offset)
-    keep = ~sensitive[penv]
-    assert np.array_equal(mk.cpu().numpy()[keep], om[keep])
+    _free_run_check(w, ow, gtraj, gmasks, acts, "spread32 T=100")
 
 
 def test_step_loop_equals_rollout_bitwise():
     """T single-step launches and one T-step persistent launch give the same bits."""
-    w = W.spread(16)
+    w = W.mixed(16, seed=3)
     T = 20
     acts = _dev(w.actions(T))
     b = _batch(w)
@@ -165,24 +213,24 @@ def test_drawn_actions_equal_host_actions_bitwise():
 
 
 def test_all_schedules_bitwise_equal():
-    w = W.uneven(300, lo=2, hi=20, seed=2)
-    acts = _dev(w.actions(15))
-    b = _batch(w)
-    ref = None
-    names = []
-    for q in range(b.n_schedules):
-        name = b.schedule_name(q)
-        if not name:
-            continue
-        names.append(name)
-        b.set_schedule(q)
-        s = _dev(w.state0)
-        b.rollout(s, acts)
-        torch.cuda.synchronize()
-        if ref is None:
-            ref = s.clone()
-        assert torch.equal(s, ref), name
-    assert len(names) >= 2
+    for w in (W.uneven(300, lo=2, hi=20, seed=2), W.mixed(40, seed=6)):
+        acts = _dev(w.actions(15))
+        b = _batch(w)
+        ref = None
+        names = []
+        for q in range(b.n_schedules):
+            name = b.schedule_name(q)
+            if not name:
+                continue
+            names.append(name)
+            b.set_schedule(q)
+            s = _dev(w.state0)
+            b.rollout(s, acts)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = s.clone()
+            assert torch.equal(s, ref), name
+        assert len(names) >= 2
 
 
 def test_determinism_run_twice():
@@ -200,8 +248,9 @@ def test_determinism_run_twice():
 
 
 def test_graph_replay_equals_eager():
-    """Replays of the cached rollout graph, with eager work in between, match
-    the eager launch every time (also after the graph's arguments change)."""
+    """Replays of the cached rollout graph, with eager work and
+    synchronisations in between, match the eager launch every time (also
+    after the graph's arguments change)."""
     w = W.spread(500, seed=1)
     T = 12
     b = _batch(w)
@@ -225,9 +274,10 @@ def test_graph_replay_equals_eager():
 
 def test_spread30k_full_size_sampled_envs():
     """The 30,000-environment configuration in the benchmark's launch shape
-    (one 100-step persistent rollout); 256 sampled environments are checked
-    against the oracle (environments are independent, so the oracle runs the
-    sample as its own batch with the same per-environment inputs)."""
+    (one 100-step persistent rollout, autotuned plan). The step loop gives the
+    same bits; 256 sampled environments are followed step by step against the
+    oracle (environments are independent, so the oracle runs the sample as its
+    own batch with the same per-environment inputs)."""
     w = W.spread(30000)
     T = 100
     acts = w.actions(T)
@@ -235,22 +285,17 @@ def test_spread30k_full_size_sampled_envs():
     q = b.autotune(_dev(w.state0), 10)
     st = _dev(w.state0)
     b.rollout(st, _dev(acts))
-    torch.cuda.synchronize()
-    g = st.cpu().numpy().reshape(6, -1)
     rng = np.random.default_rng(0)
     envs = np.sort(rng.choice(w.n_envs, 256, replace=False))
-    ws = W.subset(w, envs)
     ids = np.concatenate([np.arange(w.env_offset[e], w.env_offset[e + 1]) for e in envs])
+    slots = np.concatenate([np.arange(15 * e, 15 * e + 15) for e in envs])
     rows = np.concatenate([np.arange(4 * e, 4 * e + 4) for e in envs])
-    ow = O.OracleWorld(ws)
-    o, _, tr = ow.rollout(ws.state0, acts[:, rows], traj=True, want_mask=False)
-    err = PU.env_rel_err(g[:, ids], o, ws.env_offset).max(1)
-    sensitive = PU.ill_conditioned(ow, ws.state0, acts[:, rows]) | \
-        PU.near_threshold_envs(ow, tr, 1e-5)
-    print(f"spread30k (plan {b.schedule_name(q)}): sampled max err {err.max():.3g}, "
-          f"sensitive {sensitive.sum()}/256")
-    assert sensitive.sum() <= 64
-    assert err[~sensitive].max() <= 1e-3
+    s, gtraj, gmasks = _gpu_run(b, w.state0, acts, ids=ids, slots=slots)
+    torch.cuda.synchronize()
+    assert torch.equal(s, st)
+    ws = W.subset(w, envs)
+    print(f"spread30k plan {b.schedule_name(q)}")
+    _free_run_check(ws, O.OracleWorld(ws), gtraj, gmasks, acts[:, rows], "spread30k sample")
 
 
 # ------------------------------------------------------- mixed shapes ------
@@ -264,17 +309,15 @@ def test_mixed_one_step_full_size():
     ow = O.OracleWorld(w)
     o, om, of = ow.step(w.state0, act, want_forces=True)
     band = _mask_check(w, ow, w.state0, gm, om)
-    penv = PU.pair_env(w.env_offset)
     skip = np.zeros(w.n_envs, bool)
-    skip[penv[band]] = True
-    err = PU.env_rel_err(g, o, w.env_offset)
-    print(f"mixed4096 one step: band mask cases {len(band)}, max err {err[~skip].max():.3g}, "
-          f"contacts {om.sum()}")
+    skip[PU.pair_env(w.env_offset)[band]] = True
+    print(f"mixed4096: contacts {om.sum()}, band mask cases {len(band)}")
     assert len(band) <= 4
-    assert err[~skip].max() <= 1e-5
+    _one_step_check(w, ow, w.state0, act, g, o, "mixed4096 step", skip=skip)
+    fscale = np.abs(of).max(1, keepdims=True)
     ent_env = np.repeat(np.arange(w.n_envs), np.diff(w.env_offset))
-    ok = ~skip[ent_env]
-    np.testing.assert_allclose(gf[:, ok], of[:, ok], rtol=2e-4, atol=2e-4)
+    ok = ~(skip | PU.ill_conditioned_step(ow, w.state0, act))[ent_env]
+    assert (np.abs(gf - of)[:, ok] / fscale).max() <= 1e-5
 
 
 def test_mixed_multi_step_parity():
@@ -283,18 +326,9 @@ def test_mixed_multi_step_parity():
     T = 200
     acts = w.actions(T)
     b = _batch(w)
-    st = _dev(w.state0)
-    b.rollout(st, _dev(acts))
-    torch.cuda.synchronize()
-    g = st.cpu().numpy().reshape(6, -1)
+    _, gtraj, gmasks = _gpu_run(b, w.state0, acts)
     ow = O.OracleWorld(w)
-    o, _, tr = ow.rollout(w.state0, acts, traj=True, want_mask=False)
-    err = PU.env_rel_err(g, o, w.env_offset).max(1)
-    sensitive = PU.ill_conditioned(ow, w.state0, acts) | PU.near_threshold_envs(ow, tr, BAND)
-    print(f"mixed48 T=200: well-conditioned {(~sensitive).sum()}/48, max err there "
-          f"{err[~sensitive].max() if (~sensitive).any() else 0:.3g}")
-    if (~sensitive).any():
-        assert err[~sensitive].max() <= 1e-3
+    _free_run_check(w, ow, gtraj, gmasks, acts, "mixed48 T=200", min_full=0.5, min_steps=5)
 
 
 SHAPE_CASES = [
@@ -313,10 +347,10 @@ SHAPE_CASES = [
 @pytest.mark.parametrize("name,a,c", SHAPE_CASES, ids=[s[0] for s in SHAPE_CASES])
 def test_pair_type_micro_cases(name, a, c):
     """Each narrow-phase routine in isolation: 512 two-entity environments,
-    random relative poses (about half overlapping), forces and torques of one
-    step against the oracle."""
+    random relative poses (many overlapping), one step against the oracle,
+    forces and torques included."""
     E = 512
-    rng = np.random.default_rng(hash(name) % 2 ** 32)
+    rng = np.random.default_rng(sum(map(ord, name)))
     N = 2 * E
     shape = np.tile(np.array([a[0], c[0]], np.uint8), E)
     dims = np.tile(np.array([[a[1], a[2]], [c[1], c[2]]], np.float32), (E, 1))
@@ -334,18 +368,15 @@ def test_pair_type_micro_cases(name, a, c):
     ow = O.OracleWorld(w)
     o, om, of = ow.step(st, act, want_forces=True)
     band = _mask_check(w, ow, st, gm, om)
-    ok = np.ones(N, bool)
-    ok[2 * band] = ok[2 * band + 1] = False
     assert om.sum() > E // 8
-    # Forces scale like c * penetration; compare against the largest force.
-    scale = max(np.abs(of[:2]).max(), 1e-3)
-    tscale = max(np.abs(of[2]).max(), 1e-4)
-    fe = np.abs(gf[:2, ok] - of[:2, ok]).max() / scale
-    te = np.abs(gf[2, ok] - of[2, ok]).max() / tscale
-    print(f"{name}: contacts {om.sum()}, band {len(band)}, force err {fe:.3g}, torque err {te:.3g}")
-    assert fe <= 1e-4 and te <= 1e-3
-    assert PU.env_rel_err(g[:, ok], o[:, ok],
-                          (np.arange(ok.sum() // 2 + 1) * 2).astype(np.int32)).max() <= 1e-5
+    skip = np.zeros(E, bool)
+    skip[band] = True
+    _one_step_check(w, ow, st, act, g, o, name, skip=skip, max_ill_frac=0.03)
+    ok = ~np.repeat(skip | PU.ill_conditioned_step(ow, st, act), 2)
+    fscale = np.abs(of).max(1, keepdims=True) + 1e-12
+    ferr = (np.abs(gf - of)[:, ok] / fscale).max(1)
+    print(f"{name}: contacts {om.sum()}, band {len(band)}, force/torque err {ferr}")
+    assert ferr.max() <= 1e-5
 
 
 # ------------------------------------------------------------ edge cases ---
@@ -375,17 +406,15 @@ def test_edge_cases_ragged_and_degenerate():
     ow = O.OracleWorld(w)
     g, gm, _ = _gpu_step(b, st, acts[0])
     o, om, _ = ow.step(st, acts[0])
-    assert PU.env_rel_err(g, o, off).max() <= 1e-5
+    assert PU.env_err(g, o, off).max() <= 1e-5
     assert np.array_equal(gm, om)
-    s = _dev(st)
-    b.rollout(s, _dev(acts))
     s0 = _dev(st)
     b.rollout(s0, _dev(acts[:0]), T=0)  # T = 0 leaves the state alone
     torch.cuda.synchronize()
     assert torch.equal(s0, _dev(st))
-    o, _, _ = ow.rollout(st, acts, want_mask=False)
-    gg = s.cpu().numpy().reshape(6, -1)
-    assert PU.env_rel_err(gg, o, off).max() <= 1e-3
+    s, gtraj, gmasks = _gpu_run(b, st, acts)
+    _free_run_check(w, ow, gtraj, gmasks, acts, "edge cases T=30", min_full=0.5)
+    gg = gtraj[-1]
     assert np.all(gg[:, off[4]:off[5]] == st[:, off[4]:off[5]])
     assert np.all(np.hypot(gg[2], gg[3]) <= 0.5 * (1 + 1e-6))
 
@@ -399,17 +428,10 @@ def test_uneven_batch_parity():
     g1, gm, _ = _gpu_step(b, w.state0, acts[0])
     ow = O.OracleWorld(w)
     o1, om, _ = ow.step(w.state0, acts[0])
-    assert PU.env_rel_err(g1, o1, w.env_offset).max() <= 1e-5
+    _one_step_check(w, ow, w.state0, acts[0], g1, o1, "uneven96 step", max_ill_frac=0.15)
     assert np.array_equal(gm, om)
-    st = _dev(w.state0)
-    b.rollout(st, _dev(acts))
-    torch.cuda.synchronize()
-    g = st.cpu().numpy().reshape(6, -1)
-    o, _, tr = ow.rollout(w.state0, acts, traj=True, want_mask=False)
-    err = PU.env_rel_err(g, o, w.env_offset).max(1)
-    sensitive = PU.ill_conditioned(ow, w.state0, acts) | PU.near_threshold_envs(ow, tr, 1e-5)
-    print(f"uneven96 T=40: sensitive {sensitive.sum()}/96, max err {err[~sensitive].max():.3g}")
-    assert err[~sensitive].max() <= 1e-3
+    _, gtraj, gmasks = _gpu_run(b, w.state0, acts)
+    _free_run_check(w, ow, gtraj, gmasks, acts, "uneven96 T=40", min_full=0.5, min_steps=10)
 
 
 def test_trajectory_output():
@@ -424,5 +446,6 @@ def test_trajectory_output():
     for t in range(T):
         b.step(s2, acts[t].contiguous())
         torch.cuda.synchronize()
-        assert torch.equal(tr.view(T + 1, -1)[t + 1], s2), t
-    assert torch.equal(tr.view(T + 1, -1)[0], _dev(w.state0))
+        assert torch.equal(tr.view(T + 1, -1)[t + 1], s2.view(-1)), t
+    assert torch.equal(tr.view(T + 1, -1)[0], _dev(w.state0).view(-1))
+    assert torch.equal(s, s2)
