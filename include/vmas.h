@@ -215,6 +215,45 @@ vmas_status vmas_rollout_graph(vmas_batch* batch, float* state, const float* act
                                uint64_t action_seed, int32_t t0, int32_t T, float* traj,
                                uint8_t* final_mask, void* stream);
 
+/* ---- Learned contact surrogate -------------------------------------------
+ * A 12 -> 128 -> 128 -> 2 MLP with tanh hidden layers mapping pair features
+ * to the Eq. (2) contact force, with hand-written forward, backward and Adam
+ * kernels: products on the matrix cores with BF16 operands and FP32
+ * accumulation, everything else FP32. This is an addition to the paper's
+ * method (which has no learned component). Parameters are one FP32 vector
+ * in the order W1 [128][12], b1 [128], W2 [128][128], b2 [128], W3 [2][128],
+ * b3 [2] (row-major, output index first). Training minimises the mean
+ * squared error L = sum((y - t)^2) / (2 n). The handle owns its parameters,
+ * Adam moments (beta1 0.9, beta2 0.999, eps 1e-8) and workspaces; calls on
+ * one handle must not overlap. X, Y, dY, targets, grad and dX are DEVICE
+ * arrays owned by the caller: X [n][12], Y / dY / target [n][2]. */
+typedef struct vmas_mlp vmas_mlp;
+
+/* Number of parameters (18434). */
+int32_t vmas_mlp_num_params(void);
+
+/* params: host FP32 [num_params], or NULL for a uniform(-1/sqrt(fan_in),
+ * 1/sqrt(fan_in)) initialisation drawn from `seed`. Blocks. */
+vmas_status vmas_mlp_create(const float* params, uint64_t seed, int device, vmas_mlp** out);
+vmas_status vmas_mlp_destroy(vmas_mlp* mlp);
+
+/* Copies the FP32 parameters to host memory out [num_params]; synchronises `stream`. */
+vmas_status vmas_mlp_get_params(const vmas_mlp* mlp, float* out, void* stream);
+
+/* Y = f(X). */
+vmas_status vmas_mlp_forward(vmas_mlp* mlp, const float* X, int64_t n, float* Y, void* stream);
+
+/* Given dL/dY, the gradients dL/dparams (device [num_params], or NULL) and
+ * dL/dX (device [n][12], or NULL). Deterministic: the batch is reduced in a
+ * fixed order, no float atomics. */
+vmas_status vmas_mlp_backward(vmas_mlp* mlp, const float* X, int64_t n, const float* dY,
+                              float* grad, float* dX, void* stream);
+
+/* One Adam step on the mean squared error of the batch; loss (device [1] or
+ * NULL) receives the loss before the step. */
+vmas_status vmas_mlp_train_step(vmas_mlp* mlp, const float* X, const float* target, int64_t n,
+                                float lr, float* loss, void* stream);
+
 /* Reason for the last failure on this thread ("" if none). */
 const char* vmas_last_error(void);
 

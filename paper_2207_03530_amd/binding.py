@@ -23,7 +23,9 @@ STATUS = {0: "VMAS_OK", 1: "VMAS_ERR_INVALID_ARGUMENT", 2: "VMAS_ERR_OUT_OF_MEMO
 # Every symbol include/vmas.h declares.
 EXPORTS = ("vmas_create_batch", "vmas_destroy_batch", "vmas_batch_get_info", "vmas_step",
            "vmas_rollout", "vmas_step_backward", "vmas_rollout_backward", "vmas_set_schedule",
-           "vmas_autotune", "vmas_schedule_name", "vmas_rollout_graph", "vmas_last_error")
+           "vmas_autotune", "vmas_schedule_name", "vmas_rollout_graph", "vmas_last_error",
+           "vmas_mlp_num_params", "vmas_mlp_create", "vmas_mlp_destroy", "vmas_mlp_get_params",
+           "vmas_mlp_forward", "vmas_mlp_backward", "vmas_mlp_train_step")
 
 
 class VmasError(RuntimeError):
@@ -89,6 +91,13 @@ def lib():
     L.vmas_schedule_name.argtypes = [vp, ctypes.c_int32]
     L.vmas_schedule_name.restype = ctypes.c_char_p
     L.vmas_last_error.restype = ctypes.c_char_p
+    L.vmas_mlp_num_params.argtypes = []
+    L.vmas_mlp_create.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(vp)]
+    L.vmas_mlp_destroy.argtypes = [vp]
+    L.vmas_mlp_get_params.argtypes = [vp, vp, vp]
+    L.vmas_mlp_forward.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+    L.vmas_mlp_backward.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, vp]
+    L.vmas_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_float, vp, vp]
     for name in EXPORTS:
         if name not in ("vmas_schedule_name", "vmas_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -266,6 +275,63 @@ class Batch:
     def close(self) -> None:
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib().vmas_destroy_batch(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """The contact-surrogate network (handle of vmas_mlp_create)."""
+
+    def __init__(self, params: Optional[np.ndarray] = None, seed: int = 0, device: int = 0):
+        import torch
+        self.device = torch.device("cuda", device)
+        self.n_params = lib().vmas_mlp_num_params()
+        p = None
+        if params is not None:
+            p = np.ascontiguousarray(params, np.float32)
+            if p.size != self.n_params:
+                raise ValueError(f"params must have {self.n_params} values")
+        h = ctypes.c_void_p()
+        _check(lib().vmas_mlp_create(None if p is None else p.ctypes.data_as(ctypes.c_void_p),
+                                     ctypes.c_uint64(seed), device, ctypes.byref(h)))
+        self.handle = h
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, np.float32)
+        _check(lib().vmas_mlp_get_params(self.handle, out.ctypes.data_as(ctypes.c_void_p),
+                                         _stream(self.device)))
+        return out
+
+    def forward(self, X, Y) -> None:
+        import torch
+        n = X.shape[0]
+        _check(lib().vmas_mlp_forward(self.handle, _dptr(X, 12 * n, torch.float32, "X"), n,
+                                      _dptr(Y, 2 * n, torch.float32, "Y"), _stream(self.device)))
+
+    def backward(self, X, dY, grad=None, dX=None) -> None:
+        import torch
+        n = X.shape[0]
+        _check(lib().vmas_mlp_backward(self.handle, _dptr(X, 12 * n, torch.float32, "X"), n,
+                                       _dptr(dY, 2 * n, torch.float32, "dY"),
+                                       _dptr(grad, self.n_params, torch.float32, "grad"),
+                                       _dptr(dX, 12 * n, torch.float32, "dX"), _stream(self.device)))
+
+    def train_step(self, X, target, lr: float, loss=None) -> None:
+        import torch
+        n = X.shape[0]
+        _check(lib().vmas_mlp_train_step(self.handle, _dptr(X, 12 * n, torch.float32, "X"),
+                                         _dptr(target, 2 * n, torch.float32, "target"), n,
+                                         ctypes.c_float(lr), _dptr(loss, 1, torch.float32, "loss"),
+                                         _stream(self.device)))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().vmas_mlp_destroy(self.handle)
             self.handle = ctypes.c_void_p()
 
     def __del__(self):

@@ -1,0 +1,613 @@
+// Device geometry of the batched 2D physics step (VMAS, Sec. 3 "Core"):
+// closest features between spheres, boxes and line segments (the x_ij of
+// Eq. 2), the penalty magnitude of Eq. 2 and the pair force and torque arms
+// of Eq. 3.
+//
+// Everything is templated on the scalar type S:
+//   float -- the forward step;
+//   D3    -- a forward-mode dual number carrying the derivatives with
+//            respect to the (x, y, theta) of one entity, used by the adjoint.
+// The value part of every D3 operation is the same FP32 operation as the
+// float path (fused multiply-adds included), so both instantiations take the
+// same branches and the same contact decisions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "vmas_internal.h"
+
+namespace vmas {
+
+// ------------------------------------------------------------ dual numbers --
+
+struct D3 {
+  float v, a, b, c;  // value and d/dx, d/dy, d/dtheta of the seeded entity
+  __device__ __forceinline__ D3() {}
+  __device__ __forceinline__ D3(float x) : v(x), a(0.0f), b(0.0f), c(0.0f) {}
+  __device__ __forceinline__ D3(float x, float da, float db, float dc) : v(x), a(da), b(db), c(dc) {}
+};
+__device__ __forceinline__ D3 operator+(D3 p, D3 q) { return D3(p.v + q.v, p.a + q.a, p.b + q.b, p.c + q.c); }
+__device__ __forceinline__ D3 operator-(D3 p, D3 q) { return D3(p.v - q.v, p.a - q.a, p.b - q.b, p.c - q.c); }
+__device__ __forceinline__ D3 operator-(D3 p) { return D3(-p.v, -p.a, -p.b, -p.c); }
+__device__ __forceinline__ D3 operator*(D3 p, D3 q) {
+  return D3(p.v * q.v, p.a * q.v + p.v * q.a, p.b * q.v + p.v * q.b, p.c * q.v + p.v * q.c);
+}
+__device__ __forceinline__ D3 operator/(D3 p, D3 q) {
+  const float r = 1.0f / q.v, v = p.v / q.v;
+  return D3(v, (p.a - v * q.a) * r, (p.b - v * q.b) * r, (p.c - v * q.c) * r);
+}
+
+__device__ __forceinline__ float val(float x) { return x; }
+__device__ __forceinline__ float val(D3 x) { return x.v; }
+
+__device__ __forceinline__ float s_fma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ D3 s_fma(D3 p, D3 q, D3 r) {
+  return D3(fmaf(p.v, q.v, r.v), p.a * q.v + p.v * q.a + r.a, p.b * q.v + p.v * q.b + r.b,
+            p.c * q.v + p.v * q.c + r.c);
+}
+__device__ __forceinline__ float s_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ D3 s_sqrt(D3 p) {
+  const float s = sqrtf(p.v), k = s > 0.0f ? 0.5f / s : 0.0f;
+  return D3(s, p.a * k, p.b * k, p.c * k);
+}
+__device__ __forceinline__ float s_rsqrt(float x) { return __frsqrt_rn(x); }
+__device__ __forceinline__ D3 s_rsqrt(D3 p) {
+  const float r = __frsqrt_rn(p.v), k = -0.5f * r * r * r;
+  return D3(r, p.a * k, p.b * k, p.c * k);
+}
+__device__ __forceinline__ float s_exp(float x) { return __expf(x); }
+__device__ __forceinline__ D3 s_exp(D3 p) {
+  const float e = __expf(p.v);
+  return D3(e, p.a * e, p.b * e, p.c * e);
+}
+__device__ __forceinline__ float s_log(float x) { return __logf(x); }
+__device__ __forceinline__ D3 s_log(D3 p) {
+  const float l = __logf(p.v), k = 1.0f / p.v;
+  return D3(l, p.a * k, p.b * k, p.c * k);
+}
+template <class S> __device__ __forceinline__ S s_abs(S x) { return val(x) < 0.0f ? -x : x; }
+__device__ __forceinline__ float s_abs(float x) { return fabsf(x); }
+template <class S> __device__ __forceinline__ S s_min(S x, S y) { return val(y) < val(x) ? y : x; }
+template <class S> __device__ __forceinline__ S s_max(S x, S y) { return val(y) > val(x) ? y : x; }
+__device__ __forceinline__ float s_min(float x, float y) { return fminf(x, y); }
+__device__ __forceinline__ float s_max(float x, float y) { return fmaxf(x, y); }
+
+// ---------------------------------------------------------------- vectors --
+
+template <class S> struct V2T {
+  S x, y;
+};
+template <class S> __device__ __forceinline__ V2T<S> vadd(V2T<S> a, V2T<S> b) { return {a.x + b.x, a.y + b.y}; }
+template <class S> __device__ __forceinline__ V2T<S> vsub(V2T<S> a, V2T<S> b) { return {a.x - b.x, a.y - b.y}; }
+template <class S> __device__ __forceinline__ V2T<S> vscl(V2T<S> a, S s) { return {a.x * s, a.y * s}; }
+template <class S> __device__ __forceinline__ V2T<S> vneg(V2T<S> a) { return {-a.x, -a.y}; }
+template <class S> __device__ __forceinline__ S vdot(V2T<S> a, V2T<S> b) { return s_fma(a.x, b.x, a.y * b.y); }
+template <class S> __device__ __forceinline__ S vcross(V2T<S> a, V2T<S> b) {
+  return s_fma(a.x, b.y, -(a.y * b.x));
+}
+// R(theta) v and R(theta)^T v with (cs, sn) = (cos, sin) theta.
+template <class S> __device__ __forceinline__ V2T<S> vrot(S cs, S sn, V2T<S> v) {
+  return {s_fma(cs, v.x, -(sn * v.y)), s_fma(sn, v.x, cs * v.y)};
+}
+template <class S> __device__ __forceinline__ V2T<S> vrot_t(S cs, S sn, V2T<S> v) {
+  return {s_fma(cs, v.x, sn * v.y), s_fma(-sn, v.x, cs * v.y)};
+}
+
+// Geometry of one entity for the narrow phase: pose and (constant) size.
+template <class S> struct GeoT {
+  V2T<S> c;
+  S cs, sn;
+  float d0, d1;
+  int shape;
+};
+
+// Closest features of an ordered pair (lo, hi): signed distance between the
+// cores, unit normal along which lo is pushed, contact points on lo and hi.
+template <class S> struct HitT {
+  S d;
+  V2T<S> n, plo, phi;
+};
+
+template <class S> __device__ __forceinline__ void line_ends(const GeoT<S>& g, V2T<S>* a, V2T<S>* b) {
+  const S h = S(0.5f * g.d0);
+  const V2T<S> u = {g.cs * h, g.sn * h};
+  *a = vsub(g.c, u);
+  *b = vadd(g.c, u);
+}
+
+// Sphere centre c against a solid box: lo = sphere, hi = box. Inside, the
+// nearest face (x on a tie) gives a negative distance.
+template <class S> __device__ HitT<S> sphere_box(V2T<S> c, const GeoT<S>& bx) {
+  const S hx = S(0.5f * bx.d0), hy = S(0.5f * bx.d1);
+  const V2T<S> u = vrot_t(bx.cs, bx.sn, vsub(c, bx.c));
+  V2T<S> nl, ql;
+  HitT<S> h;
+  const S ax = s_abs(u.x), ay = s_abs(u.y);
+  if (val(ax) <= val(hx) && val(ay) <= val(hy)) {
+    const S dx = hx - ax, dy = hy - ay;
+    if (val(dx) <= val(dy)) {
+      const float s = val(u.x) >= 0.0f ? 1.0f : -1.0f;
+      h.d = -dx;
+      nl = {S(s), S(0.0f)};
+      ql = {S(s) * hx, u.y};
+    } else {
+      const float s = val(u.y) >= 0.0f ? 1.0f : -1.0f;
+      h.d = -dy;
+      nl = {S(0.0f), S(s)};
+      ql = {u.x, S(s) * hy};
+    }
+  } else {
+    ql = {s_min(s_max(u.x, -hx), hx), s_min(s_max(u.y, -hy), hy)};
+    const V2T<S> w = vsub(u, ql);
+    h.d = s_sqrt(vdot(w, w));
+    nl = vscl(w, S(1.0f) / h.d);
+  }
+  h.n = vrot(bx.cs, bx.sn, nl);
+  h.phi = vadd(bx.c, vrot(bx.cs, bx.sn, ql));
+  h.plo = c;
+  return h;
+}
+
+__device__ __forceinline__ int fsign(float x) { return (x > 0.0f) - (x < 0.0f); }
+
+// Running minimum over vertex-versus-edge candidates (first strict minimum
+// of the squared distance wins). A candidate is worked out in the frame of
+// the edge p0 + s u, 0 <= s <= len (u unit): when the foot is interior the
+// separation direction is the edge normal itself, so the normal stays exact
+// to rounding of (cos, sin) however close the vertex is; only a foot at an
+// end of the edge uses the (vertex - end) vector.
+template <class S> struct ClosestT {
+  float d2v;     // value of the running minimum of the squared distance
+  S d2, d;
+  V2T<S> e, q, dir;  // vertex, foot, unit direction from the foot to the vertex
+  bool exact;        // dir already known (interior foot)
+  bool of_lo;        // the vertex belongs to lo
+};
+
+template <class S>
+__device__ __forceinline__ void consider(ClosestT<S>& b, V2T<S> e, V2T<S> p0, V2T<S> u, float len,
+                                         bool of_lo) {
+  const V2T<S> r = vsub(e, p0);
+  const S st = vdot(r, u);
+  if (val(st) > 0.0f && val(st) < len) {
+    const S sn = vcross(u, r);  // offset along the left normal (-u.y, u.x)
+    const S d2 = sn * sn;
+    if (val(d2) < b.d2v) {
+      b.d2v = val(d2);
+      b.d2 = d2;
+      b.d = s_abs(sn);
+      b.e = e;
+      b.q = {s_fma(u.x, st, p0.x), s_fma(u.y, st, p0.y)};
+      b.dir = val(sn) >= 0.0f ? V2T<S>{-u.y, u.x} : V2T<S>{u.y, -u.x};
+      b.exact = true;
+      b.of_lo = of_lo;
+    }
+  } else {
+    const V2T<S> q = val(st) <= 0.0f ? p0 : V2T<S>{s_fma(u.x, S(len), p0.x), s_fma(u.y, S(len), p0.y)};
+    const V2T<S> w = vsub(e, q);
+    const S d2 = vdot(w, w);
+    if (val(d2) < b.d2v) {
+      b.d2v = val(d2);
+      b.d2 = d2;
+      b.d = S(-1.0f);
+      b.e = e;
+      b.q = q;
+      b.exact = false;
+      b.of_lo = of_lo;
+    }
+  }
+}
+
+// fb_lo / fb_hi: the normal of lo used at zero distance when the vertex
+// belongs to lo / to hi.
+template <class S>
+__device__ __forceinline__ HitT<S> finish_closest(const ClosestT<S>& b, V2T<S> fb_lo, V2T<S> fb_hi) {
+  HitT<S> h;
+  V2T<S> dir;
+  if (b.exact) {
+    h.d = b.d;
+    dir = b.dir;
+  } else {
+    h.d = s_sqrt(b.d2);
+    dir = val(h.d) == 0.0f ? (b.of_lo ? fb_lo : vneg(fb_hi)) : vscl(vsub(b.e, b.q), S(1.0f) / h.d);
+  }
+  if (b.of_lo) {  // vertex of lo, foot on hi: lo pushed from the foot to the vertex
+    h.n = dir;
+    h.plo = b.e;
+    h.phi = b.q;
+  } else {        // vertex of hi, foot on lo: lo pushed the other way
+    h.n = vneg(dir);
+    h.plo = b.q;
+    h.phi = b.e;
+  }
+  return h;
+}
+
+// Sphere centre c against a line segment: lo = sphere, hi = line.
+template <class S> __device__ HitT<S> sphere_line(V2T<S> c, const GeoT<S>& l) {
+  V2T<S> a, bb;
+  line_ends(l, &a, &bb);
+  ClosestT<S> b;
+  b.d2v = INFINITY;
+  consider(b, c, a, V2T<S>{l.cs, l.sn}, l.d0, true);
+  return finish_closest(b, V2T<S>{-l.sn, l.cs}, V2T<S>{-l.sn, l.cs});
+}
+
+// Two segments: orientation-sign crossing test (collinear overlap counts as
+// crossing); apart -> exact segment distance; crossing -> separating-axis
+// depth of the endpoint nearest to the other supporting line.
+template <class S> __device__ HitT<S> line_line(const GeoT<S>& I, const GeoT<S>& J) {
+  V2T<S> ai, bi, aj, bj;
+  line_ends(I, &ai, &bi);
+  line_ends(J, &aj, &bj);
+  const V2T<S> ni = {-I.sn, I.cs}, nj = {-J.sn, J.cs};
+  const V2T<S> ui = vsub(bi, ai), uj = vsub(bj, aj);
+  const int o1 = fsign(val(vcross(ui, vsub(aj, ai))));
+  const int o2 = fsign(val(vcross(ui, vsub(bj, ai))));
+  const int o3 = fsign(val(vcross(uj, vsub(ai, aj))));
+  const int o4 = fsign(val(vcross(uj, vsub(bi, aj))));
+  bool crossing;
+  if ((o1 | o2 | o3 | o4) == 0) {
+    const float tu = val(vdot(ui, ui));
+    const float ta = val(vdot(vsub(aj, ai), ui)), tb = val(vdot(vsub(bj, ai), ui));
+    crossing = !(fmaxf(ta, tb) < 0.0f || fminf(ta, tb) > tu);
+  } else {
+    crossing = (o1 * o2 <= 0) && (o3 * o4 <= 0);
+  }
+  if (!crossing) {
+    ClosestT<S> b;
+    b.d2v = INFINITY;
+    const V2T<S> ti = {I.cs, I.sn}, tj = {J.cs, J.sn};
+    consider(b, ai, aj, tj, J.d0, true);
+    consider(b, bi, aj, tj, J.d0, true);
+    consider(b, aj, ai, ti, I.d0, false);
+    consider(b, bj, ai, ti, I.d0, false);
+    return finish_closest(b, nj, vneg(ni));
+  }
+  // Endpoints in order ai, bi (against line J), aj, bj (against line I).
+  HitT<S> h;
+  float best = INFINITY;
+  S bestS = S(0.0f);
+  const V2T<S> ends[4] = {ai, bi, aj, bj};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const bool of_lo = k < 2;
+    const V2T<S> base = of_lo ? aj : ai;
+    const V2T<S> nrm = of_lo ? nj : ni;
+    const S s = vdot(vsub(ends[k], base), nrm);
+    const S dist = s_abs(s);
+    if (val(dist) < best) {
+      best = val(dist);
+      bestS = dist;
+      const V2T<S> push = val(s) > 0.0f ? vneg(nrm) : nrm;
+      h.n = of_lo ? push : vneg(push);
+      h.plo = ends[k];
+      h.phi = ends[k];
+    }
+  }
+  h.d = -bestS;
+  return h;
+}
+
+// Convex polygon view of a box (4 CCW vertices, 4 edges, 2 axes) or a line
+// (2 vertices, 1 edge, 1 axis).
+template <class S> struct PolyT {
+  int nv, ne, na;
+  V2T<S> v[4];
+  V2T<S> ax[2];
+  V2T<S> eu[4];  // unit direction of edge k (from v[k] to v[k+1])
+  float el[4];   // its length
+};
+
+template <class S> __device__ __forceinline__ void make_poly(const GeoT<S>& g, PolyT<S>& p) {
+  if (g.shape == BOX) {
+    const S hx = S(0.5f * g.d0), hy = S(0.5f * g.d1);
+    p.nv = 4;
+    p.ne = 4;
+    p.na = 2;
+    p.v[0] = vadd(g.c, vrot(g.cs, g.sn, V2T<S>{hx, hy}));
+    p.v[1] = vadd(g.c, vrot(g.cs, g.sn, V2T<S>{-hx, hy}));
+    p.v[2] = vadd(g.c, vrot(g.cs, g.sn, V2T<S>{-hx, -hy}));
+    p.v[3] = vadd(g.c, vrot(g.cs, g.sn, V2T<S>{hx, -hy}));
+    p.ax[0] = {g.cs, g.sn};
+    p.ax[1] = {-g.sn, g.cs};
+    p.eu[0] = {-g.cs, -g.sn};
+    p.eu[1] = {g.sn, -g.cs};
+    p.eu[2] = {g.cs, g.sn};
+    p.eu[3] = {-g.sn, g.cs};
+    p.el[0] = g.d0;
+    p.el[1] = g.d1;
+    p.el[2] = g.d0;
+    p.el[3] = g.d1;
+  } else {
+    p.nv = 2;
+    p.ne = 1;
+    p.na = 1;
+    line_ends(g, &p.v[0], &p.v[1]);
+    p.v[2] = p.v[1];
+    p.v[3] = p.v[0];
+    p.ax[0] = {-g.sn, g.cs};
+    p.ax[1] = p.ax[0];
+    p.eu[0] = {g.cs, g.sn};
+    p.el[0] = g.d0;
+    p.eu[1] = p.eu[2] = p.eu[3] = p.eu[0];
+    p.el[1] = p.el[2] = p.el[3] = p.el[0];
+  }
+}
+
+template <class S> __device__ __forceinline__ void project(const PolyT<S>& p, V2T<S> s, float* mn, float* mx) {
+  float a = val(vdot(p.v[0], s)), b = a;
+#pragma unroll
+  for (int q = 1; q < 4; ++q) {
+    if (q < p.nv) {
+      const float t = val(vdot(p.v[q], s));
+      a = fminf(a, t);
+      b = fmaxf(b, t);
+    }
+  }
+  *mn = a;
+  *mx = b;
+}
+
+// Projection extremes as S (only the winning axis needs derivatives).
+template <class S> __device__ __forceinline__ S proj_min(const PolyT<S>& p, V2T<S> s) {
+  S a = vdot(p.v[0], s);
+#pragma unroll
+  for (int q = 1; q < 4; ++q)
+    if (q < p.nv) a = s_min(a, vdot(p.v[q], s));
+  return a;
+}
+template <class S> __device__ __forceinline__ S proj_max(const PolyT<S>& p, V2T<S> s) {
+  S a = vdot(p.v[0], s);
+#pragma unroll
+  for (int q = 1; q < 4; ++q)
+    if (q < p.nv) a = s_max(a, vdot(p.v[q], s));
+  return a;
+}
+
+// Line/box and box/box by the separating-axis test: apart -> exact distance
+// between the convex sets (vertex against edge, lo's vertices first);
+// overlapping -> smallest overlap over the axes (lo's first), contact point
+// at the deepest vertex of the shape that does not own the winning axis.
+template <class S> __device__ HitT<S> poly_poly(const GeoT<S>& I, const GeoT<S>& J) {
+  PolyT<S> A, B;
+  make_poly(I, A);
+  make_poly(J, B);
+  bool separated = false;
+  float best = INFINITY;
+  int best_k = 0;
+  bool best_plus = true;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k < A.na + B.na) {
+      const V2T<S> s = k < A.na ? A.ax[k] : B.ax[k - A.na];
+      float mina, maxa, minb, maxb;
+      project(A, s, &mina, &maxa);
+      project(B, s, &minb, &maxb);
+      if (maxa < minb || maxb < mina) separated = true;
+      const float op = maxb - mina, om = maxa - minb;
+      const float ov = op <= om ? op : om;
+      if (ov < best) {
+        best = ov;
+        best_k = k;
+        best_plus = op <= om;
+      }
+    }
+  }
+  if (separated) {
+    ClosestT<S> b;
+    b.d2v = INFINITY;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q < A.nv) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (e < B.ne) consider(b, A.v[q], B.v[e], B.eu[e], B.el[e], true);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q < B.nv) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (e < A.ne) consider(b, B.v[q], A.v[e], A.eu[e], A.el[e], false);
+      }
+    }
+    const V2T<S> fb = {S(1.0f), S(0.0f)};
+    return finish_closest(b, fb, fb);
+  }
+  HitT<S> h;
+  V2T<S> s = A.ax[0];
+#pragma unroll
+  for (int k = 1; k < 4; ++k)
+    if (k == best_k) s = k < A.na ? A.ax[k] : B.ax[k - A.na];
+  // overlap along the winning axis with derivatives
+  h.d = best_plus ? -(proj_max(B, s) - proj_min(A, s)) : -(proj_max(A, s) - proj_min(B, s));
+  h.n = best_plus ? s : vneg(s);
+  V2T<S> p;
+  if (best_k >= A.na) {  // axis of hi: deepest vertex of lo
+    p = A.v[0];
+    float m = val(vdot(h.n, p));
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+      if (q < A.nv) {
+        const float t = val(vdot(h.n, A.v[q]));
+        if (t < m) {
+          m = t;
+          p = A.v[q];
+        }
+      }
+    }
+  } else {               // axis of lo: deepest vertex of hi
+    p = B.v[0];
+    float m = val(vdot(h.n, p));
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+      if (q < B.nv) {
+        const float t = val(vdot(h.n, B.v[q]));
+        if (t > m) {
+          m = t;
+          p = B.v[q];
+        }
+      }
+    }
+  }
+  h.plo = p;
+  h.phi = p;
+  return h;
+}
+
+// Narrow phase of a pair that is not sphere-sphere, canonical (lo, hi) order.
+template <class S> __device__ HitT<S> narrow(const GeoT<S>& lo, const GeoT<S>& hi) {
+  if (lo.shape == SPHERE) return hi.shape == LINE ? sphere_line(lo.c, hi) : sphere_box(lo.c, hi);
+  if (hi.shape == SPHERE) {
+    const HitT<S> r = lo.shape == LINE ? sphere_line(hi.c, lo) : sphere_box(hi.c, lo);
+    HitT<S> o;
+    o.d = r.d;
+    o.n = vneg(r.n);
+    o.plo = r.phi;
+    o.phi = r.plo;
+    return o;
+  }
+  if (lo.shape == LINE && hi.shape == LINE) return line_line(lo, hi);
+  return poly_poly(lo, hi);
+}
+
+// Magnitude of Eq. (2): c k log(1 + e^z), z = (d_min - d)/k, in the stable
+// form max(z, 0) + log(1 + e^{-|z|}); the second term lies in (0, ln 2] and
+// is evaluated with the hardware exp2/log2 (about 1 ulp each), an absolute
+// error of a few 1e-8 against max(z, 0) >= 0.
+template <class S> __device__ __forceinline__ S contact_mag(S dmin, S d, const WorldK& w) {
+  const S z = (dmin - d) * S(w.inv_k);
+  return S(w.ck) * (s_max(z, S(0.0f)) + s_log(S(1.0f) + s_exp(-s_abs(z))));
+}
+
+// Distance and unit normal along (dx, dy) from the squared length sq, with
+// one reciprocal square root; coincident centres push the lower index +x.
+template <class S>
+__device__ __forceinline__ void sphere_normal(S dx, S dy, S sq, bool self_lo, S* d, V2T<S>* n) {
+  if (val(sq) == 0.0f) {
+    *d = S(0.0f);
+    *n = self_lo ? V2T<S>{S(1.0f), S(0.0f)} : V2T<S>{S(-1.0f), S(0.0f)};
+  } else {
+    const S rs = s_rsqrt(sq);
+    *d = sq * rs;
+    *n = {dx * rs, dy * rs};
+  }
+}
+
+// Contact predicate of Eq. (2) between two spheres, decided in FP32 on the
+// squared lengths: fl(dx*dx) + fl(dy*dy) <= fl(d_min * d_min).
+__device__ __forceinline__ bool sphere_contact(float dx, float dy, float dmin, float* sq) {
+  *sq = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
+  return *sq <= __fmul_rn(dmin, dmin);
+}
+
+// Contact of the lane's entity (self, environment-local index a) with the
+// partner in LDS slot q (local index b). Accumulates the lane's force and
+// torque and reports the contact bit.
+template <bool SPH>
+__device__ __forceinline__ bool pair_force(const GeoT<float>& self, float rho_s, int a, const float4 P,
+                                           const float4 S, int b, const WorldK& w, float& fx,
+                                           float& fy, float& tq) {
+  const float rho_o = S.z;
+  const float dmin = (rho_s + rho_o) + w.min_dist;
+  const int so = SPH ? SPHERE : (__float_as_int(S.w) & 0xff);
+  if (SPH || (self.shape == SPHERE && so == SPHERE)) {
+    // Both spheres: x_ij joins the centres; decision on squared lengths.
+    const float dx = self.c.x - P.x, dy = self.c.y - P.y;
+    const float s = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
+    if (!(s <= __fmul_rn(dmin, dmin))) return false;
+    V2T<float> n;
+    float d;
+    sphere_normal(dx, dy, s, a < b, &d, &n);
+    const float F = contact_mag(dmin, d, w);
+    fx = fmaf(F, n.x, fx);
+    fy = fmaf(F, n.y, fy);
+    return true;
+  }
+  GeoT<float> o;
+  o.c = V2T<float>{P.x, P.y};
+  o.cs = P.z;
+  o.sn = P.w;
+  o.d0 = S.x;
+  o.d1 = S.y;
+  o.shape = so;
+  const bool self_lo = a < b;
+  const HitT<float> h = self_lo ? narrow(self, o) : narrow(o, self);
+  if (!(h.d <= dmin)) return false;
+  const float F = contact_mag(dmin, h.d, w);
+  const float sg = self_lo ? F : -F;
+  const V2T<float> f = V2T<float>{sg * h.n.x, sg * h.n.y};
+  const V2T<float> arm = vsub(self_lo ? h.plo : h.phi, self.c);
+  fx += f.x;
+  fy += f.y;
+  tq += vcross(arm, f);
+  return true;
+}
+
+__device__ __forceinline__ bool excluded(int excl, int b) {
+  const unsigned u = (unsigned)excl;
+  return ((u & 0xffu) == (unsigned)b) | (((u >> 8) & 0xffu) == (unsigned)b) |
+         (((u >> 16) & 0xffu) == (unsigned)b) | ((u >> 24) == (unsigned)b);
+}
+
+
+// Joint between entities a and b (Eq. 1 force of a linear spring between the
+// world anchor points P_a = x_a + R_a anchor_a and P_b): f_a = -k (l - rest)
+// (P_a - P_b) / l, f_b = -f_a, torques from the anchor arms. Seen from the
+// lane's entity ("self", which is a when is_a): its force, its torque and the
+// other entity's torque. Returns false when the anchors coincide (no force).
+template <class S>
+__device__ __forceinline__ bool joint_eval(V2T<S> xs, S cs, S sn, V2T<S> xo, S co, S so, bool is_a,
+                                           const JointK& J, float k, V2T<S>* f_self, S* tq_self,
+                                           S* tq_other) {
+  const V2T<S> xa = is_a ? xs : xo, xb = is_a ? xo : xs;
+  const S ca = is_a ? cs : co, sa = is_a ? sn : so;
+  const S cb = is_a ? co : cs, sb = is_a ? so : sn;
+  const V2T<S> Pa = vadd(xa, vrot(ca, sa, V2T<S>{S(J.ax), S(J.ay)}));
+  const V2T<S> Pb = vadd(xb, vrot(cb, sb, V2T<S>{S(J.bx), S(J.by)}));
+  const V2T<S> dl = vsub(Pa, Pb);
+  const S len = s_sqrt(vdot(dl, dl));
+  if (val(len) == 0.0f) return false;
+  const S mag = S(-k) * (len - S(J.rest)) / len;
+  const V2T<S> fa = vscl(dl, mag);
+  const V2T<S> fs = is_a ? fa : vneg(fa);
+  const V2T<S> arm_s = is_a ? vsub(Pa, xa) : vsub(Pb, xb);
+  const V2T<S> arm_o = is_a ? vsub(Pb, xb) : vsub(Pa, xa);
+  *f_self = fs;
+  *tq_self = vcross(arm_s, fs);
+  *tq_other = vcross(arm_o, vneg(fs));
+  return true;
+}
+
+// Derivative form of one contact for the adjoint: the pair (self, other) is
+// known to be in contact (decided by pair_force's FP32 rule); self carries
+// the dual seeds. Outputs the force on self and both torques, with their
+// derivatives with respect to self's (x, y, theta).
+__device__ __forceinline__ void pair_grad(const GeoT<D3>& self, float rho_s, bool self_lo,
+                                          const GeoT<D3>& other, float rho_o, const WorldK& w,
+                                          V2T<D3>* f_self, D3* tq_self, D3* tq_other) {
+  const float dmin = (rho_s + rho_o) + w.min_dist;
+  if (self.shape == SPHERE && other.shape == SPHERE) {
+    const D3 dx = self.c.x - other.c.x, dy = self.c.y - other.c.y;
+    const D3 sq = dx * dx + dy * dy;
+    V2T<D3> n;
+    D3 d;
+    sphere_normal(dx, dy, sq, self_lo, &d, &n);
+    const D3 F = contact_mag(D3(dmin), d, w);
+    *f_self = vscl(n, F);
+    *tq_self = D3(0.0f);
+    *tq_other = D3(0.0f);
+    return;
+  }
+  const HitT<D3> h = self_lo ? narrow(self, other) : narrow(other, self);
+  const D3 F = contact_mag(D3(dmin), h.d, w);
+  const V2T<D3> flo = vscl(h.n, F);
+  const V2T<D3> fs = self_lo ? flo : vneg(flo);
+  *f_self = fs;
+  *tq_self = vcross(vsub(self_lo ? h.plo : h.phi, self.c), fs);
+  *tq_other = vcross(vsub(self_lo ? h.phi : h.plo, other.c), vneg(fs));
+}
+
+}  // namespace vmas

@@ -73,6 +73,7 @@ struct StepArgs {
   const int32_t* jlist;
   const JointK* joints;
   const int64_t* pair_off;   // [n_envs] first mask slot of each environment
+  const int32_t* grp_maxn;   // [groups] size of the largest environment of each group
   int32_t max_stage;         // LDS slots per group
   int32_t pad;
   WorldK w;
@@ -100,11 +101,11 @@ struct BackArgs {
 // Host-side launchers (vmas_kernels.hip).
 hipError_t launch_rollout(const StepArgs& a, int groups, int block, bool spheres_only,
                           hipStream_t s);
-hipError_t launch_backward(const BackArgs& a, int groups, int block, bool spheres_only,
-                           hipStream_t s);
+hipError_t launch_backward(const BackArgs& a, int groups, int block, hipStream_t s);
 // Device function of the rollout kernel launched by launch_rollout (for
-// explicit graph construction); dynamic LDS is max_stage * 48 bytes.
+// explicit graph construction) and its dynamic LDS size.
 const void* rollout_kernel(bool spheres_only, int block);
+size_t rollout_lds_bytes(int max_stage, bool spheres_only);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_replicate(const float* src, float* dst, int64_t n, int copies, hipStream_t s);

@@ -1,0 +1,460 @@
+// Contact-force surrogate: a 12 -> 128 -> 128 -> 2 tanh MLP on pair
+// features, with hand-written forward, backward and Adam kernels for gfx950.
+// Products run on the matrix cores (v_mfma_f32_16x16x16_bf16: BF16 operands,
+// FP32 accumulation); biases, activations, losses and optimiser state are
+// FP32.
+//
+// Fragment layouts of the 16x16x16 BF16 MFMA (wave64): for A (16 x 16,
+// row-major, K contiguous) lane l holds row l % 16, columns 4 (l / 16) .. +3;
+// for B given as B^T (16 x 16, K contiguous) lane l holds column l % 16,
+// k = 4 (l / 16) .. +3; the 16 x 16 FP32 result gives lane l the column
+// l % 16, rows 4 (l / 16) .. +3. Every product below is written as
+// C = A B^T with both operands staged row-major with K contiguous.
+//
+// One workgroup of 4 wavefronts handles 64 rows (pairs), 16 per wavefront.
+// The weight gradient of a workgroup is a partial over its 64 rows; partials
+// are summed over workgroups in a fixed order by a second kernel, so
+// training is deterministic (no float atomics).
+
+#include <hip/hip_runtime.h>
+
+#include "vmas_internal.h"
+
+namespace vmas {
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int NI = 12, NIP = 16, NH = 128, NO = 2, NOP = 16;
+constexpr int ROWS = 64;        // rows per workgroup
+constexpr int LDH = NH + 8;     // padded row stride (bf16) of 128-wide operands
+constexpr int LDI = NIP + 8;    // padded row stride of 16-wide operands
+constexpr int LDR = ROWS + 8;   // padded row stride of transposed (K = rows) operands
+
+// BF16 from FP32, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ unsigned short to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// 4 consecutive bf16 of a row-major operand as one MFMA fragment.
+__device__ __forceinline__ s4 frag(const unsigned short* base, int ld, int row, int k0) {
+  const unsigned short* p = base + row * ld + k0;
+  s4 v;
+  v.x = (short)p[0];
+  v.y = (short)p[1];
+  v.z = (short)p[2];
+  v.w = (short)p[3];
+  return v;
+}
+
+// acc += A[r0 .. r0+15][0 .. K) * Bt[c0 .. c0+15][0 .. K)^T
+__device__ __forceinline__ f4 mma(f4 acc, const unsigned short* A, int lda, int r0,
+                                  const unsigned short* Bt, int ldb, int c0, int K, int lane) {
+  const int r = lane & 15, kq = (lane >> 4) * 4;
+  for (int k = 0; k < K; k += 16) {
+    const s4 a = frag(A, lda, r0 + r, k + kq);
+    const s4 b = frag(Bt, ldb, c0 + r, k + kq);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+struct MlpArgs {
+  const unsigned short* W1;  // [NH][NIP]  bf16, columns >= NI are zero
+  const unsigned short* W2;  // [NH][NH]
+  const unsigned short* W3;  // [NOP][NH], rows >= NO are zero
+  const float* b1;           // [NH]
+  const float* b2;           // [NH]
+  const float* b3;           // [NO]
+};
+
+// Stages the three weight matrices of one network into LDS.
+__device__ void stage_weights(const MlpArgs& m, unsigned short* w1, unsigned short* w2,
+                              unsigned short* w3) {
+  for (int i = threadIdx.x; i < NH * NIP; i += blockDim.x) w1[(i / NIP) * LDI + i % NIP] = m.W1[i];
+  for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) w2[(i / NH) * LDH + i % NH] = m.W2[i];
+  for (int i = threadIdx.x; i < NOP * NH; i += blockDim.x) w3[(i / NH) * LDH + i % NH] = m.W3[i];
+}
+
+// Forward pass of 64 rows. X [n][12] -> Y [n][2]; optionally the FP32
+// activations H1, H2 [n][128] for the backward pass.
+__global__ void __launch_bounds__(256) k_mlp_forward(MlpArgs m, const float* __restrict__ X,
+                                                     int64_t n, float* __restrict__ Y,
+                                                     float* __restrict__ H1, float* __restrict__ H2) {
+  __shared__ unsigned short w1[NH * LDI], w2[NH * LDH], w3[NOP * LDH];
+  __shared__ unsigned short xs[ROWS * LDI], h1s[ROWS * LDH], h2s[ROWS * LDH];
+  stage_weights(m, w1, w2, w3);
+  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+  for (int i = threadIdx.x; i < ROWS * NIP; i += blockDim.x) {
+    const int r = i / NIP, c = i % NIP;
+    const int64_t g = row0 + r;
+    xs[r * LDI + c] = to_bf16((c < NI && g < n) ? X[g * NI + c] : 0.0f);
+  }
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r0 = wv * 16, col = lane & 15, rq = (lane >> 4) * 4;
+  // layer 1: h1 = tanh(x W1^T + b1)
+  for (int j = 0; j < NH / 16; ++j) {
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = mma(acc, xs, LDI, r0, w1, LDI, j * 16, NIP, lane);
+    const int c = j * 16 + col;
+    for (int i = 0; i < 4; ++i) {
+      const float h = tanhf(acc[i] + m.b1[c]);
+      const int r = r0 + rq + i;
+      h1s[r * LDH + c] = to_bf16(h);
+      if (H1 && row0 + r < n) H1[(row0 + r) * NH + c] = h;
+    }
+  }
+  __syncthreads();
+  // layer 2: h2 = tanh(h1 W2^T + b2)
+  for (int j = 0; j < NH / 16; ++j) {
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = mma(acc, h1s, LDH, r0, w2, LDH, j * 16, NH, lane);
+    const int c = j * 16 + col;
+    for (int i = 0; i < 4; ++i) {
+      const float h = tanhf(acc[i] + m.b2[c]);
+      const int r = r0 + rq + i;
+      h2s[r * LDH + c] = to_bf16(h);
+      if (H2 && row0 + r < n) H2[(row0 + r) * NH + c] = h;
+    }
+  }
+  __syncthreads();
+  // layer 3: y = h2 W3^T + b3
+  f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  acc = mma(acc, h2s, LDH, r0, w3, LDH, 0, NH, lane);
+  if (col < NO) {
+    for (int i = 0; i < 4; ++i) {
+      const int64_t g = row0 + r0 + rq + i;
+      if (g < n) Y[g * NO + col] = acc[i] + m.b3[col];
+    }
+  }
+}
+
+// Backward pass of 64 rows given dY [n][2] and the forward activations.
+// Writes dX [n][12] (optional) and this workgroup's partial gradient of all
+// parameters, in the canonical order W1 (128x12), b1, W2 (128x128), b2,
+// W3 (2x128), b3, into part[blockIdx.x][NPARAM].
+constexpr int NPARAM = NH * NI + NH + NH * NH + NH + NO * NH + NO;
+
+__global__ void __launch_bounds__(256) k_mlp_backward(MlpArgs m, const float* __restrict__ X,
+                                                      const float* __restrict__ H1,
+                                                      const float* __restrict__ H2,
+                                                      const float* __restrict__ dY, int64_t n,
+                                                      float* __restrict__ dX,
+                                                      float* __restrict__ part) {
+  // transposed weights: W3^T [NH][NOP], W2^T [NH][NH], W1^T [NIP][NH]
+  __shared__ unsigned short w3t[NH * LDI], w2t[NH * LDH], w1t[NIP * LDH];
+  // per-row operands (row-major, K = features) and their transposes (K = rows)
+  __shared__ unsigned short dys[ROWS * LDI], dz2s[ROWS * LDH], dz1s[ROWS * LDH];
+  __shared__ unsigned short dyT[NOP * LDR], dz2T[NH * LDR], dz1T[NH * LDR];
+  __shared__ unsigned short h1T[NH * LDR], xT[NIP * LDR];
+  __shared__ float bsum[4][NH + NH + NOP];
+  for (int i = threadIdx.x; i < NH * NIP; i += blockDim.x) {
+    const int o = i / NIP, k = i % NIP;
+    w1t[k * LDH + o] = m.W1[i];
+  }
+  for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) {
+    const int o = i / NH, k = i % NH;
+    w2t[k * LDH + o] = m.W2[i];
+  }
+  for (int i = threadIdx.x; i < NOP * NH; i += blockDim.x) {
+    const int o = i / NH, k = i % NH;
+    w3t[k * LDI + o] = m.W3[i];
+  }
+  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+  for (int i = threadIdx.x; i < ROWS * NH; i += blockDim.x) {
+    const int r = i / NH, c = i % NH;
+    const int64_t g = row0 + r;
+    h1T[c * LDR + r] = to_bf16(g < n ? H1[g * NH + c] : 0.0f);
+  }
+  for (int i = threadIdx.x; i < ROWS * NOP; i += blockDim.x) {
+    const int r = i / NOP, c = i % NOP;
+    const int64_t g = row0 + r;
+    const float v = (c < NO && g < n) ? dY[g * NO + c] : 0.0f;
+    dys[r * LDI + c] = to_bf16(v);
+    dyT[c * LDR + r] = to_bf16(v);
+    xT[c * LDR + r] = to_bf16((c < NI && g < n) ? X[g * NI + c] : 0.0f);
+  }
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r0 = wv * 16, col = lane & 15, rq = (lane >> 4) * 4;
+  float* bs = bsum[wv];
+  // dz2 = (dy W3) * (1 - h2^2)
+  for (int j = 0; j < NH / 16; ++j) {
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = mma(acc, dys, LDI, r0, w3t, LDI, j * 16, NOP, lane);
+    const int c = j * 16 + col;
+    float cs = 0.0f;
+    for (int i = 0; i < 4; ++i) {
+      const int r = r0 + rq + i;
+      const int64_t g = row0 + r;
+      const float h = g < n ? H2[g * NH + c] : 0.0f;
+      const float dz = acc[i] * (1.0f - h * h);
+      cs += dz;
+      const unsigned short b = to_bf16(dz);
+      dz2s[r * LDH + c] = b;
+      dz2T[c * LDR + r] = b;
+    }
+    // column sum over the 16 rows of this wavefront (4 lanes share a column)
+    cs += __shfl_xor(cs, 16);
+    cs += __shfl_xor(cs, 32);
+    if (lane < 16) bs[NH + c] = cs;
+  }
+  __syncthreads();
+  // dz1 = (dz2 W2) * (1 - h1^2)
+  for (int j = 0; j < NH / 16; ++j) {
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = mma(acc, dz2s, LDH, r0, w2t, LDH, j * 16, NH, lane);
+    const int c = j * 16 + col;
+    float cs = 0.0f;
+    for (int i = 0; i < 4; ++i) {
+      const int r = r0 + rq + i;
+      const int64_t g = row0 + r;
+      const float h = g < n ? H1[g * NH + c] : 0.0f;
+      const float dz = acc[i] * (1.0f - h * h);
+      cs += dz;
+      const unsigned short b = to_bf16(dz);
+      dz1s[r * LDH + c] = b;
+      dz1T[c * LDR + r] = b;
+    }
+    cs += __shfl_xor(cs, 16);
+    cs += __shfl_xor(cs, 32);
+    if (lane < 16) bs[c] = cs;
+  }
+  // db3: column sums of dy
+  if (lane < NO) {
+    float cs = 0.0f;
+    for (int i = 0; i < 16; ++i) {
+      const int64_t g = row0 + r0 + i;
+      cs += g < n ? dY[g * NO + lane] : 0.0f;
+    }
+    bs[2 * NH + lane] = cs;
+  }
+  __syncthreads();
+  // dX = dz1 W1 (first 12 columns)
+  if (dX) {
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = mma(acc, dz1s, LDH, r0, w1t, LDH, 0, NH, lane);
+    if (col < NI)
+      for (int i = 0; i < 4; ++i) {
+        const int64_t g = row0 + r0 + rq + i;
+        if (g < n) dX[g * NI + col] = acc[i];
+      }
+  }
+  float* P = part + (size_t)blockIdx.x * NPARAM;
+  // dW2 = dz2^T h1 (128 x 128, K = 64 rows): 64 output tiles, 16 per wavefront
+  for (int t = wv; t < 64; t += 4) {
+    const int ti = t / 8, tj = t % 8;
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = mma(acc, dz2T, LDR, ti * 16, h1T, LDR, tj * 16, ROWS, lane);
+    for (int i = 0; i < 4; ++i)
+      P[NH * NI + NH + (ti * 16 + rq + i) * NH + tj * 16 + col] = acc[i];
+  }
+  // dW1 = dz1^T x (128 x 12): 8 tiles, 2 per wavefront
+  for (int t = wv; t < 8; t += 4) {
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = mma(acc, dz1T, LDR, t * 16, xT, LDR, 0, ROWS, lane);
+    if (col < NI)
+      for (int i = 0; i < 4; ++i) P[(t * 16 + rq + i) * NI + col] = acc[i];
+  }
+  // dW3 = dy^T h2 (2 x 128, K = 64 rows) on the vector units, one output per
+  // thread, BF16-rounded operands as in the matrix-core products
+  {
+    const int o = threadIdx.x / NH, k = threadIdx.x % NH;
+    float acc = 0.0f;
+    for (int r = 0; r < ROWS; ++r) {
+      const int64_t g = row0 + r;
+      if (g < n)
+        acc = fmaf(from_bf16(to_bf16(dY[g * NO + o])), from_bf16(to_bf16(H2[g * NH + k])), acc);
+    }
+    P[NH * NI + NH + NH * NH + NH + o * NH + k] = acc;
+  }
+  __syncthreads();
+  // bias partials: wavefront partial sums added in a fixed order
+  for (int c = threadIdx.x; c < NH; c += blockDim.x) {
+    P[NH * NI + c] = ((bsum[0][c] + bsum[1][c]) + bsum[2][c]) + bsum[3][c];
+    P[NH * NI + NH + NH * NH + c] =
+        ((bsum[0][NH + c] + bsum[1][NH + c]) + bsum[2][NH + c]) + bsum[3][NH + c];
+  }
+  if (threadIdx.x < NO) {
+    const int c = threadIdx.x;
+    P[NPARAM - NO + c] =
+        ((bsum[0][2 * NH + c] + bsum[1][2 * NH + c]) + bsum[2][2 * NH + c]) + bsum[3][2 * NH + c];
+  }
+}
+
+// grad[p] = sum over workgroups b (in order) of part[b][p].
+__global__ void k_reduce_parts(const float* __restrict__ part, int nparts, float* __restrict__ grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPARAM) return;
+  float s = 0.0f;
+  for (int b = 0; b < nparts; ++b) s += part[(size_t)b * NPARAM + p];
+  grad[p] = s;
+}
+
+// dY = (Y - target) / n, and the loss sum (Y - target)^2 / (2n) per row.
+__global__ void k_mse_grad(const float* __restrict__ Y, const float* __restrict__ tgt, int64_t n,
+                           float* __restrict__ dY, float* __restrict__ row_loss) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float inv = 1.0f / (float)n;
+  float l = 0.0f;
+  for (int c = 0; c < NO; ++c) {
+    const float e = Y[i * NO + c] - tgt[i * NO + c];
+    dY[i * NO + c] = e * inv;
+    l += e * e;
+  }
+  if (row_loss) row_loss[i] = 0.5f * l * inv;
+}
+
+// Adam on the FP32 master parameters; refreshes the BF16 padded copies.
+__global__ void k_adam(float* __restrict__ master, float* __restrict__ mom, float* __restrict__ var,
+                       const float* __restrict__ grad, float lr, float b1, float b2, float eps,
+                       float c1, float c2, unsigned short* __restrict__ W1,
+                       unsigned short* __restrict__ W2, unsigned short* __restrict__ W3,
+                       float* __restrict__ bias1, float* __restrict__ bias2, float* __restrict__ bias3) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPARAM) return;
+  const float g = grad[p];
+  const float mm = b1 * mom[p] + (1.0f - b1) * g;
+  const float vv = b2 * var[p] + (1.0f - b2) * g * g;
+  mom[p] = mm;
+  var[p] = vv;
+  const float w = master[p] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+  master[p] = w;
+  int q = p;
+  if (q < NH * NI) {
+    W1[(q / NI) * NIP + q % NI] = to_bf16(w);
+    return;
+  }
+  q -= NH * NI;
+  if (q < NH) {
+    bias1[q] = w;
+    return;
+  }
+  q -= NH;
+  if (q < NH * NH) {
+    W2[q] = to_bf16(w);
+    return;
+  }
+  q -= NH * NH;
+  if (q < NH) {
+    bias2[q] = w;
+    return;
+  }
+  q -= NH;
+  if (q < NO * NH) {
+    W3[q] = to_bf16(w);
+    return;
+  }
+  q -= NO * NH;
+  bias3[q] = w;
+}
+
+// Copies FP32 master parameters into the kernel layouts (no update).
+__global__ void k_unpack(const float* __restrict__ master, unsigned short* __restrict__ W1,
+                         unsigned short* __restrict__ W2, unsigned short* __restrict__ W3,
+                         float* __restrict__ bias1, float* __restrict__ bias2,
+                         float* __restrict__ bias3) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPARAM) return;
+  const float w = master[p];
+  int q = p;
+  if (q < NH * NI) { W1[(q / NI) * NIP + q % NI] = to_bf16(w); return; }
+  q -= NH * NI;
+  if (q < NH) { bias1[q] = w; return; }
+  q -= NH;
+  if (q < NH * NH) { W2[q] = to_bf16(w); return; }
+  q -= NH * NH;
+  if (q < NH) { bias2[q] = w; return; }
+  q -= NH;
+  if (q < NO * NH) { W3[q] = to_bf16(w); return; }
+  q -= NO * NH;
+  bias3[q] = w;
+}
+
+// loss[0] = sum of row losses, one workgroup, fixed order.
+__global__ void k_sum(const float* __restrict__ v, int64_t n, float* __restrict__ out) {
+  __shared__ float red[256];
+  float s = 0.0f;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += v[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+}  // namespace
+
+hipError_t mlp_launch_sum(const float* v, int64_t n, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, v, n, out);
+  return hipGetLastError();
+}
+
+int mlp_nparam() { return NPARAM; }
+
+hipError_t mlp_launch_forward(const unsigned short* W1, const unsigned short* W2,
+                              const unsigned short* W3, const float* b1, const float* b2,
+                              const float* b3, const float* X, int64_t n, float* Y, float* H1,
+                              float* H2, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  MlpArgs m{W1, W2, W3, b1, b2, b3};
+  const int64_t blocks = (n + ROWS - 1) / ROWS;
+  hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)blocks), dim3(256), 0, s, m, X, n, Y, H1, H2);
+  return hipGetLastError();
+}
+
+hipError_t mlp_launch_backward(const unsigned short* W1, const unsigned short* W2,
+                               const unsigned short* W3, const float* b1, const float* b2,
+                               const float* b3, const float* X, const float* H1, const float* H2,
+                               const float* dY, int64_t n, float* dX, float* part, float* grad,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  MlpArgs m{W1, W2, W3, b1, b2, b3};
+  const int64_t blocks = (n + ROWS - 1) / ROWS;
+  hipLaunchKernelGGL(k_mlp_backward, dim3((unsigned)blocks), dim3(256), 0, s, m, X, H1, H2, dY, n,
+                     dX, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !grad) return e;
+  hipLaunchKernelGGL(k_reduce_parts, dim3((NPARAM + 255) / 256), dim3(256), 0, s, part,
+                     (int)blocks, grad);
+  return hipGetLastError();
+}
+
+hipError_t mlp_launch_mse(const float* Y, const float* tgt, int64_t n, float* dY, float* row_loss,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mse_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Y, tgt, n, dY,
+                     row_loss);
+  return hipGetLastError();
+}
+
+hipError_t mlp_launch_adam(float* master, float* mom, float* var, const float* grad, float lr,
+                           float b1, float b2, float eps, int step, unsigned short* W1,
+                           unsigned short* W2, unsigned short* W3, float* bias1, float* bias2,
+                           float* bias3, hipStream_t s) {
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, s, master, mom, var, grad,
+                     lr, b1, b2, eps, c1, c2, W1, W2, W3, bias1, bias2, bias3);
+  return hipGetLastError();
+}
+
+hipError_t mlp_launch_unpack(const float* master, unsigned short* W1, unsigned short* W2,
+                             unsigned short* W3, float* bias1, float* bias2, float* bias3,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack, dim3((NPARAM + 255) / 256), dim3(256), 0, s, master, W1, W2, W3,
+                     bias1, bias2, bias3);
+  return hipGetLastError();
+}
+
+int64_t mlp_parts_for(int64_t n) { return (n + ROWS - 1) / ROWS; }
+
+}  // namespace vmas

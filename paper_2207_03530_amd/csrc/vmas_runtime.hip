@@ -20,7 +20,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/vmas.h"
+#include "vmas.h"
 #include "vmas_internal.h"
 
 using namespace vmas;
@@ -50,12 +50,14 @@ struct Plan {
   std::string name;
   int block = 64;
   bool sorted = false;
+  bool all_lanes = false;  // every entity gets a lane (adjoint plans)
   bool valid = false;
   int groups = 0;
   int max_stage = 0;
   LaneRec* d_lanes = nullptr;
   int32_t* d_stage_off = nullptr;
   int32_t* d_stage = nullptr;
+  int32_t* d_maxn = nullptr;  // largest environment of each group
 };
 
 // Restores the caller's current device on scope exit.
@@ -73,6 +75,18 @@ struct DeviceGuard {
 
 }  // namespace
 
+namespace vmas {
+vmas_status set_error(vmas_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+}  // namespace vmas
+
 struct vmas_batch {
   int device = 0;
   int n_envs = 0, N = 0, A = 0, J = 0, max_env = 0;
@@ -86,6 +100,7 @@ struct vmas_batch {
   int64_t* d_pair_off = nullptr;
   std::vector<Plan> plans;
   int cur = 0;
+  Plan back;  // adjoint plan: every entity has a lane
   // checkpoint workspace of the adjoint driver and the autotuner scratch
   float* d_ws = nullptr;
   size_t ws_floats = 0;
@@ -103,6 +118,8 @@ void free_plan(Plan& p) {
   if (p.d_lanes) (void)hipFree(p.d_lanes);
   if (p.d_stage_off) (void)hipFree(p.d_stage_off);
   if (p.d_stage) (void)hipFree(p.d_stage);
+  if (p.d_maxn) (void)hipFree(p.d_maxn);
+  p.d_maxn = nullptr;
   p.d_lanes = nullptr;
   p.d_stage_off = nullptr;
   p.d_stage = nullptr;
@@ -113,6 +130,7 @@ void free_batch(vmas_batch* b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (auto& p : b->plans) free_plan(p);
+  free_plan(b->back);
   if (b->d_ent) (void)hipFree(b->d_ent);
   if (b->d_joff) (void)hipFree(b->d_joff);
   if (b->d_jlist) (void)hipFree(b->d_jlist);
@@ -244,17 +262,21 @@ vmas_status validate(const vmas_world_params* pr, const vmas_batch_desc* d, Host
 
 // Builds one launch plan on the host and uploads it.
 vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8_t>& shape,
-                       const std::vector<uint8_t>& flags, int block, bool sorted, Plan& p) {
+                       const std::vector<uint8_t>& flags, int block, bool sorted, Plan& p,
+                       bool all_lanes = false) {
   p.block = block;
   p.sorted = sorted;
-  p.name = std::string("entity-lane/") + std::to_string(block) + (sorted ? "/size-sorted" : "/natural");
+  p.all_lanes = all_lanes;
+  p.name = std::string(all_lanes ? "adjoint-lane/" : "entity-lane/") + std::to_string(block) +
+           (sorted ? "/size-sorted" : "/natural");
   const int E = b->n_envs;
+  auto has_lane = [&](int i) { return all_lanes || (flags[i] & (MOVABLE | ROTATABLE)) != 0; };
   std::vector<int> active(E, 0);
   for (int e = 0; e < E; ++e)
-    for (int i = h.off[e]; i < h.off[e + 1]; ++i) active[e] += (flags[i] & (MOVABLE | ROTATABLE)) != 0;
+    for (int i = h.off[e]; i < h.off[e + 1]; ++i) active[e] += has_lane(i);
   std::vector<int> order;
   for (int e = 0; e < E; ++e)
-    if (active[e] > 0) order.push_back(e);
+    if (active[e] > 0 && (all_lanes ? h.off[e + 1] > h.off[e] : true)) order.push_back(e);
   if (sorted)
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
       return (h.off[x + 1] - h.off[x]) > (h.off[y + 1] - h.off[y]);
@@ -279,17 +301,18 @@ vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8
   }
   const int G = (int)groups.size();
   std::vector<LaneRec> lane((size_t)std::max(G, 1) * block);
-  std::vector<int32_t> stage_off(G + 1, 0), stage;
+  std::vector<int32_t> stage_off(G + 1, 0), stage, maxn(std::max(G, 1), 0);
   int max_stage = 1;
   for (int g = 0; g < G; ++g) {
     std::vector<LaneRec> recs;
     int slot = 0;
     for (int e : groups[g]) {
       const int lo = slot, n = h.off[e + 1] - h.off[e];
+      maxn[g] = std::max(maxn[g], n);
       const int agent_row = (int)h.agent_off[e];
       for (int i = h.off[e]; i < h.off[e + 1]; ++i, ++slot) {
         stage.push_back(i);
-        if (flags[i] & (MOVABLE | ROTATABLE)) {
+        if (has_lane(i)) {
           LaneRec r;
           r.ent = i;
           r.slot = slot;
@@ -322,6 +345,7 @@ vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8
   if ((s = upload(&p.d_lanes, lane.data(), lane.size())) != VMAS_OK) return s;
   if ((s = upload(&p.d_stage_off, stage_off.data(), stage_off.size())) != VMAS_OK) return s;
   if ((s = upload(&p.d_stage, stage.data(), std::max<size_t>(stage.size(), 1))) != VMAS_OK) return s;
+  if ((s = upload(&p.d_maxn, maxn.data(), maxn.size())) != VMAS_OK) return s;
   p.valid = true;
   return VMAS_OK;
 }
@@ -336,6 +360,7 @@ StepArgs make_args(vmas_batch* b, const Plan& p) {
   a.jlist = b->d_jlist;
   a.joints = b->d_joints;
   a.pair_off = b->d_pair_off;
+  a.grp_maxn = p.d_maxn;
   a.max_stage = p.max_stage;
   a.w = b->w;
   return a;
@@ -539,6 +564,15 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
     return fail(VMAS_ERR_UNSUPPORTED, "an environment is too large to stage in LDS");
   }
   b->cur = first_valid;
+  {
+    int need = 64;
+    for (int e = 0; e < E; ++e)
+      while (need < h.off[e + 1] - h.off[e] && need < 1024) need *= 2;
+    if ((s = build_plan(b, h, shape, flags, std::max(need, 64), false, b->back, true)) != VMAS_OK) {
+      free_batch(b);
+      return s;
+    }
+  }
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_batch(b);
@@ -658,7 +692,7 @@ vmas_status vmas_rollout_graph(vmas_batch* b, float* state, const float* actions
   kp.func = const_cast<void*>(rollout_kernel(b->spheres_only, p.block));
   kp.gridDim = dim3(p.groups);
   kp.blockDim = dim3(p.block);
-  kp.sharedMemBytes = (unsigned)((size_t)p.max_stage * 3 * sizeof(float4));
+  kp.sharedMemBytes = (unsigned)rollout_lds_bytes(p.max_stage, b->spheres_only);
   kp.kernelParams = args;
   kp.extra = nullptr;
   if (!b->gexec || b->graph_T != T || b->graph_plan != b->cur || b->graph_drawn != drawn) {
@@ -736,31 +770,102 @@ vmas_status vmas_autotune(vmas_batch* b, const float* state, int32_t T, void* st
 vmas_status vmas_step_backward(vmas_batch* b, const float* state_t, const float* actions_t,
                                const float* grad_state_next, float* grad_state_t,
                                float* grad_actions_t, void* stream) {
-  (void)state_t;
-  (void)actions_t;
-  (void)grad_state_next;
-  (void)grad_state_t;
-  (void)grad_actions_t;
-  (void)stream;
   g_err.clear();
   if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
-  return fail(VMAS_ERR_UNSUPPORTED, "vmas_step_backward is not built yet");
+  if (!state_t || !grad_state_next || !grad_state_t)
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "state_t, grad_state_next and grad_state_t are required");
+  if (!actions_t && b->A > 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "actions_t must not be NULL");
+  if (grad_state_t == grad_state_next || grad_state_t == state_t)
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "grad_state_t must not alias its inputs");
+  if (!b->back.valid)
+    return fail(VMAS_ERR_UNSUPPORTED, "an environment is too large for the adjoint plan");
+  DeviceGuard guard(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  // Entities without a lane in no group (environments of size 0) keep a zero gradient.
+  BackArgs a{};
+  a.state = state_t;
+  a.actions = actions_t;
+  a.gnext = grad_state_next;
+  a.gstate = grad_state_t;
+  a.gact = grad_actions_t;
+  a.ent = b->d_ent;
+  a.lanes = b->back.d_lanes;
+  a.stage_off = b->back.d_stage_off;
+  a.stage = b->back.d_stage;
+  a.joff = b->d_joff;
+  a.jlist = b->d_jlist;
+  a.joints = b->d_joints;
+  a.max_stage = b->back.max_stage;
+  a.w = b->w;
+  if (b->back.groups == 0) return VMAS_OK;
+  hipError_t e = launch_backward(a, b->back.groups, b->back.block, s);
+  if (e != hipSuccess) return fail(VMAS_ERR_DEVICE, "adjoint launch failed: %s", hipGetErrorString(e));
+  return VMAS_OK;
 }
 
 vmas_status vmas_rollout_backward(vmas_batch* b, const float* state0, const float* actions,
                                   int32_t T, int32_t ckpt_every, const float* grad_state_T,
                                   float* grad_state0, float* grad_actions, void* stream) {
-  (void)state0;
-  (void)actions;
-  (void)T;
-  (void)ckpt_every;
-  (void)grad_state_T;
-  (void)grad_state0;
-  (void)grad_actions;
-  (void)stream;
   g_err.clear();
   if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
-  return fail(VMAS_ERR_UNSUPPORTED, "vmas_rollout_backward is not built yet");
+  if (!state0 || !grad_state_T) return fail(VMAS_ERR_INVALID_ARGUMENT, "state0 and grad_state_T are required");
+  if (T < 1) return fail(VMAS_ERR_INVALID_ARGUMENT, "T must be >= 1");
+  if (ckpt_every < 1) return fail(VMAS_ERR_INVALID_ARGUMENT, "ckpt_every must be >= 1");
+  if (!actions && b->A > 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "actions must not be NULL");
+  DeviceGuard guard(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  const int k = std::min(ckpt_every, T);
+  const int nseg = (T + k - 1) / k;
+  const size_t S6 = 6 * (size_t)b->N;
+  // workspace: nseg checkpoints, k + 1 states of the segment being replayed,
+  // two gradient buffers
+  const size_t need = S6 * ((size_t)nseg + (size_t)k + 1 + 2);
+  if (b->ws_floats < need) {
+    if (b->d_ws) (void)hipFree(b->d_ws);
+    b->d_ws = nullptr;
+    b->ws_floats = 0;
+    hipError_t e = hipMalloc((void**)&b->d_ws, need * sizeof(float));
+    if (e != hipSuccess)
+      return fail(VMAS_ERR_OUT_OF_MEMORY, "checkpoint workspace (%zu bytes): %s", need * sizeof(float),
+                  hipGetErrorString(e));
+    b->ws_floats = need;
+  }
+  float* ckpt = b->d_ws;
+  float* seg = ckpt + S6 * nseg;
+  float* g0 = seg + S6 * (k + 1);
+  float* g1 = g0 + S6;
+  const size_t A2 = 2 * (size_t)b->A;
+  // forward: checkpoints at t = 0, k, 2k, ...
+  HIPCHK(hipMemcpyAsync(ckpt, state0, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  for (int q = 1; q < nseg; ++q) {
+    HIPCHK(hipMemcpyAsync(ckpt + S6 * q, ckpt + S6 * (q - 1), S6 * sizeof(float),
+                          hipMemcpyDeviceToDevice, s));
+    vmas_status st = vmas_rollout(b, ckpt + S6 * q, actions ? actions + A2 * (size_t)(q - 1) * k : nullptr,
+                                  0, 0, k, nullptr, nullptr, stream);
+    if (st != VMAS_OK) return st;
+  }
+  // backward: replay each segment from its checkpoint, then step back through it
+  HIPCHK(hipMemcpyAsync(g0, grad_state_T, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  for (int q = nseg - 1; q >= 0; --q) {
+    const int t0 = q * k, len = std::min(k, T - t0);
+    HIPCHK(hipMemcpyAsync(seg, ckpt + S6 * q, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+    // seg[0 .. len]: states t0 .. t0 + len (the rollout writes them as a trajectory)
+    float* st_tmp = g1;  // scratch for the rolled state, overwritten below
+    HIPCHK(hipMemcpyAsync(st_tmp, seg, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+    vmas_status st = vmas_rollout(b, st_tmp, actions ? actions + A2 * (size_t)t0 : nullptr, 0, 0, len,
+                                  seg, nullptr, stream);
+    if (st != VMAS_OK) return st;
+    for (int t = len - 1; t >= 0; --t) {
+      const float* at = actions ? actions + A2 * (size_t)(t0 + t) : nullptr;
+      float* ga = grad_actions ? grad_actions + A2 * (size_t)(t0 + t) : nullptr;
+      st = vmas_step_backward(b, seg + S6 * t, at, g0, g1, ga, stream);
+      if (st != VMAS_OK) return st;
+      std::swap(g0, g1);
+    }
+  }
+  if (grad_state0)
+    HIPCHK(hipMemcpyAsync(grad_state0, g0, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  return VMAS_OK;
 }
 
 }  // extern "C"

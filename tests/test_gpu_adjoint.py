@@ -1,0 +1,264 @@
+"""GPU checks of the hand-written adjoint (vmas_step_backward,
+vmas_rollout_backward with checkpointing, torch.autograd wrappers).
+
+References, all FP64 and from the oracle: its forward-mode dual-number JVP
+(dot-product test <J^T w, v> = <w, J v>, per environment) and central
+finite differences with eps = 1e-6 of the loss sum |x_T|^2 with respect to
+the actions. Components whose +-eps perturbation flips a contact decision
+anywhere along the rollout (Eq. 2 jumps by c k ln 2 there), and
+environments past their FP64 predictability horizon, are excluded and
+counted.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2207_03530_amd import workloads as W
+from tests import parity as PU
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _batch(w):
+    from paper_2207_03530_amd import binding as B
+    return B.Batch(w, 0)
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, np.float32)).to("cuda:0")
+
+
+def _seg(w):
+    return np.repeat(np.arange(w.n_envs), np.diff(w.env_offset))
+
+
+def _agent_env(w):
+    return np.repeat(np.arange(w.n_envs), w.n_agents)
+
+
+def _per_env_dot(w, a_state, b_state, a_act=None, b_act=None):
+    seg = _seg(w)
+    out = np.zeros(w.n_envs)
+    np.add.at(out, seg, (np.asarray(a_state, np.float64) * b_state).sum(0))
+    if a_act is not None:
+        ae = _agent_env(w)
+        out2 = np.zeros(w.n_envs)
+        np.add.at(out2, ae, (np.asarray(a_act, np.float64) * b_act).sum(2).sum(0)
+                  if a_act.ndim == 3 else (np.asarray(a_act, np.float64) * b_act).sum(1))
+        out += out2
+    return out
+
+
+def _per_env_norm(w, x, act=None):
+    seg = _seg(w)
+    out = np.zeros(w.n_envs)
+    np.add.at(out, seg, (np.asarray(x, np.float64) ** 2).sum(0))
+    if act is not None:
+        ae = _agent_env(w)
+        o2 = np.zeros(w.n_envs)
+        a = np.asarray(act, np.float64)
+        np.add.at(o2, ae, (a ** 2).sum(2).sum(0) if a.ndim == 3 else (a ** 2).sum(1))
+        out += o2
+    return np.sqrt(out)
+
+
+def _tangent_mask(w):
+    """Tangents only where the state is free to move: positions/velocities
+    of movable entities, angles/angular velocities of rotatable ones."""
+    m = np.zeros((6, w.n_entities))
+    mov = (w.flags & W.MOVABLE) != 0
+    rot = (w.flags & W.ROTATABLE) != 0
+    m[0:4, mov] = 1
+    m[4:6, rot & (w.shape != W.SPHERE)] = 1
+    return m
+
+
+def _dot_test(w, T, k, name, tol, min_frac):
+    rng = np.random.default_rng(3)
+    acts = w.actions(T)
+    b = _batch(w)
+    gw = rng.standard_normal((6, w.n_entities)).astype(np.float32) * _tangent_mask(w)
+    vs = (rng.standard_normal((6, w.n_entities)) * _tangent_mask(w)).astype(np.float32)
+    va = rng.standard_normal(acts.shape).astype(np.float32)
+    gs = torch.zeros(6 * w.n_entities, device="cuda:0")
+    ga = torch.zeros(acts.size, device="cuda:0")
+    if T == 1:
+        b.step_backward(_dev(w.state0), _dev(acts[0]), _dev(gw), gs, ga)
+    else:
+        b.rollout_backward(_dev(w.state0), _dev(acts), _dev(gw), k, gs, ga)
+    torch.cuda.synchronize()
+    gs = gs.cpu().numpy().reshape(6, -1)
+    ga = ga.cpu().numpy().reshape(acts.shape)
+    ow = O.OracleWorld(w)
+    _, jv = ow.rollout_jvp(w.state0, vs, acts, va)
+    lhs = _per_env_dot(w, gs, vs, ga, va)          # <J^T w, v>
+    rhs = _per_env_dot(w, gw, jv)                  # <w, J v>
+    scale = _per_env_norm(w, gw) * _per_env_norm(w, jv) + \
+        _per_env_norm(w, gs, ga) * _per_env_norm(w, vs, va)
+    err = np.abs(lhs - rhs) / np.maximum(scale, 1e-30)
+    if T == 1:
+        ok = ~PU.ill_conditioned_step(ow, w.state0, acts[0])
+    else:
+        ok = PU.horizon(ow, w.state0, acts, tol=1e-3) >= T
+    print(f"{name}: dot-test rel err max {err[ok].max() if ok.any() else 0:.3g} "
+          f"(median {np.median(err[ok]) if ok.any() else 0:.3g}) on {ok.sum()}/{w.n_envs} envs")
+    assert ok.mean() >= min_frac
+    assert err[ok].max() <= tol
+    return gs, ga
+
+
+def test_step_adjoint_dot_test_mixed():
+    """One step, 512 mixed-shape environments with joints and a speed cap."""
+    w = W.mixed(512, seed=5)
+    w.max_speed = np.full(w.n_entities, 1.5, np.float32)
+    _dot_test(w, 1, 1, "mixed512 step", tol=1e-4, min_frac=0.9)
+
+
+def test_step_adjoint_dot_test_spread():
+    w = W.spread(256, seed=2)
+    _dot_test(w, 1, 1, "spread256 step", tol=1e-4, min_frac=0.95)
+
+
+def test_rollout_adjoint_dot_test_uneven():
+    """50-step rollout, checkpoints every 10 steps, uneven sphere batches."""
+    w = W.uneven(64, lo=2, hi=12, seed=4)
+    _dot_test(w, 50, 10, "uneven64 T=50", tol=1e-3, min_frac=0.5)
+
+
+def test_rollout_adjoint_dot_test_mixed_short():
+    w = W.mixed(128, n_spheres=6, n_boxes=2, n_lines=3, seed=6)
+    _dot_test(w, 8, 3, "mixed128 T=8", tol=1e-3, min_frac=0.5)
+
+
+def _oracle_masks(ow, s0, acts):
+    s = np.asarray(s0, np.float64)
+    ms = []
+    for t in range(acts.shape[0]):
+        s, m, _ = ow.step(s, acts[t])
+        ms.append(m)
+    return s, np.stack(ms)
+
+
+def test_rollout_gradient_vs_finite_differences():
+    """d/d actions of sum |x_T|^2 through 50 steps (checkpoint every 10)
+    against FP64 central differences, eps = 1e-6, several action components
+    per environment perturbed at once (environments are independent)."""
+    w = W.uneven(96, lo=2, hi=10, seed=8)
+    T, k, eps = 50, 10, 1e-6
+    acts = w.actions(T)
+    b = _batch(w)
+    st = _dev(w.state0)
+    b.rollout(st, _dev(acts))
+    torch.cuda.synchronize()
+    xT = st.cpu().numpy().reshape(6, -1)
+    gT = np.zeros_like(xT)
+    gT[0:2] = 2 * xT[0:2]
+    ga = torch.zeros(acts.size, device="cuda:0")
+    b.rollout_backward(_dev(w.state0), _dev(acts), _dev(gT), k, None, ga)
+    torch.cuda.synchronize()
+    ga = ga.cpu().numpy().reshape(acts.shape)
+    ow = O.OracleWorld(w)
+    _, m0 = _oracle_masks(ow, w.state0, acts)
+    hor = PU.horizon(ow, w.state0, acts, tol=1e-3)
+    ae = _agent_env(w)
+    seg = _seg(w)
+    rng = np.random.default_rng(0)
+    compared = flipped = 0
+    worst = 0.0
+    for rep in range(6):
+        # one (t, agent, comp) per environment
+        t_e = rng.integers(0, T, w.n_envs)
+        comp_e = rng.integers(0, 2, w.n_envs)
+        first = np.concatenate([[0], np.cumsum(w.n_agents)[:-1]])
+        agent_e = first + (rng.random(w.n_envs) * w.n_agents).astype(int)
+        vals = []
+        flips = np.zeros(w.n_envs, bool)
+        for sgn in (+1, -1):
+            a = acts.astype(np.float64).copy()
+            a[t_e, agent_e, comp_e] += sgn * eps
+            sT, ms = _oracle_masks(ow, w.state0, a)
+            L = np.zeros(w.n_envs)
+            np.add.at(L, seg, (sT[0:2] ** 2).sum(0))
+            vals.append(L)
+            penv = PU.pair_env(w.env_offset)
+            diff = (ms != m0).any(0)
+            flips[np.unique(penv[diff])] = True
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        g = ga[t_e, agent_e, comp_e].astype(np.float64)
+        ok = ~flips & (hor >= T)
+        flipped += flips.sum()
+        scale = np.maximum(np.abs(fd), 1e-2)
+        rel = np.abs(g - fd) / scale
+        worst = max(worst, rel[ok].max() if ok.any() else 0.0)
+        compared += ok.sum()
+        assert rel[ok].max() <= 2e-3, (rep, rel[ok].max())
+    print(f"FD check: compared {compared}, excluded for contact flips {flipped}, "
+          f"beyond horizon {(hor < T).sum()} envs, worst rel err {worst:.3g}")
+    assert compared >= 0.5 * 6 * w.n_envs
+
+
+def test_checkpoint_stride_does_not_change_gradients():
+    w = W.mixed(32, n_spheres=6, n_boxes=2, n_lines=3, seed=2)
+    T = 24
+    acts = _dev(w.actions(T))
+    b = _batch(w)
+    gT = _dev(np.random.default_rng(1).standard_normal((6, w.n_entities)))
+    outs = []
+    for k in (1, 5, 24, 100):
+        gs = torch.zeros(6 * w.n_entities, device="cuda:0")
+        ga = torch.zeros(acts.numel(), device="cuda:0")
+        b.rollout_backward(_dev(w.state0), acts, gT, k, gs, ga)
+        torch.cuda.synchronize()
+        outs.append((gs.clone(), ga.clone()))
+    for gs, ga in outs[1:]:
+        assert torch.equal(gs, outs[0][0]) and torch.equal(ga, outs[0][1])
+
+
+def test_rollout_backward_equals_step_chain():
+    """The checkpointed driver equals T explicit vmas_step_backward calls."""
+    w = W.spread(40, seed=3)
+    T = 12
+    acts = w.actions(T)
+    b = _batch(w)
+    gT = np.random.default_rng(2).standard_normal((6, w.n_entities)).astype(np.float32)
+    gs = torch.zeros(6 * w.n_entities, device="cuda:0")
+    ga = torch.zeros(acts.size, device="cuda:0")
+    b.rollout_backward(_dev(w.state0), _dev(acts), _dev(gT), 4, gs, ga)
+    traj = torch.zeros((T + 1) * 6 * w.n_entities, device="cuda:0")
+    s = _dev(w.state0)
+    b.rollout(s, _dev(acts), traj=traj)
+    g = _dev(gT).view(-1).clone()
+    ga2 = torch.zeros(T, w.n_agents_total * 2, device="cuda:0")
+    tr = traj.view(T + 1, -1)
+    for t in range(T - 1, -1, -1):
+        g2 = torch.zeros_like(g)
+        b.step_backward(tr[t].contiguous(), _dev(acts[t]), g, g2, ga2[t])
+        g = g2
+    torch.cuda.synchronize()
+    assert torch.equal(gs, g)
+    assert torch.equal(ga.view(T, -1), ga2)
+
+
+def test_autograd_rollout_matches_direct_call():
+    from paper_2207_03530_amd import autograd as AG
+    w = W.mixed(16, n_spheres=6, n_boxes=2, n_lines=3, seed=9)
+    T = 10
+    b = _batch(w)
+    s0 = _dev(w.state0).requires_grad_(True)
+    a = _dev(w.actions(T)).requires_grad_(True)
+    sT = AG.rollout(b, s0, a, ckpt_every=4)
+    loss = (sT[0:2] ** 2).sum()
+    loss.backward()
+    gT = torch.zeros_like(sT)
+    gT[0:2] = 2 * sT[0:2].detach()
+    gs = torch.zeros(6 * w.n_entities, device="cuda:0")
+    ga = torch.zeros(a.numel(), device="cuda:0")
+    b.rollout_backward(s0.detach(), a.detach(), gT, 4, gs, ga)
+    torch.cuda.synchronize()
+    assert torch.equal(s0.grad.view(-1), gs)
+    assert torch.equal(a.grad.view(-1), ga)
+    s1 = _dev(w.state0).requires_grad_(True)
+    out = AG.step(b, s1, _dev(w.actions(1)[0]))
+    out.sum().backward()
+    assert s1.grad is not None and torch.isfinite(s1.grad).all()
