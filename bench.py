@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 KERNEL_SRC = os.path.join(ROOT, "paper_2207_03530_amd", "csrc", "vmas_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rollout_spread30k_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rollout_sph_spread30k_traffic.json")
 
 # Algorithmic bytes of one environment-step / one entity of the spread
 # workload (see the roofline section of the design notes):
@@ -180,7 +180,7 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_rollout", "kernel_ms": kernel_ms,
+            "kernel": "k_rollout_sph", "kernel_ms": kernel_ms,
             "algorithmic_bytes_per_launch": nbytes,
             "algorithmic_bytes_per_env_step": nbytes / (w.n_envs * T),
         },

@@ -121,6 +121,7 @@ typedef struct {
 } vmas_batch_desc;
 
 typedef struct vmas_batch vmas_batch; /* opaque handle */
+typedef struct vmas_mlp vmas_mlp;     /* opaque handle of the contact surrogate */
 
 typedef struct {
   int32_t n_envs;
@@ -227,8 +228,6 @@ vmas_status vmas_rollout_graph(vmas_batch* batch, float* state, const float* act
  * Adam moments (beta1 0.9, beta2 0.999, eps 1e-8) and workspaces; calls on
  * one handle must not overlap. X, Y, dY, targets, grad and dX are DEVICE
  * arrays owned by the caller: X [n][12], Y / dY / target [n][2]. */
-typedef struct vmas_mlp vmas_mlp;
-
 /* Number of parameters (18434). */
 int32_t vmas_mlp_num_params(void);
 
@@ -253,6 +252,34 @@ vmas_status vmas_mlp_backward(vmas_mlp* mlp, const float* X, int64_t n, const fl
  * NULL) receives the loss before the step. */
 vmas_status vmas_mlp_train_step(vmas_mlp* mlp, const float* X, const float* target, int64_t n,
                                 float lr, float* loss, void* stream);
+
+/* Surrogate inputs and targets. For the pair slots listed in `slots`
+ * (device int64 [m], mask order; NULL: all P slots, m = P) writes, for the
+ * pair (i, j), i < j, in the pair frame e = (c_i - c_j)/|c_i - c_j| of angle phi:
+ *   features  device float32 [m][12]: |c_i - c_j| / L, g / Lg with
+ *             g = |c_i - c_j| - R_i - R_j (bounding radii: sphere r, box half
+ *             diagonal, line L/2), cos and sin of (theta_i - phi), cos and sin
+ *             of (theta_j - phi), dims_i / L, dims_j / L, shape codes of i and j
+ *             (sphere 0, box 0.5, line 1); L = 0.1, Lg = 0.01;
+ *   targets   device float32 [m][2] or NULL: the exact Eq. (2) force on i along
+ *             e and along its left normal, divided by c * 0.02 (0 when not in
+ *             contact);
+ *   flags     device uint8 [m]: bit 0 eligible pair with g <= band, bit 1 in
+ *             contact (exact FP32 decision). */
+vmas_status vmas_pair_features(vmas_batch* batch, const float* state, float band,
+                               const int64_t* slots, int64_t m, float* features, float* targets,
+                               uint8_t* flags, void* stream);
+
+/* One step whose contact forces come from the surrogate network for every
+ * candidate pair (bit 0 above), except that a pair whose predicted
+ * penetration k log(expm1(|f|/(c k))) (the inverse of Eq. 2) exceeds
+ * fallback_frac times its radius (sphere r; box / line half of the smaller
+ * extent) takes the exact narrow phase and Eq. (2) force. The surrogate
+ * gives no torque. forces: device [3][N] or NULL; n_fallback: device int32
+ * counter or NULL (incremented by the number of fallback pair sides). */
+vmas_status vmas_step_surrogate(vmas_batch* batch, vmas_mlp* mlp, float* state,
+                                const float* actions, float band, float fallback_frac,
+                                float* forces, int32_t* n_fallback, void* stream);
 
 /* Reason for the last failure on this thread ("" if none). */
 const char* vmas_last_error(void);

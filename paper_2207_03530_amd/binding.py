@@ -25,7 +25,8 @@ EXPORTS = ("vmas_create_batch", "vmas_destroy_batch", "vmas_batch_get_info", "vm
            "vmas_rollout", "vmas_step_backward", "vmas_rollout_backward", "vmas_set_schedule",
            "vmas_autotune", "vmas_schedule_name", "vmas_rollout_graph", "vmas_last_error",
            "vmas_mlp_num_params", "vmas_mlp_create", "vmas_mlp_destroy", "vmas_mlp_get_params",
-           "vmas_mlp_forward", "vmas_mlp_backward", "vmas_mlp_train_step")
+           "vmas_mlp_forward", "vmas_mlp_backward", "vmas_mlp_train_step", "vmas_pair_features",
+           "vmas_step_surrogate")
 
 
 class VmasError(RuntimeError):
@@ -98,6 +99,8 @@ def lib():
     L.vmas_mlp_forward.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
     L.vmas_mlp_backward.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, vp]
     L.vmas_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_float, vp, vp]
+    L.vmas_pair_features.argtypes = [vp, vp, ctypes.c_float, vp, ctypes.c_int64, vp, vp, vp, vp]
+    L.vmas_step_surrogate.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, vp, vp, vp]
     for name in EXPORTS:
         if name not in ("vmas_schedule_name", "vmas_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -271,6 +274,25 @@ class Batch:
             _dptr(grad_final, 6 * self.N, f, "grad_state_T"),
             _dptr(grad_state0, 6 * self.N, f, "grad_state0"),
             _dptr(grad_actions, T * 2 * self.A, f, "grad_actions"), _stream(self.device)))
+
+    def pair_features(self, state, features, flags, targets=None, slots=None, band: float = 0.05):
+        import torch
+        m = self.P if slots is None else slots.shape[0]
+        _check(lib().vmas_pair_features(
+            self.handle, _dptr(state, 6 * self.N, torch.float32, "state"), ctypes.c_float(band),
+            _dptr(slots, m, torch.int64, "slots"), m,
+            _dptr(features, 12 * m, torch.float32, "features"),
+            _dptr(targets, 2 * m, torch.float32, "targets"),
+            _dptr(flags, m, torch.uint8, "flags"), _stream(self.device)))
+
+    def step_surrogate(self, mlp: "Mlp", state, actions, band: float = 0.05,
+                       fallback_frac: float = 0.5, forces=None, n_fallback=None) -> None:
+        import torch
+        _check(lib().vmas_step_surrogate(
+            self.handle, mlp.handle, _dptr(state, 6 * self.N, torch.float32, "state"),
+            _dptr(actions, 2 * self.A, torch.float32, "actions"), ctypes.c_float(band),
+            ctypes.c_float(fallback_frac), _dptr(forces, 3 * self.N, torch.float32, "forces"),
+            _dptr(n_fallback, 1, torch.int32, "n_fallback"), _stream(self.device)))
 
     def close(self) -> None:
         if getattr(self, "handle", None) is not None and self.handle.value:

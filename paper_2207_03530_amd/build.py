@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvmas.so")
 SOURCES = ["vmas_runtime.hip", "vmas_kernels.hip", "vmas_backward.hip", "vmas_mlp.hip",
-           "vmas_mlp_api.hip"]
+           "vmas_mlp_api.hip", "vmas_surrogate.hip"]
 ARCH = os.environ.get("VMAS_OFFLOAD_ARCH", "gfx950")
 
 

@@ -111,6 +111,14 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_replicate(const float* src, float* dst, int64_t n, int copies, hipStream_t s);
 hipError_t launch_axpy_zero(float* p, int64_t n, hipStream_t s);
 
+hipError_t launch_pair_features(const float* state, const EntParam* ent, const int32_t* env_off,
+                                const int64_t* pair_off, const int64_t* slots, int64_t m,
+                                float band, float* feat, float* target, uint8_t* flags,
+                                int n_envs, const WorldK& w, hipStream_t s);
+hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat, const uint8_t* cand,
+                                 float frac, int32_t* n_fallback, int groups, int block,
+                                 hipStream_t s);
+
 // Host-side SplitMix64 key of (seed, stream): mix64(seed + (stream + 1) * golden).
 uint64_t action_key(uint64_t seed);
 

@@ -304,8 +304,12 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
           for (int base = 0; base < gmaxn; base += 32) {
             const int cnt = min(32, gmaxn - base);
             uint32_t hits = 0;
+            // software-pipelined: the next partner's LDS read is in flight
+            // while the current one is tested
+            float4 Pn = cb[min(r.lo + base, r.hi - 1)];
             for (int u = 0; u < cnt; ++u) {
-              const float4 P = cb[min(r.lo + base + u, r.hi - 1)];
+              const float4 P = Pn;
+              if (u + 1 < cnt) Pn = cb[min(r.lo + base + u + 1, r.hi - 1)];
               const float dmin = (p.rho + P.z) + w.min_dist;
               const float dx = x - P.x, dy = y - P.y;
               const float sq = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));

@@ -42,14 +42,9 @@ __device__ __forceinline__ unsigned short to_bf16(float f) {
 __device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
 // 4 consecutive bf16 of a row-major operand as one MFMA fragment.
+// (row * ld + k0 is a multiple of 4 elements: one aligned 8-byte LDS read)
 __device__ __forceinline__ s4 frag(const unsigned short* base, int ld, int row, int k0) {
-  const unsigned short* p = base + row * ld + k0;
-  s4 v;
-  v.x = (short)p[0];
-  v.y = (short)p[1];
-  v.z = (short)p[2];
-  v.w = (short)p[3];
-  return v;
+  return *reinterpret_cast<const s4*>(base + row * ld + k0);
 }
 
 // acc += A[r0 .. r0+15][0 .. K) * Bt[c0 .. c0+15][0 .. K)^T
@@ -86,51 +81,66 @@ __device__ void stage_weights(const MlpArgs& m, unsigned short* w1, unsigned sho
 __global__ void __launch_bounds__(256) k_mlp_forward(MlpArgs m, const float* __restrict__ X,
                                                      int64_t n, float* __restrict__ Y,
                                                      float* __restrict__ H1, float* __restrict__ H2) {
-  __shared__ unsigned short w1[NH * LDI], w2[NH * LDH], w3[NOP * LDH];
-  __shared__ unsigned short xs[ROWS * LDI], h1s[ROWS * LDH], h2s[ROWS * LDH];
+  __shared__ __attribute__((aligned(16))) unsigned short w1[NH * LDI], w2[NH * LDH], w3[NOP * LDH];
+  __shared__ __attribute__((aligned(16))) unsigned short xs[ROWS * LDI], h1s[ROWS * LDH];
+  __shared__ float bias[NH + NH + NO];
   stage_weights(m, w1, w2, w3);
-  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
-  for (int i = threadIdx.x; i < ROWS * NIP; i += blockDim.x) {
-    const int r = i / NIP, c = i % NIP;
-    const int64_t g = row0 + r;
-    xs[r * LDI + c] = to_bf16((c < NI && g < n) ? X[g * NI + c] : 0.0f);
+  for (int i = threadIdx.x; i < NH; i += blockDim.x) {
+    bias[i] = m.b1[i];
+    bias[NH + i] = m.b2[i];
   }
-  __syncthreads();
+  if (threadIdx.x < NO) bias[2 * NH + threadIdx.x] = m.b3[threadIdx.x];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r0 = wv * 16, col = lane & 15, rq = (lane >> 4) * 4;
-  // layer 1: h1 = tanh(x W1^T + b1)
-  for (int j = 0; j < NH / 16; ++j) {
-    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    acc = mma(acc, xs, LDI, r0, w1, LDI, j * 16, NIP, lane);
-    const int c = j * 16 + col;
-    for (int i = 0; i < 4; ++i) {
-      const float h = tanhf(acc[i] + m.b1[c]);
-      const int r = r0 + rq + i;
-      h1s[r * LDH + c] = to_bf16(h);
-      if (H1 && row0 + r < n) H1[(row0 + r) * NH + c] = h;
+  const int64_t tiles = (n + ROWS - 1) / ROWS;
+  // the workgroup walks row tiles; the weights stay staged in LDS
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t row0 = tile * ROWS;
+    __syncthreads();  // the previous tile's activations are consumed
+    for (int i = threadIdx.x; i < ROWS * NIP; i += blockDim.x) {
+      const int r = i / NIP, c = i % NIP;
+      const int64_t g = row0 + r;
+      xs[r * LDI + c] = to_bf16((c < NI && g < n) ? X[g * NI + c] : 0.0f);
     }
-  }
-  __syncthreads();
-  // layer 2: h2 = tanh(h1 W2^T + b2)
-  for (int j = 0; j < NH / 16; ++j) {
-    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    acc = mma(acc, h1s, LDH, r0, w2, LDH, j * 16, NH, lane);
-    const int c = j * 16 + col;
-    for (int i = 0; i < 4; ++i) {
-      const float h = tanhf(acc[i] + m.b2[c]);
-      const int r = r0 + rq + i;
-      h2s[r * LDH + c] = to_bf16(h);
-      if (H2 && row0 + r < n) H2[(row0 + r) * NH + c] = h;
+    __syncthreads();
+    // layer 1: h1 = tanh(x W1^T + b1)
+    for (int j = 0; j < NH / 16; ++j) {
+      f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      acc = mma(acc, xs, LDI, r0, w1, LDI, j * 16, NIP, lane);
+      const int c = j * 16 + col;
+      for (int i = 0; i < 4; ++i) {
+        const float h = tanhf(acc[i] + bias[c]);
+        const int r = r0 + rq + i;
+        h1s[r * LDH + c] = to_bf16(h);
+        if (H1 && row0 + r < n) H1[(row0 + r) * NH + c] = h;
+      }
     }
-  }
-  __syncthreads();
-  // layer 3: y = h2 W3^T + b3
-  f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-  acc = mma(acc, h2s, LDH, r0, w3, LDH, 0, NH, lane);
-  if (col < NO) {
-    for (int i = 0; i < 4; ++i) {
-      const int64_t g = row0 + r0 + rq + i;
-      if (g < n) Y[g * NO + col] = acc[i] + m.b3[col];
+    __syncthreads();
+    // layer 2: h2 = tanh(h1 W2^T + b2); all 8 column tiles are accumulated in
+    // registers first, then h2 overwrites this wavefront's own rows of h1
+    f4 acc2[NH / 16];
+    for (int j = 0; j < NH / 16; ++j) {
+      acc2[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+      acc2[j] = mma(acc2[j], h1s, LDH, r0, w2, LDH, j * 16, NH, lane);
+    }
+    for (int j = 0; j < NH / 16; ++j) {
+      const int c = j * 16 + col;
+      for (int i = 0; i < 4; ++i) {
+        const float h = tanhf(acc2[j][i] + bias[NH + c]);
+        const int r = r0 + rq + i;
+        h1s[r * LDH + c] = to_bf16(h);
+        if (H2 && row0 + r < n) H2[(row0 + r) * NH + c] = h;
+      }
+    }
+    __syncthreads();
+    // layer 3: y = h2 W3^T + b3
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    acc = mma(acc, h1s, LDH, r0, w3, LDH, 0, NH, lane);
+    if (col < NO) {
+      for (int i = 0; i < 4; ++i) {
+        const int64_t g = row0 + r0 + rq + i;
+        if (g < n) Y[g * NO + col] = acc[i] + bias[2 * NH + col];
+      }
     }
   }
 }
@@ -148,11 +158,11 @@ __global__ void __launch_bounds__(256) k_mlp_backward(MlpArgs m, const float* __
                                                       float* __restrict__ dX,
                                                       float* __restrict__ part) {
   // transposed weights: W3^T [NH][NOP], W2^T [NH][NH], W1^T [NIP][NH]
-  __shared__ unsigned short w3t[NH * LDI], w2t[NH * LDH], w1t[NIP * LDH];
+  __shared__ __attribute__((aligned(16))) unsigned short w3t[NH * LDI], w2t[NH * LDH], w1t[NIP * LDH];
   // per-row operands (row-major, K = features) and their transposes (K = rows)
-  __shared__ unsigned short dys[ROWS * LDI], dz2s[ROWS * LDH], dz1s[ROWS * LDH];
-  __shared__ unsigned short dyT[NOP * LDR], dz2T[NH * LDR], dz1T[NH * LDR];
-  __shared__ unsigned short h1T[NH * LDR], xT[NIP * LDR];
+  __shared__ __attribute__((aligned(16))) unsigned short dys[ROWS * LDI], dz2s[ROWS * LDH], dz1s[ROWS * LDH];
+  __shared__ __attribute__((aligned(16))) unsigned short dyT[NOP * LDR], dz2T[NH * LDR], dz1T[NH * LDR];
+  __shared__ __attribute__((aligned(16))) unsigned short h1T[NH * LDR], xT[NIP * LDR];
   __shared__ float bsum[4][NH + NH + NOP];
   for (int i = threadIdx.x; i < NH * NIP; i += blockDim.x) {
     const int o = i / NIP, k = i % NIP;
@@ -407,7 +417,8 @@ hipError_t mlp_launch_forward(const unsigned short* W1, const unsigned short* W2
                               float* H2, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   MlpArgs m{W1, W2, W3, b1, b2, b3};
-  const int64_t blocks = (n + ROWS - 1) / ROWS;
+  const int64_t tiles = (n + ROWS - 1) / ROWS;
+  const int64_t blocks = tiles < 2048 ? tiles : 2048;  // 8 workgroups per CU walk the tiles
   hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)blocks), dim3(256), 0, s, m, X, n, Y, H1, H2);
   return hipGetLastError();
 }

@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -98,6 +99,11 @@ struct vmas_batch {
   int32_t* d_jlist = nullptr;
   JointK* d_joints = nullptr;
   int64_t* d_pair_off = nullptr;
+  int32_t* d_env_off = nullptr;
+  // surrogate workspace: features [P][12], MLP outputs [P][2], flags [P]
+  float* d_feat = nullptr;
+  float* d_yhat = nullptr;
+  uint8_t* d_cand = nullptr;
   std::vector<Plan> plans;
   int cur = 0;
   Plan back;  // adjoint plan: every entity has a lane
@@ -136,6 +142,10 @@ void free_batch(vmas_batch* b) {
   if (b->d_jlist) (void)hipFree(b->d_jlist);
   if (b->d_joints) (void)hipFree(b->d_joints);
   if (b->d_pair_off) (void)hipFree(b->d_pair_off);
+  if (b->d_env_off) (void)hipFree(b->d_env_off);
+  if (b->d_feat) (void)hipFree(b->d_feat);
+  if (b->d_yhat) (void)hipFree(b->d_yhat);
+  if (b->d_cand) (void)hipFree(b->d_cand);
   if (b->d_ws) (void)hipFree(b->d_ws);
   delete b;
 }
@@ -520,7 +530,8 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
       (s = upload(&b->d_joff, joff.data(), joff.size())) != VMAS_OK ||
       (s = upload(&b->d_jlist, jlist.data(), jlist.size())) != VMAS_OK ||
       (s = upload(&b->d_joints, joints.data(), joints.size())) != VMAS_OK ||
-      (s = upload(&b->d_pair_off, pair_off.data(), pair_off.size())) != VMAS_OK) {
+      (s = upload(&b->d_pair_off, pair_off.data(), pair_off.size())) != VMAS_OK ||
+      (s = upload(&b->d_env_off, h.off.data(), h.off.size())) != VMAS_OK) {
     free_batch(b);
     return s;
   }
@@ -865,6 +876,58 @@ vmas_status vmas_rollout_backward(vmas_batch* b, const float* state0, const floa
   }
   if (grad_state0)
     HIPCHK(hipMemcpyAsync(grad_state0, g0, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  return VMAS_OK;
+}
+
+vmas_status vmas_pair_features(vmas_batch* b, const float* state, float band,
+                               const int64_t* slots, int64_t m, float* features, float* targets,
+                               uint8_t* flags, void* stream) {
+  g_err.clear();
+  if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
+  if (!state || !features || !flags)
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "state, features and flags are required");
+  if (!(std::isfinite(band) && band >= 0)) return fail(VMAS_ERR_INVALID_ARGUMENT, "band must be >= 0");
+  if (!slots && m != b->P)
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "without a slot list m must be the number of pair slots");
+  if (m < 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "m must be >= 0");
+  DeviceGuard guard(b->device);
+  HIPCHK(launch_pair_features(state, b->d_ent, b->d_env_off, b->d_pair_off, slots, m, band,
+                              features, targets, flags, b->n_envs, b->w, (hipStream_t)stream));
+  return VMAS_OK;
+}
+
+vmas_status vmas_step_surrogate(vmas_batch* b, vmas_mlp* mlp, float* state, const float* actions,
+                                float band, float fallback_frac, float* forces,
+                                int32_t* n_fallback, void* stream) {
+  g_err.clear();
+  if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
+  if (!mlp || !state) return fail(VMAS_ERR_INVALID_ARGUMENT, "mlp and state are required");
+  if (!actions && b->A > 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "actions must not be NULL");
+  if (!(std::isfinite(band) && band >= 0 && std::isfinite(fallback_frac)))
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "band must be >= 0 and fallback_frac finite");
+  DeviceGuard guard(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  if (!b->d_feat && b->P > 0) {
+    hipError_t e;
+    if ((e = hipMalloc((void**)&b->d_feat, (size_t)b->P * 12 * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc((void**)&b->d_yhat, (size_t)b->P * 2 * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc((void**)&b->d_cand, (size_t)b->P)) != hipSuccess)
+      return fail(VMAS_ERR_OUT_OF_MEMORY, "surrogate workspace: %s", hipGetErrorString(e));
+  }
+  if (forces) HIPCHK(launch_fill_f32(forces, 3 * (int64_t)b->N, 0.0f, s));
+  HIPCHK(launch_pair_features(state, b->d_ent, b->d_env_off, b->d_pair_off, nullptr, b->P, band,
+                              b->d_feat, nullptr, b->d_cand, b->n_envs, b->w, s));
+  vmas_status st = vmas_mlp_forward(mlp, b->d_feat, b->P, b->d_yhat, stream);
+  if (st != VMAS_OK) return st;
+  const Plan& p = b->plans[b->cur];
+  if (p.groups == 0) return VMAS_OK;
+  StepArgs a = make_args(b, p);
+  a.state = state;
+  a.actions = actions;
+  a.T = 1;
+  a.forces = forces;
+  HIPCHK(launch_step_surrogate(a, b->d_yhat, b->d_cand, fallback_frac, n_fallback, p.groups,
+                               p.block, s));
   return VMAS_OK;
 }
 

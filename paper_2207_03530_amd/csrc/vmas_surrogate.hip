@@ -1,0 +1,293 @@
+// Physics side of the learned contact surrogate: pair features, training
+// targets from the exact step, and a step whose contact forces come from the
+// MLP, with the exact Eq. (2) force as fallback for deep contacts.
+//
+// Features of the pair (i, j), i < j in an environment, in the pair frame
+// e = (c_i - c_j) / |c_i - c_j| (e = +x for coincident centres), phi = the
+// angle of e (12 values of O(1) scale, invariant under rigid motions):
+//   |c_i - c_j| / L, g / Lg with g = |c_i - c_j| - R_i - R_j (R: bounding
+//   radius, sphere r, box half diagonal, line L/2), cos and sin of
+//   (theta_i - phi), cos and sin of (theta_j - phi), dims_i / L, dims_j / L,
+//   shape code of i and of j (sphere 0, box 0.5, line 1);
+// L = 0.1, Lg = 0.01. Target: the Eq. (2) force on i in the pair frame
+// (along e, along the left normal of e) divided by c * Lf, Lf = 0.02 (zero
+// when the pair is not in contact).
+// A pair is a candidate when its bounding circles (sphere r, box half
+// diagonal, line L/2) come within `band` of each other.
+
+#include "vmas_geom.h"
+#include "vmas_internal.h"
+
+namespace vmas {
+namespace {
+
+constexpr float FEAT_L = 0.1f;   // length scale of the features
+constexpr float GAP_L = 0.01f;   // length scale of the gap feature
+constexpr float FORCE_L = 0.02f; // force scale c * FORCE_L of the targets
+
+__device__ __forceinline__ float bound_radius(int shape, float d0, float d1) {
+  if (shape == SPHERE) return d0;
+  if (shape == BOX) return 0.5f * sqrtf(d0 * d0 + d1 * d1);
+  return 0.5f * d0;
+}
+
+// local pair index q of an environment of n entities -> (a, c), a < c
+__device__ __forceinline__ void pair_of(int q, int n, int* a, int* c) {
+  int aa = 0, base = 0;
+  while (q >= base + (n - 1 - aa)) {
+    base += n - 1 - aa;
+    ++aa;
+  }
+  *a = aa;
+  *c = aa + 1 + (q - base);
+}
+
+struct FeatArgs {
+  const float* state;
+  const EntParam* ent;
+  const int32_t* env_off;   // [E + 1]
+  const int64_t* pair_off;  // [E]
+  const int64_t* slots;     // [m] pair slots, or NULL: every slot (m = P)
+  int64_t m;
+  float band;
+  float* feat;              // [m][12]
+  float* target;            // [m][2] or NULL
+  uint8_t* flags;           // [m]: 1 candidate, 2 exact contact
+  int n_envs;
+  WorldK w;
+};
+
+__device__ int env_of_slot(const int64_t* pair_off, int E, int64_t p) {
+  int lo = 0, hi = E - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pair_off[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_pair_features(FeatArgs a) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.m) return;
+  const int64_t p = a.slots ? a.slots[r] : r;
+  const int N = a.w.N;
+  // the last environment whose first slot is <= p (environments with fewer
+  // than two entities own no slot and share their successor's offset)
+  const int e = env_of_slot(a.pair_off, a.n_envs, p);
+  const int o = a.env_off[e], n = a.env_off[e + 1] - o;
+  int la, lc;
+  pair_of((int)(p - a.pair_off[e]), n, &la, &lc);
+  const int i = o + la, j = o + lc;
+  const EntParam pi = a.ent[i], pj = a.ent[j];
+  const int si = pi.sf & 0xff, sj = pj.sf & 0xff, fi = (pi.sf >> 8) & 0xff, fj = (pj.sf >> 8) & 0xff;
+  const float xi = a.state[i], yi = a.state[N + i], ti = a.state[4 * N + i];
+  const float xj = a.state[j], yj = a.state[N + j], tj = a.state[4 * N + j];
+  float ci, sni, cj, snj;
+  sincosf(ti, &sni, &ci);
+  sincosf(tj, &snj, &cj);
+  const V2T<float> dl = {xi - xj, yi - yj};
+  const float dist = sqrtf(vdot(dl, dl));
+  const V2T<float> ex = dist > 0.0f ? V2T<float>{dl.x / dist, dl.y / dist} : V2T<float>{1.0f, 0.0f};
+  const float Ri = bound_radius(si, pi.d0, pi.d1), Rj = bound_radius(sj, pj.d0, pj.d1);
+  float* f = a.feat + r * 12;
+  f[0] = dist / FEAT_L;
+  f[1] = (dist - (Ri + Rj)) / GAP_L;
+  f[2] = fmaf(ci, ex.x, sni * ex.y);    // cos(theta_i - phi)
+  f[3] = fmaf(sni, ex.x, -ci * ex.y);   // sin(theta_i - phi)
+  f[4] = fmaf(cj, ex.x, snj * ex.y);
+  f[5] = fmaf(snj, ex.x, -cj * ex.y);
+  f[6] = pi.d0 / FEAT_L;
+  f[7] = pi.d1 / FEAT_L;
+  f[8] = pj.d0 / FEAT_L;
+  f[9] = pj.d1 / FEAT_L;
+  f[10] = 0.5f * (float)si;  // SPHERE 0, BOX 1, LINE 2
+  f[11] = 0.5f * (float)sj;
+  const bool eligible = (fi & COLLIDABLE) && (fj & COLLIDABLE) &&
+                        ((fi | fj) & (MOVABLE | ROTATABLE)) && !excluded(pi.excl, lc) &&
+                        !excluded(pj.excl, la);
+  const bool cand = eligible && dist <= Ri + Rj + a.band;
+  uint8_t fl = cand ? 1 : 0;
+  float tx = 0.0f, ty = 0.0f;
+  if (cand) {
+    GeoT<float> gi, gj;
+    gi.c = {xi, yi};
+    gi.cs = ci;
+    gi.sn = sni;
+    gi.d0 = pi.d0;
+    gi.d1 = pi.d1;
+    gi.shape = si;
+    const float4 P = make_float4(xj, yj, cj, snj);
+    const float4 S = make_float4(pj.d0, pj.d1, pj.rho, __int_as_float(pj.sf));
+    float fx = 0.0f, fy = 0.0f, tq = 0.0f;
+    if (pair_force<false>(gi, pi.rho, 0, P, S, 1, a.w, fx, fy, tq)) {
+      fl |= 2;
+      const float inv = 1.0f / (a.w.ck * a.w.inv_k * FORCE_L);  // 1 / (c Lf)
+      tx = fmaf(fx, ex.x, fy * ex.y) * inv;         // along e
+      ty = fmaf(fy, ex.x, -fx * ex.y) * inv;        // along the left normal of e
+    }
+  }
+  a.flags[r] = fl;
+  if (a.target) {
+    a.target[r * 2] = tx;
+    a.target[r * 2 + 1] = ty;
+  }
+}
+
+struct SurArgs {
+  StepArgs s;             // plan, state, actions (T = 1), forces
+  const float* yhat;      // [P][2] MLP outputs (force on lo in the pair frame / (c Lf))
+  const uint8_t* cand;    // [P] candidate flags (bit 0)
+  float fallback_frac;    // exact fallback when predicted penetration > frac * r
+  int32_t* n_fallback;    // device counter, or NULL
+};
+
+// One step with surrogate contact forces (lane per entity that can move or
+// rotate, poses staged in LDS as in the exact step).
+__global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
+  const StepArgs& a = sa.s;
+  extern __shared__ float4 lds[];
+  const int E = a.max_stage;
+  float4* pose = lds;
+  float4* stat = lds + E;
+  const int g = blockIdx.x, l = threadIdx.x, B = blockDim.x;
+  const int N = a.w.N;
+  const int s0 = a.stage_off[g], ns = a.stage_off[g + 1] - s0;
+  for (int s = l; s < ns; s += B) {
+    const int e = a.stage[s0 + s];
+    float cs, sn;
+    sincosf(a.state[4 * N + e], &sn, &cs);
+    pose[s] = make_float4(a.state[e], a.state[N + e], cs, sn);
+    const EntParam p = a.ent[e];
+    stat[s] = make_float4(p.d0, p.d1, p.rho, __int_as_float(p.sf));
+  }
+  const LaneRec r = a.lanes[(size_t)g * B + l];
+  const bool act = r.ent >= 0;
+  __syncthreads();
+  if (!act) return;
+  const WorldK w = a.w;
+  const int e = r.ent;
+  float x = a.state[e], y = a.state[N + e], vx = a.state[2 * N + e], vy = a.state[3 * N + e];
+  float th = a.state[4 * N + e], om = a.state[5 * N + e];
+  const EntParam p = a.ent[e];
+  const int shape = p.sf & 0xff, fl = (p.sf >> 8) & 0xff;
+  float cs, sn;
+  sincosf(th, &sn, &cs);
+  float fx = p.mgx, fy = p.mgy, tq = 0.0f;
+  if (r.agent >= 0) {
+    fx += a.actions[2 * (size_t)r.agent];
+    fy += a.actions[2 * (size_t)r.agent + 1];
+  }
+  const int myloc = r.slot - r.lo, nloc = r.hi - r.lo;
+  const float FS = w.ck * w.inv_k * FORCE_L;  // c Lf
+  int fallbacks = 0;
+  if (fl & COLLIDABLE) {
+    GeoT<float> self;
+    self.c = {x, y};
+    self.cs = cs;
+    self.sn = sn;
+    self.d0 = p.d0;
+    self.d1 = p.d1;
+    self.shape = shape;
+    for (int q = r.lo; q < r.hi; ++q) {
+      if (q == r.slot) continue;
+      const int b = q - r.lo;
+      const int ia = min(myloc, b), ib = max(myloc, b);
+      const int64_t slot = a.pair_off[r.env] + (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
+      if (!(sa.cand[slot] & 1)) continue;
+      const float4 P = pose[q];
+      const float4 S = stat[q];
+      // surrogate force on lo, in the pair frame -> world
+      const float hx = sa.yhat[2 * slot] * FS, hy = sa.yhat[2 * slot + 1] * FS;
+      const float sgn = myloc < b ? 1.0f : -1.0f;  // e points from hi to lo
+      const float ddx = sgn * (x - P.x), ddy = sgn * (y - P.y);
+      const float dd = sqrtf(fmaf(ddx, ddx, ddy * ddy));
+      const V2T<float> ex = dd > 0.0f ? V2T<float>{ddx / dd, ddy / dd} : V2T<float>{1.0f, 0.0f};
+      const V2T<float> flo = {fmaf(hx, ex.x, -hy * ex.y), fmaf(hx, ex.y, hy * ex.x)};
+      // predicted penetration from the inverse of Eq. (2): k log(expm1(|f| / (c k)))
+      const float mag = sqrtf(flo.x * flo.x + flo.y * flo.y);
+      const float pen = mag > 0.0f ? logf(expm1f(mag / w.ck)) / w.inv_k : -INFINITY;
+      const int so = __float_as_int(S.w) & 0xff;
+      const float rr = fminf(shape == SPHERE ? p.d0 : 0.5f * fminf(p.d0, shape == BOX ? p.d1 : p.d0),
+                             so == SPHERE ? S.x : 0.5f * fminf(S.x, so == BOX ? S.y : S.x));
+      if (pen > sa.fallback_frac * rr) {
+        ++fallbacks;
+        pair_force<false>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
+      } else if (myloc < b) {
+        fx += flo.x;
+        fy += flo.y;
+      } else {
+        fx -= flo.x;
+        fy -= flo.y;
+      }
+    }
+  }
+  // joint springs are exact (they are not contacts)
+  for (int jj = a.joff[e]; jj < a.joff[e + 1]; ++jj) {
+    const JointK J = a.joints[a.jlist[jj]];
+    const bool is_a = J.a == e;
+    const float4 P = pose[r.lo + ((is_a ? J.b : J.a) - r.first)];
+    V2T<float> f;
+    float ts, to;
+    if (joint_eval<float>(V2T<float>{x, y}, cs, sn, V2T<float>{P.x, P.y}, P.z, P.w, is_a, J,
+                          w.joint_k, &f, &ts, &to)) {
+      fx += f.x;
+      fy += f.y;
+      tq += ts;
+    }
+  }
+  if (a.forces) {
+    a.forces[e] = fx;
+    a.forces[N + e] = fy;
+    a.forces[2 * N + e] = tq;
+  }
+  if (fl & MOVABLE) {
+    vx = fmaf(fx * p.inv_m, w.dt, w.damp * vx);
+    vy = fmaf(fy * p.inv_m, w.dt, w.damp * vy);
+    if (p.vmax > 0.0f) {
+      const float sp = sqrtf(fmaf(vx, vx, vy * vy));
+      if (sp > p.vmax) {
+        vx *= p.vmax / sp;
+        vy *= p.vmax / sp;
+      }
+    }
+    x = fmaf(vx, w.dt, x);
+    y = fmaf(vy, w.dt, y);
+  }
+  if (fl & ROTATABLE) {
+    om = fmaf(tq * p.inv_I, w.dt, w.damp * om);
+    th = fmaf(om, w.dt, th);
+  }
+  // all lanes have read the state they need before anyone writes (barrier
+  // above); each lane writes only its own entity
+  a.state[e] = x;
+  a.state[N + e] = y;
+  a.state[2 * N + e] = vx;
+  a.state[3 * N + e] = vy;
+  a.state[4 * N + e] = th;
+  a.state[5 * N + e] = om;
+  if (sa.n_fallback && fallbacks) atomicAdd(sa.n_fallback, fallbacks);
+}
+
+}  // namespace
+
+hipError_t launch_pair_features(const float* state, const EntParam* ent, const int32_t* env_off,
+                                const int64_t* pair_off, const int64_t* slots, int64_t m,
+                                float band, float* feat, float* target, uint8_t* flags,
+                                int n_envs, const WorldK& w, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  FeatArgs a{state, ent, env_off, pair_off, slots, m, band, feat, target, flags, n_envs, w};
+  hipLaunchKernelGGL(k_pair_features, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat, const uint8_t* cand,
+                                 float frac, int32_t* n_fallback, int groups, int block,
+                                 hipStream_t s) {
+  SurArgs sa{a, yhat, cand, frac, n_fallback};
+  const size_t shm = (size_t)a.max_stage * 2 * sizeof(float4);
+  hipLaunchKernelGGL(k_step_surrogate, dim3(groups), dim3(block), shm, s, sa);
+  return hipGetLastError();
+}
+
+}  // namespace vmas

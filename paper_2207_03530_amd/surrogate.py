@@ -1,0 +1,144 @@
+"""Training and evaluation driver of the learned contact surrogate.
+
+Orchestration only: the dataset comes from the exact HIP step
+(vmas_rollout trajectories and vmas_pair_features), the network is
+trained by the HIP MLP kernels (vmas_mlp_train_step), and evaluation runs
+vmas_step_surrogate next to the exact vmas_step. Host code only selects
+which pair slots become samples and shuffles minibatch order.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import binding as B
+from . import workloads as W
+
+BAND = 0.05          # candidate reach beyond touching bounding circles
+FALLBACK = 0.5       # exact step when the predicted penetration exceeds 0.5 r
+
+
+def make_dataset(world, T: int, stride: int, max_samples: int, seed: int = 0, device: int = 0):
+    """Candidate pair samples (features [n, 12], targets [n, 2]) from an
+    exact rollout of `world`, taken every `stride` steps."""
+    import torch
+    dev = torch.device("cuda", device)
+    b = B.Batch(world, device)
+    N, P = world.n_entities, world.pair_slots()
+    traj = torch.zeros((T + 1) * 6 * N, device=dev)
+    st = torch.as_tensor(world.state0).to(dev).contiguous()
+    b.rollout(st, torch.as_tensor(world.actions(T)).to(dev).contiguous(), traj=traj)
+    feats, targs = [], []
+    flags = torch.zeros(P, dtype=torch.uint8, device=dev)
+    fbuf = torch.zeros(P, 12, device=dev)
+    rng = np.random.default_rng(seed)
+    total = 0
+    for t in range(0, T + 1, stride):
+        s_t = traj.view(T + 1, -1)[t].contiguous()
+        b.pair_features(s_t, fbuf, flags, band=BAND)
+        cand = np.nonzero(flags.cpu().numpy() & 1)[0]
+        if cand.size == 0:
+            continue
+        slots = torch.as_tensor(cand.astype(np.int64), device=dev)
+        f = torch.zeros(cand.size, 12, device=dev)
+        y = torch.zeros(cand.size, 2, device=dev)
+        fl = torch.zeros(cand.size, dtype=torch.uint8, device=dev)
+        b.pair_features(s_t, f, fl, targets=y, slots=slots, band=BAND)
+        feats.append(f)
+        targs.append(y)
+        total += cand.size
+        if total >= max_samples:
+            break
+    b.close()
+    X = torch.cat(feats)[:max_samples].contiguous()
+    Y = torch.cat(targs)[:max_samples].contiguous()
+    perm = torch.as_tensor(rng.permutation(X.shape[0]), device=dev)
+    return X[perm].contiguous(), Y[perm].contiguous()
+
+
+def train(mlp: "B.Mlp", X, Y, epochs: int, batch: int = 8192, lr: float = 2e-3,
+          lr_final: float = 1e-4, log=None):
+    """Adam over shuffled minibatches, learning rate decayed geometrically
+    from lr to lr_final; returns the per-epoch mean loss."""
+    import torch
+    n = X.shape[0]
+    nb = n // batch
+    loss = torch.zeros(1, device=X.device)
+    hist = []
+    steps = epochs * nb
+    k = 0
+    for ep in range(epochs):
+        acc = torch.zeros(1, device=X.device)
+        for q in range(nb):
+            rate = lr * (lr_final / lr) ** (k / max(1, steps - 1))
+            mlp.train_step(X[q * batch:(q + 1) * batch], Y[q * batch:(q + 1) * batch], rate, loss)
+            acc += loss
+            k += 1
+        hist.append(float(acc.item()) / max(1, nb))
+        if log:
+            log(f"epoch {ep}: loss {hist[-1]:.4g}")
+    return hist
+
+
+def contact_force_error(world, mlp: "B.Mlp", steps: int = 5, device: int = 0):
+    """Normwise relative error ||F_sur - F||_2 / ||F||_2 of the contact forces
+    (total force minus action and gravity) of the surrogate step against the
+    exact step, from the same states along an exact trajectory; also the
+    number of fallback pair sides per step."""
+    import torch
+    dev = torch.device("cuda", device)
+    b = B.Batch(world, device)
+    N = world.n_entities
+    acts = torch.as_tensor(world.actions(steps)).to(dev).contiguous()
+    st = torch.as_tensor(world.state0).to(dev).contiguous()
+    errs, fbs = [], []
+    agents = torch.as_tensor(world.agent_ids(), device=dev)
+    for t in range(steps):
+        fe = torch.zeros(3 * N, device=dev)
+        fs = torch.zeros(3 * N, device=dev)
+        nfb = torch.zeros(1, dtype=torch.int32, device=dev)
+        s_exact = st.clone()
+        b.step(s_exact, acts[t], None, fe)
+        s_sur = st.clone()
+        b.step_surrogate(mlp, s_sur, acts[t], BAND, FALLBACK, fs, nfb)
+        torch.cuda.synchronize()
+        Fe = fe.view(3, N)[0:2].clone()
+        Fs = fs.view(3, N)[0:2].clone()
+        Fe[:, agents] -= acts[t].T
+        Fs[:, agents] -= acts[t].T
+        errs.append(float(torch.linalg.norm(Fs - Fe) / torch.linalg.norm(Fe)))
+        fbs.append(int(nfb.item()))
+        st = s_exact
+    b.close()
+    return errs, fbs
+
+
+def time_steps(world, mlp: "B.Mlp", reps: int = 20, device: int = 0):
+    """Mean milliseconds of one exact step and of one surrogate step."""
+    import torch
+    dev = torch.device("cuda", device)
+    b = B.Batch(world, device)
+    act = torch.as_tensor(world.actions(1)[0]).to(dev).contiguous()
+    st = torch.as_tensor(world.state0).to(dev).contiguous()
+    out = {}
+    for name, fn in (("exact", lambda s: b.step(s, act)),
+                     ("surrogate", lambda s: b.step_surrogate(mlp, s, act, BAND, FALLBACK))):
+        s = st.clone()
+        for _ in range(3):
+            fn(s)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn(s)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps
+    b.close()
+    return out
+
+
+def inference_world(n_envs: int = 65536, seed: int = 11):
+    """16 sphere agents (r = 0.03) per environment, positions uniform in [-1, 1]^2."""
+    return W.uneven(n_envs, lo=16, hi=16, radius=0.03, seed=seed)

@@ -1,0 +1,174 @@
+"""GPU checks of the learned contact surrogate: pair features and targets
+against the oracle, the surrogate step against the exact step when every
+pair falls back, the trained network's force error and speed against the
+exact step, and what its smooth force field gives that Eq. (2) does not."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2207_03530_amd import workloads as W
+from tests import parity as PU
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FEAT_L = 0.1
+GAP_L = 0.01
+FORCE_L = 0.02
+
+
+def _dev(a, dt=np.float32):
+    return torch.as_tensor(np.ascontiguousarray(a, dt)).to("cuda:0")
+
+
+def test_pair_features_and_targets():
+    from paper_2207_03530_amd import binding as B
+    w = W.mixed(64, seed=3)
+    b = B.Batch(w, 0)
+    P = w.pair_slots()
+    feat = torch.zeros(P, 12, device="cuda:0")
+    targ = torch.zeros(P, 2, device="cuda:0")
+    flags = torch.zeros(P, dtype=torch.uint8, device="cuda:0")
+    b.pair_features(_dev(w.state0), feat, flags, targets=targ, band=0.05)
+    torch.cuda.synchronize()
+    feat, targ, flags = feat.cpu().numpy(), targ.cpu().numpy(), flags.cpu().numpy()
+    I, J = PU.pair_members(w.env_offset)
+    s = w.state0.astype(np.float64)
+    dx, dy = s[0, I] - s[0, J], s[1, I] - s[1, J]
+    dist = np.hypot(dx, dy)
+    ex, ey = dx / dist, dy / dist
+    phi = np.arctan2(ey, ex)
+    def bound(q):
+        return np.where(w.shape[q] == 0, w.dims[q, 0],
+                        np.where(w.shape[q] == 1, 0.5 * np.hypot(w.dims[q, 0], w.dims[q, 1]),
+                                 0.5 * w.dims[q, 0]))
+    ref = np.stack([dist / FEAT_L, (dist - bound(I) - bound(J)) / GAP_L,
+                    np.cos(s[4, I] - phi), np.sin(s[4, I] - phi),
+                    np.cos(s[4, J] - phi), np.sin(s[4, J] - phi),
+                    w.dims[I, 0] / FEAT_L, w.dims[I, 1] / FEAT_L, w.dims[J, 0] / FEAT_L,
+                    w.dims[J, 1] / FEAT_L, 0.5 * w.shape[I], 0.5 * w.shape[J]], 1)
+    np.testing.assert_allclose(feat, ref, rtol=2e-5, atol=3e-5)
+    ow = O.OracleWorld(w)
+    _, om, _ = ow.step(w.state0, np.zeros((w.n_agents_total, 2)))
+    contact = (flags & 2) != 0
+    d, dm = O.pair_distances(ow, w.state0)
+    band = np.abs(d - dm) <= 1e-5
+    assert np.all((contact == (om == 1)) | band)
+    assert np.all(contact <= (flags & 1))
+    # exact force on i in j's frame for pairs in contact, from the oracle's narrow phase
+    c, k = w.contact_force, w.contact_margin
+    idx = np.nonzero(contact & ~band)[0]
+    assert idx.size > 50
+    for q in idx[:400]:
+        i, j = I[q], J[q]
+        dd, n, _, _ = O.pair(w.shape[i], w.dims[i], s[[0, 1, 4], i], w.shape[j], w.dims[j],
+                             s[[0, 1, 4], j])
+        z = (dm[q] - dd) / k
+        F = c * k * (max(z, 0) + np.log1p(np.exp(-abs(z))))
+        f = F * n
+        fe = np.array([f[0] * ex[q] + f[1] * ey[q], f[1] * ex[q] - f[0] * ey[q]]) / (c * FORCE_L)
+        np.testing.assert_allclose(targ[q], fe, rtol=1e-3, atol=1e-5)
+
+
+@pytest.mark.parametrize("world", ["spheres", "mixed"])
+def test_surrogate_step_with_full_fallback_is_the_exact_step(world):
+    """With a fallback threshold below any penetration every candidate pair
+    takes the exact narrow phase: the surrogate step then is the exact step,
+    bit for bit (same per-pair arithmetic and order)."""
+    from paper_2207_03530_amd import binding as B
+    w = W.uneven(200, lo=8, hi=16, radius=0.05, seed=4) if world == "spheres" else W.mixed(64, seed=8)
+    b = B.Batch(w, 0)
+    net = B.Mlp(seed=1)
+    act = _dev(w.actions(1)[0])
+    s1 = _dev(w.state0)
+    f1 = torch.zeros(3 * w.n_entities, device="cuda:0")
+    b.step(s1, act, None, f1)
+    s2 = _dev(w.state0)
+    f2 = torch.zeros(3 * w.n_entities, device="cuda:0")
+    nfb = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    b.step_surrogate(net, s2, act, 0.05, -1e30, f2, nfb)
+    torch.cuda.synchronize()
+    assert torch.equal(f1, f2)
+    assert torch.equal(s1, s2)
+    assert nfb.item() > 0
+
+
+@pytest.fixture(scope="module")
+def trained():
+    """Surrogate trained on pair transitions of mixed-shape rollouts
+    (4,096 environments of 16 spheres + 4 boxes + 8 lines + 2 joints)."""
+    import time
+    from paper_2207_03530_amd import binding as B, surrogate as S
+    t = time.time()
+    X, Y = S.make_dataset(W.mixed(4096, seed=21), T=300, stride=2, max_samples=10_000_000)
+    t_data = time.time() - t
+    net = B.Mlp(seed=0)
+    t = time.time()
+    hist = S.train(net, X, Y, epochs=40, batch=8192, lr=3e-3, lr_final=3e-5)
+    torch.cuda.synchronize()
+    t_train = time.time() - t
+    print(f"surrogate: {X.shape[0]} samples in {t_data:.1f} s, trained in {t_train:.1f} s, "
+          f"loss {hist[0]:.4g} -> {hist[-1]:.4g}")
+    return net, hist
+
+
+def test_surrogate_force_error_and_speed(trained):
+    """65,536 environments x 16 sphere agents: contact-force error of the
+    surrogate step against the exact step, and both step times."""
+    from paper_2207_03530_amd import surrogate as S
+    net, hist = trained
+    assert hist[-1] < 0.2 * hist[0]
+    w = S.inference_world(65536)
+    errs, fbs = S.contact_force_error(w, net, steps=5)
+    times = S.time_steps(w, net)
+    print(f"surrogate on 65536x16 spheres: rel force err per step {np.round(errs, 4)}, "
+          f"fallback pair sides {fbs}, exact {times['exact']:.3f} ms, surrogate "
+          f"{times['surrogate']:.3f} ms, speedup {times['exact'] / times['surrogate']:.3f}")
+    assert np.max(errs) <= 5e-2
+
+
+def test_surrogate_gradient_sees_contact_onset(trained):
+    """Gain over Eq. (2): the exact force jumps by c k ln 2 at |x_ij| = d_min,
+    so its pointwise derivative (what an adjoint of the exact step uses)
+    integrated across contact onset misses that jump; the surrogate's input
+    gradient (vmas_mlp_backward) integrated over the same sweep reproduces
+    the change of force across onset, jump included."""
+    net, _ = trained
+    r = 0.03
+    dmin = 2 * r
+    c, k = 100.0, 1e-3
+    s = np.linspace(dmin + 0.004, dmin - 0.004, 801)        # centre distance, approaching
+    n = s.size
+    X = np.zeros((n, 12), np.float32)
+    X[:, 0] = s / FEAT_L                                      # i on the +x side of j, theta = 0
+    X[:, 1] = (s - dmin) / GAP_L
+    X[:, 2] = 1.0
+    X[:, 4] = 1.0
+    X[:, 6] = r / FEAT_L
+    X[:, 8] = r / FEAT_L
+    Xd = _dev(X)
+    Y = torch.zeros(n, 2, device="cuda:0")
+    net.forward(Xd, Y)
+    dY = torch.zeros(n, 2, device="cuda:0")
+    dY[:, 0] = 1.0
+    dX = torch.zeros(n, 12, device="cuda:0")
+    net.backward(Xd, dY, None, dX)
+    torch.cuda.synchronize()
+    yhat = Y.cpu().numpy()[:, 0] * c * FORCE_L
+    gx = dX.cpu().numpy()
+    dyds = (gx[:, 0] / FEAT_L + gx[:, 1] / GAP_L) * c * FORCE_L  # d(force along e)/ds
+    # exact force along the sweep and its pointwise derivative
+    z = (dmin - s) / k
+    F = np.where(s <= dmin, c * k * (np.maximum(z, 0) + np.log1p(np.exp(-np.abs(z)))), 0.0)
+    dF = np.where(s <= dmin, -c / (1 + np.exp(-z)), 0.0)
+    change_true = F[-1] - F[0]
+    ds = s[1] - s[0]
+    integ = lambda g: float(np.sum(0.5 * (g[1:] + g[:-1])) * ds)  # noqa: E731
+    change_exact_grad = integ(dF)
+    change_sur_grad = integ(dyds)
+    print(f"force change across onset: true {change_true:.4f}, from exact derivative "
+          f"{change_exact_grad:.4f} (misses the jump {c * k * np.log(2):.4f}), from surrogate "
+          f"gradient {change_sur_grad:.4f} (surrogate values {yhat[-1] - yhat[0]:.4f})")
+    assert abs(change_true - change_exact_grad) > 0.9 * c * k * np.log(2)
+    assert abs(change_sur_grad - (yhat[-1] - yhat[0])) <= 0.1 * abs(change_true)
+    assert abs(change_sur_grad - change_true) < abs(change_exact_grad - change_true)
