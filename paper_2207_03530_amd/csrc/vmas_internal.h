@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "vmas.h"
+
 namespace vmas {
 
 enum : int { SPHERE = 0, BOX = 1, LINE = 2 };
@@ -75,9 +77,16 @@ struct StepArgs {
   const int64_t* pair_off;   // [n_envs] first mask slot of each environment
   const int32_t* grp_maxn;   // [groups] size of the largest environment of each group
   int32_t max_stage;         // LDS slots per group
-  int32_t pad;
+  int32_t max_n;             // size of the largest environment of the plan
   WorldK w;
 };
+
+// Workgroup barrier for LDS traffic only: waits for this wavefront's LDS
+// operations, then meets the other wavefronts. Unlike __syncthreads() it does
+// not wait for outstanding global loads (prefetched actions stay in flight).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 
 // Arguments of the adjoint kernel (one step backwards).
 struct BackArgs {
@@ -104,10 +113,11 @@ hipError_t launch_rollout(const StepArgs& a, int groups, int block, bool spheres
 hipError_t launch_backward(const BackArgs& a, int groups, int block, hipStream_t s);
 // Device function of the rollout kernel launched by launch_rollout (for
 // explicit graph construction) and its dynamic LDS size.
-const void* rollout_kernel(bool spheres_only, int block);
-size_t rollout_lds_bytes(int max_stage, bool spheres_only);
+const void* rollout_kernel(bool spheres_only, int block, int max_n, float min_dist);
+size_t rollout_lds_bytes(int max_stage, bool spheres_only, int block, int max_n);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_replicate(const float* src, float* dst, int64_t n, int copies, hipStream_t s);
 hipError_t launch_axpy_zero(float* p, int64_t n, hipStream_t s);
 
@@ -115,7 +125,13 @@ hipError_t launch_pair_features(const float* state, const EntParam* ent, const i
                                 const int64_t* pair_off, const int64_t* slots, int64_t m,
                                 float band, float* feat, float* target, uint8_t* flags,
                                 int n_envs, const WorldK& w, hipStream_t s);
-hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat, const uint8_t* cand,
+vmas_status mlp_forward_counted(vmas_mlp* m, const float* X, int64_t max_n, const int32_t* d_n,
+                                float* Y, hipStream_t s);
+hipError_t launch_candidate_features(const float* state, const EntParam* ent,
+                                     const int32_t* env_off, const int64_t* pair_off, int64_t P,
+                                     float band, float* feat, int32_t* row_of, int32_t* count,
+                                     int n_envs, const WorldK& w, hipStream_t s);
+hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat, const int32_t* row_of,
                                  float frac, int32_t* n_fallback, int groups, int block,
                                  hipStream_t s);
 

@@ -208,31 +208,47 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
 }
 
 // Sphere-only batches (every collidable or moving entity is a sphere): the
-// pair force acts along the line of centres and never makes a torque, so a
-// partner needs only (x, y, radius, flags) -- one 16-byte LDS read. The
-// actions of KCH steps are loaded per chunk into registers one chunk ahead,
-// which hides the HBM latency behind KCH steps of work; the chunk loop is
-// unrolled so every action register is addressed statically. The arithmetic
-// is the same, operation for operation, as the sphere path of k_rollout.
+// pair force acts along the line of centres and never makes a torque, so the
+// per-step LDS exchange is the centre (x, y) alone; radius and flags are
+// staged once. The actions of KCH steps are loaded per chunk into registers
+// one chunk ahead, which hides the HBM latency behind KCH steps of work (the
+// per-step barrier waits for LDS traffic only, so the loads stay in flight);
+// the chunk loop is unrolled so every action register is addressed
+// statically.
+//
+// NB > 0: every environment of the plan has at most NB entities. A lane's
+// partner slots are fixed for the whole rollout, so the squared contact
+// distance of each slot, fl((r_i + r_j [+ d_min])^2), is computed once into
+// registers, -1 for slots that must never report contact (the lane itself,
+// slots past its environment, which read neighbours or padding). The
+// per-step test of slot u is then the FP32 rule
+// fl(dx^2) + fl(dy^2) <= dmin2[u]. NB = 0: any size, one partner at a time. MD: the world has a nonzero minimum distance. The
+// arithmetic of a contact is the same, operation for operation, in every
+// variant and as the sphere path of k_rollout.
 constexpr int KCH = 8;
-constexpr int PB = 8;  // partners whose LDS reads are issued together
 
-template <int MAXB>
+template <int MAXB, int NB, bool MD>
 __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
-  extern __shared__ float4 lds[];
-  const int E = a.max_stage;
-  float4* buf0 = lds;
-  float4* buf1 = lds + E;
+  extern __shared__ float2 lds2[];
+  const int E = a.max_stage + NB;  // slots per array, padding included
+  float2* pos0 = lds2;
+  float2* pos1 = lds2 + E;
+  float2* stat = lds2 + 2 * E;     // (radius or NaN if not collidable, flags)
   const int g = blockIdx.x, l = threadIdx.x, B = blockDim.x;
   const int N = a.w.N;
   const int s0 = a.stage_off[g], ns = a.stage_off[g + 1] - s0;
-  for (int s = l; s < ns; s += B) {
-    const int e = a.stage[s0 + s];
-    const int sf = a.ent[e].sf;
-    const float rho = ((sf >> 8) & COLLIDABLE) ? a.ent[e].rho : __int_as_float(0x7fc00000);
-    const float4 P = make_float4(a.state[e], a.state[N + e], rho, __int_as_float(sf));
-    buf0[s] = P;
-    buf1[s] = P;
+  const float qnan = __int_as_float(0x7fc00000);
+  for (int s = l; s < ns + NB; s += B) {
+    float2 P = make_float2(0.0f, 0.0f), S = make_float2(qnan, 0.0f);  // padding
+    if (s < ns) {
+      const int e = a.stage[s0 + s];
+      const int sf = a.ent[e].sf;
+      P = make_float2(a.state[e], a.state[N + e]);
+      S = make_float2(((sf >> 8) & COLLIDABLE) ? a.ent[e].rho : qnan, __int_as_float(sf));
+    }
+    pos0[s] = P;
+    pos1[s] = P;
+    stat[s] = S;
   }
   const LaneRec r = a.lanes[(size_t)g * B + l];
   const bool act = r.ent >= 0;
@@ -252,25 +268,25 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
   const bool movable = act && (fl & MOVABLE) != 0, rotatable = act && (fl & ROTATABLE) != 0;
   const bool collide = act && (fl & COLLIDABLE) != 0;
   const bool agent = act && r.agent >= 0;
-  const float sfbits = __int_as_float(p.sf);
-  const float rho_lds = (fl & COLLIDABLE) ? p.rho : __int_as_float(0x7fc00000);
   const int myloc = r.slot - r.lo, nloc = r.hi - r.lo;
   const int gmaxn = a.grp_maxn[g];
   const WorldK w = a.w;
   const int T = a.T;
   const size_t A = (size_t)w.A;
-  const float2* ap = agent && a.actions
-                         ? reinterpret_cast<const float2*>(a.actions) + r.agent
-                         : nullptr;
+  const bool drawn = a.actions == nullptr;  // uniform
+  const float2* ap = reinterpret_cast<const float2*>(a.actions) + (agent ? r.agent : 0);
   float2 cur[KCH], nxt[KCH];
   auto load_chunk = [&](float2* dst, int c) {
 #pragma unroll
-    for (int k = 0; k < KCH; ++k) {
-      dst[k] = make_float2(0.0f, 0.0f);
-      if (agent && c + k < T) {
-        if (ap) {
-          dst[k] = ap[(size_t)(c + k) * A];
-        } else {
+    for (int k = 0; k < KCH; ++k) dst[k] = make_float2(0.0f, 0.0f);
+    if (!drawn) {
+#pragma unroll
+      for (int k = 0; k < KCH; ++k)
+        if (agent && c + k < T) dst[k] = ap[(size_t)(c + k) * A];
+    } else {
+#pragma unroll
+      for (int k = 0; k < KCH; ++k) {
+        if (agent && c + k < T) {
           const uint64_t base = ((uint64_t)(a.t0 + c + k) * (uint64_t)w.A + (uint64_t)r.agent) * 2ull;
           dst[k] = make_float2(draw_sym(a.key, base), draw_sym(a.key, base + 1));
         }
@@ -279,67 +295,89 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
   };
   load_chunk(cur, 0);
   __syncthreads();
+  // squared contact distance of each partner slot (-1: never in contact)
+  float dm2[NB > 0 ? NB : 1];
+#pragma unroll
+  for (int u = 0; u < (NB > 0 ? NB : 1); ++u) {
+    dm2[u] = -1.0f;
+    if (NB > 0 && collide && u < nloc && u != myloc) {
+      float dmin = p.rho + stat[r.lo + u].x;
+      if (MD) dmin += w.min_dist;
+      dm2[u] = __fmul_rn(dmin, dmin);
+    }
+  }
   for (int c = 0; c < T; c += KCH) {
     if (c + KCH < T) load_chunk(nxt, c + KCH);
 #pragma unroll
     for (int k = 0; k < KCH; ++k) {
       const int t = c + k;
       if (t < T) {  // uniform over the block
-        float4* cb = (t & 1) ? buf1 : buf0;
+        float2* cb = (t & 1) ? pos1 : pos0;
         if (t > 0) {
-          if (act) cb[r.slot] = make_float4(x, y, rho_lds, sfbits);
-          __syncthreads();
+          if (act) cb[r.slot] = make_float2(x, y);
+          lds_barrier();
         }
         float fx = cur[k].x + p.mgx, fy = cur[k].y + p.mgy;
         uint8_t* mk = (t == T - 1 && a.mask) ? a.mask : nullptr;
-        if (collide) {
-          // Pass 1: branch-free contact test of every partner, 64 at a time,
-          // into a bit mask. Pass 2: contact forces for the set bits only, so
-          // a wavefront runs the force code as often as its busiest lane has
-          // contacts, not once per partner index with any contact.
-          // The trip count is the largest environment of the group (uniform
-          // over the workgroup); a partner index past the lane's own
-          // environment is clamped to a valid slot and masked out. A
-          // non-collidable partner carries a NaN radius, which fails the test.
-          for (int base = 0; base < gmaxn; base += 32) {
-            const int cnt = min(32, gmaxn - base);
-            uint32_t hits = 0;
-            // software-pipelined: the next partner's LDS read is in flight
-            // while the current one is tested
-            float4 Pn = cb[min(r.lo + base, r.hi - 1)];
-            for (int u = 0; u < cnt; ++u) {
-              const float4 P = Pn;
-              if (u + 1 < cnt) Pn = cb[min(r.lo + base + u + 1, r.hi - 1)];
-              const float dmin = (p.rho + P.z) + w.min_dist;
-              const float dx = x - P.x, dy = y - P.y;
-              const float sq = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
-              const bool hit = (sq <= __fmul_rn(dmin, dmin)) & (base + u < nloc);
-              hits |= (uint32_t)hit << u;
+        // contact force of partner slot q (in contact), and its mask entry
+        auto contact = [&](int q) {
+          const float2 P = cb[q];
+          const float2 S = stat[q];
+          float dmin = p.rho + S.x;
+          if (MD) dmin += w.min_dist;
+          const float dx = x - P.x, dy = y - P.y;
+          const float sq = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
+          V2 n;
+          float d;
+          sphere_normal(dx, dy, sq, r.slot < q, &d, &n);
+          const float F = contact_mag(dmin, d, w);
+          fx = fmaf(F, n.x, fx);
+          fy = fmaf(F, n.y, fy);
+          if (mk) {
+            const int of = __float_as_int(S.y) >> 8;
+            const int b = q - r.lo;
+            if (myloc < b || (of & (MOVABLE | ROTATABLE)) == 0) {
+              const int ia = min(myloc, b), ib = max(myloc, b);
+              const int64_t idx = (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
+              mk[a.pair_off[r.env] + idx] = 1;
             }
-            if (myloc >= base && myloc < base + 32) hits &= ~(1u << (myloc - base));
+          }
+        };
+        if (collide) {
+          if constexpr (NB > 0) {
+            // Pass 1: the test of every partner slot into a bit mask (slot u
+            // -> bit u). Pass 2: forces for the set bits only, first partner
+            // first, so a wavefront runs the force code as often as its
+            // busiest lane has contacts.
+            const float2* pb = cb + r.lo;
+            uint32_t hits = 0;
+#pragma unroll
+            for (int blk = 0; blk < NB; blk += 8) {
+              if (blk < gmaxn) {  // uniform over the block
+                constexpr int W8 = NB < 8 ? NB : 8;
+#pragma unroll
+                for (int v = 0; v < W8; ++v) {
+                  const float2 P = pb[blk + v];
+                  const float dx = x - P.x, dy = y - P.y;
+                  const bool hit = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)) <= dm2[blk + v];
+                  hits |= (hit ? 1u : 0u) << (blk + v);
+                }
+              }
+            }
             while (hits) {
               const int u = __builtin_ctz(hits);
               hits &= hits - 1;
-              const int q = r.lo + base + u;
-              const float4 P = cb[q];
-              const float dmin = (p.rho + P.z) + w.min_dist;
+              contact(r.lo + u);
+            }
+          } else {
+            for (int u = 0; u < gmaxn; ++u) {
+              const int q = min(r.lo + u, r.hi - 1);
+              const float2 P = cb[q];
+              float dmin = p.rho + stat[q].x;
+              if (MD) dmin += w.min_dist;
               const float dx = x - P.x, dy = y - P.y;
               const float sq = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
-              V2 n;
-              float d;
-              sphere_normal(dx, dy, sq, r.slot < q, &d, &n);
-              const float F = contact_mag(dmin, d, w);
-              fx = fmaf(F, n.x, fx);
-              fy = fmaf(F, n.y, fy);
-              if (mk) {
-                const int of = __float_as_int(P.w) >> 8;
-                const int b = q - r.lo;
-                if (myloc < b || (of & (MOVABLE | ROTATABLE)) == 0) {
-                  const int ia = min(myloc, b), ib = max(myloc, b);
-                  const int64_t idx = (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
-                  mk[a.pair_off[r.env] + idx] = 1;
-                }
-              }
+              if ((sq <= __fmul_rn(dmin, dmin)) & (u < nloc) & (u != myloc)) contact(q);
             }
           }
         }
@@ -392,6 +430,30 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
   }
 }
 
+// Partner-slot bound of the sphere kernel for a plan whose largest
+// environment has max_n entities (0: the any-size loop).
+int sph_nb(int max_n) {
+  for (int nb : {4, 6, 8, 16, 32})
+    if (max_n <= nb) return nb;
+  return 0;
+}
+
+template <int NB>
+const void* sph_pick(bool md) {
+  return md ? (const void*)k_rollout_sph<256, NB, true> : (const void*)k_rollout_sph<256, NB, false>;
+}
+
+const void* sph_kernel256(int nb, bool md) {
+  switch (nb) {
+    case 4: return sph_pick<4>(md);
+    case 6: return sph_pick<6>(md);
+    case 8: return sph_pick<8>(md);
+    case 16: return sph_pick<16>(md);
+    case 32: return sph_pick<32>(md);
+    default: return sph_pick<0>(md);
+  }
+}
+
 __global__ void k_fill_u8(uint8_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -399,6 +461,12 @@ __global__ void k_fill_u8(uint8_t* p, int64_t n) {
 }
 
 __global__ void k_fill_f32(float* p, int64_t n, float v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -420,33 +488,31 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
-size_t rollout_lds_bytes(int max_stage, bool spheres_only);
+// Padding slots of the sphere kernel chosen for a launch shape.
+int sph_pad(int block, int max_n) { return block <= 256 ? sph_nb(max_n) : 0; }
+
+const void* rollout_kernel(bool spheres_only, int block, int max_n, float min_dist) {
+  if (spheres_only) {
+    const bool md = min_dist != 0.0f;
+    if (block > 256)
+      return md ? (const void*)k_rollout_sph<1024, 0, true> : (const void*)k_rollout_sph<1024, 0, false>;
+    return sph_kernel256(sph_pad(block, max_n), md);
+  }
+  return block <= 256 ? (const void*)k_rollout<false, 256> : (const void*)k_rollout<false, 1024>;
+}
+
+size_t rollout_lds_bytes(int max_stage, bool spheres_only, int block, int max_n) {
+  if (!spheres_only) return (size_t)max_stage * 3 * sizeof(float4);
+  return (size_t)(max_stage + sph_pad(block, max_n)) * 3 * sizeof(float2);
+}
 
 hipError_t launch_rollout(const StepArgs& a, int groups, int block, bool spheres_only,
                           hipStream_t s) {
-  const size_t shm = rollout_lds_bytes(a.max_stage, spheres_only);
-  if (block <= 256) {
-    if (spheres_only)
-      hipLaunchKernelGGL((k_rollout_sph<256>), dim3(groups), dim3(block), shm, s, a);
-    else
-      hipLaunchKernelGGL((k_rollout<false, 256>), dim3(groups), dim3(block), shm, s, a);
-  } else {
-    if (spheres_only)
-      hipLaunchKernelGGL((k_rollout_sph<1024>), dim3(groups), dim3(block), shm, s, a);
-    else
-      hipLaunchKernelGGL((k_rollout<false, 1024>), dim3(groups), dim3(block), shm, s, a);
-  }
-  return hipGetLastError();
-}
-
-const void* rollout_kernel(bool spheres_only, int block) {
-  if (block <= 256)
-    return spheres_only ? (const void*)k_rollout_sph<256> : (const void*)k_rollout<false, 256>;
-  return spheres_only ? (const void*)k_rollout_sph<1024> : (const void*)k_rollout<false, 1024>;
-}
-
-size_t rollout_lds_bytes(int max_stage, bool spheres_only) {
-  return (size_t)max_stage * (spheres_only ? 2 : 3) * sizeof(float4);
+  const void* f = rollout_kernel(spheres_only, block, a.max_n, a.w.min_dist);
+  const size_t shm = rollout_lds_bytes(a.max_stage, spheres_only, block, a.max_n);
+  StepArgs args = a;
+  void* kargs[1] = {&args};
+  return hipLaunchKernel(f, dim3(groups), dim3(block), kargs, shm, s);
 }
 
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, hipStream_t s) {
@@ -458,6 +524,12 @@ hipError_t launch_fill_u8(uint8_t* p, int64_t n, hipStream_t s) {
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

@@ -76,11 +76,16 @@ __device__ void stage_weights(const MlpArgs& m, unsigned short* w1, unsigned sho
   for (int i = threadIdx.x; i < NOP * NH; i += blockDim.x) w3[(i / NH) * LDH + i % NH] = m.W3[i];
 }
 
-// Forward pass of 64 rows. X [n][12] -> Y [n][2]; optionally the FP32
-// activations H1, H2 [n][128] for the backward pass.
+// Forward pass over 64-row tiles. X [n][12] -> Y [n][2]; optionally the FP32
+// activations H1, H2 [n][128] for the backward pass. With n_dev set, the row
+// count is min(n, *n_dev), read on the device.
 __global__ void __launch_bounds__(256) k_mlp_forward(MlpArgs m, const float* __restrict__ X,
-                                                     int64_t n, float* __restrict__ Y,
+                                                     int64_t n, const int32_t* __restrict__ n_dev,
+                                                     float* __restrict__ Y,
                                                      float* __restrict__ H1, float* __restrict__ H2) {
+  if (n_dev) n = min(n, (int64_t)max(*n_dev, 0));
+  const int64_t tiles = (n + ROWS - 1) / ROWS;
+  if ((int64_t)blockIdx.x >= tiles) return;  // uniform per workgroup, before any barrier
   __shared__ __attribute__((aligned(16))) unsigned short w1[NH * LDI], w2[NH * LDH], w3[NOP * LDH];
   __shared__ __attribute__((aligned(16))) unsigned short xs[ROWS * LDI], h1s[ROWS * LDH];
   __shared__ float bias[NH + NH + NO];
@@ -92,7 +97,6 @@ __global__ void __launch_bounds__(256) k_mlp_forward(MlpArgs m, const float* __r
   if (threadIdx.x < NO) bias[2 * NH + threadIdx.x] = m.b3[threadIdx.x];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r0 = wv * 16, col = lane & 15, rq = (lane >> 4) * 4;
-  const int64_t tiles = (n + ROWS - 1) / ROWS;
   // the workgroup walks row tiles; the weights stay staged in LDS
   for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int64_t row0 = tile * ROWS;
@@ -413,13 +417,14 @@ int mlp_nparam() { return NPARAM; }
 
 hipError_t mlp_launch_forward(const unsigned short* W1, const unsigned short* W2,
                               const unsigned short* W3, const float* b1, const float* b2,
-                              const float* b3, const float* X, int64_t n, float* Y, float* H1,
-                              float* H2, hipStream_t s) {
+                              const float* b3, const float* X, int64_t n, const int32_t* n_dev,
+                              float* Y, float* H1, float* H2, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   MlpArgs m{W1, W2, W3, b1, b2, b3};
   const int64_t tiles = (n + ROWS - 1) / ROWS;
   const int64_t blocks = tiles < 2048 ? tiles : 2048;  // 8 workgroups per CU walk the tiles
-  hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)blocks), dim3(256), 0, s, m, X, n, Y, H1, H2);
+  hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)blocks), dim3(256), 0, s, m, X, n, n_dev, Y, H1,
+                     H2);
   return hipGetLastError();
 }
 

@@ -55,6 +55,7 @@ struct Plan {
   bool valid = false;
   int groups = 0;
   int max_stage = 0;
+  int max_n = 0;  // largest environment of the plan
   LaneRec* d_lanes = nullptr;
   int32_t* d_stage_off = nullptr;
   int32_t* d_stage = nullptr;
@@ -103,7 +104,7 @@ struct vmas_batch {
   // surrogate workspace: features [P][12], MLP outputs [P][2], flags [P]
   float* d_feat = nullptr;
   float* d_yhat = nullptr;
-  uint8_t* d_cand = nullptr;
+  int32_t* d_rows = nullptr;   // [P] candidate row of each pair slot, then [1] the count
   std::vector<Plan> plans;
   int cur = 0;
   Plan back;  // adjoint plan: every entity has a lane
@@ -145,7 +146,7 @@ void free_batch(vmas_batch* b) {
   if (b->d_env_off) (void)hipFree(b->d_env_off);
   if (b->d_feat) (void)hipFree(b->d_feat);
   if (b->d_yhat) (void)hipFree(b->d_yhat);
-  if (b->d_cand) (void)hipFree(b->d_cand);
+  if (b->d_rows) (void)hipFree(b->d_rows);
   if (b->d_ws) (void)hipFree(b->d_ws);
   delete b;
 }
@@ -351,6 +352,8 @@ vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8
   }
   p.groups = G;
   p.max_stage = max_stage;
+  p.max_n = 0;
+  for (int32_t m : maxn) p.max_n = std::max(p.max_n, (int)m);
   vmas_status s;
   if ((s = upload(&p.d_lanes, lane.data(), lane.size())) != VMAS_OK) return s;
   if ((s = upload(&p.d_stage_off, stage_off.data(), stage_off.size())) != VMAS_OK) return s;
@@ -372,6 +375,7 @@ StepArgs make_args(vmas_batch* b, const Plan& p) {
   a.pair_off = b->d_pair_off;
   a.grp_maxn = p.d_maxn;
   a.max_stage = p.max_stage;
+  a.max_n = p.max_n;
   a.w = b->w;
   return a;
 }
@@ -700,10 +704,10 @@ vmas_status vmas_rollout_graph(vmas_batch* b, float* state, const float* actions
   const bool drawn = actions == nullptr;
   void* args[1] = {&a};
   hipKernelNodeParams kp{};
-  kp.func = const_cast<void*>(rollout_kernel(b->spheres_only, p.block));
+  kp.func = const_cast<void*>(rollout_kernel(b->spheres_only, p.block, p.max_n, b->w.min_dist));
   kp.gridDim = dim3(p.groups);
   kp.blockDim = dim3(p.block);
-  kp.sharedMemBytes = (unsigned)rollout_lds_bytes(p.max_stage, b->spheres_only);
+  kp.sharedMemBytes = (unsigned)rollout_lds_bytes(p.max_stage, b->spheres_only, p.block, p.max_n);
   kp.kernelParams = args;
   kp.extra = nullptr;
   if (!b->gexec || b->graph_T != T || b->graph_plan != b->cur || b->graph_drawn != drawn) {
@@ -905,20 +909,27 @@ vmas_status vmas_step_surrogate(vmas_batch* b, vmas_mlp* mlp, float* state, cons
   if (!actions && b->A > 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "actions must not be NULL");
   if (!(std::isfinite(band) && band >= 0 && std::isfinite(fallback_frac)))
     return fail(VMAS_ERR_INVALID_ARGUMENT, "band must be >= 0 and fallback_frac finite");
+  if (b->P >= INT32_MAX)
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "surrogate step supports fewer than 2^31 pair slots");
   DeviceGuard guard(b->device);
   hipStream_t s = (hipStream_t)stream;
   if (!b->d_feat && b->P > 0) {
     hipError_t e;
     if ((e = hipMalloc((void**)&b->d_feat, (size_t)b->P * 12 * sizeof(float))) != hipSuccess ||
         (e = hipMalloc((void**)&b->d_yhat, (size_t)b->P * 2 * sizeof(float))) != hipSuccess ||
-        (e = hipMalloc((void**)&b->d_cand, (size_t)b->P)) != hipSuccess)
+        (e = hipMalloc((void**)&b->d_rows, (size_t)(b->P + 1) * sizeof(int32_t))) != hipSuccess)
       return fail(VMAS_ERR_OUT_OF_MEMORY, "surrogate workspace: %s", hipGetErrorString(e));
   }
   if (forces) HIPCHK(launch_fill_f32(forces, 3 * (int64_t)b->N, 0.0f, s));
-  HIPCHK(launch_pair_features(state, b->d_ent, b->d_env_off, b->d_pair_off, nullptr, b->P, band,
-                              b->d_feat, nullptr, b->d_cand, b->n_envs, b->w, s));
-  vmas_status st = vmas_mlp_forward(mlp, b->d_feat, b->P, b->d_yhat, stream);
-  if (st != VMAS_OK) return st;
+  if (b->P > 0) {
+    // candidates' features into consecutive rows, the network on those rows only
+    int32_t* count = b->d_rows + b->P;
+    HIPCHK(launch_fill_i32(count, 1, 0, s));
+    HIPCHK(launch_candidate_features(state, b->d_ent, b->d_env_off, b->d_pair_off, b->P, band,
+                                     b->d_feat, b->d_rows, count, b->n_envs, b->w, s));
+    vmas_status st = mlp_forward_counted(mlp, b->d_feat, b->P, count, b->d_yhat, s);
+    if (st != VMAS_OK) return st;
+  }
   const Plan& p = b->plans[b->cur];
   if (p.groups == 0) return VMAS_OK;
   StepArgs a = make_args(b, p);
@@ -926,7 +937,7 @@ vmas_status vmas_step_surrogate(vmas_batch* b, vmas_mlp* mlp, float* state, cons
   a.actions = actions;
   a.T = 1;
   a.forces = forces;
-  HIPCHK(launch_step_surrogate(a, b->d_yhat, b->d_cand, fallback_frac, n_fallback, p.groups,
+  HIPCHK(launch_step_surrogate(a, b->d_yhat, b->d_rows, fallback_frac, n_fallback, p.groups,
                                p.block, s));
   return VMAS_OK;
 }

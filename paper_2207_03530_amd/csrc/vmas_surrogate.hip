@@ -11,9 +11,17 @@
 //   shape code of i and of j (sphere 0, box 0.5, line 1);
 // L = 0.1, Lg = 0.01. Target: the Eq. (2) force on i in the pair frame
 // (along e, along the left normal of e) divided by c * Lf, Lf = 0.02 (zero
-// when the pair is not in contact).
-// A pair is a candidate when its bounding circles (sphere r, box half
-// diagonal, line L/2) come within `band` of each other.
+// when the pair is not in contact). The gap feature is clamped below at -4
+// (bounding circles of boxes overlap far before the boxes touch; the centre
+// distance carries that range).
+// A pair is a candidate for the network when neither entity is a segment and
+// their bounding circles (sphere r, box half diagonal) come within `band` of
+// each other. A segment has no thickness, so the fallback rule (penetration
+// beyond half the smaller size) has no meaning for it: pairs with a segment
+// always take the exact narrow phase. The surrogate step
+// compacts the candidates' features into consecutive rows (one atomic per
+// wavefront; the row order varies between runs, the per-row network output
+// does not) so that the network runs on candidates only.
 
 #include "vmas_geom.h"
 #include "vmas_internal.h"
@@ -52,7 +60,9 @@ struct FeatArgs {
   float band;
   float* feat;              // [m][12]
   float* target;            // [m][2] or NULL
-  uint8_t* flags;           // [m]: 1 candidate, 2 exact contact
+  uint8_t* flags;           // [m]: 1 candidate, 2 exact contact (NULL in compact mode)
+  int32_t* row_of;          // compact mode: [m] feature row of each slot, -1 if no candidate
+  int32_t* count;           // compact mode: number of candidate rows (starts at 0)
   int n_envs;
   WorldK w;
 };
@@ -90,9 +100,27 @@ __global__ void k_pair_features(FeatArgs a) {
   const float dist = sqrtf(vdot(dl, dl));
   const V2T<float> ex = dist > 0.0f ? V2T<float>{dl.x / dist, dl.y / dist} : V2T<float>{1.0f, 0.0f};
   const float Ri = bound_radius(si, pi.d0, pi.d1), Rj = bound_radius(sj, pj.d0, pj.d1);
-  float* f = a.feat + r * 12;
+  const bool eligible = (fi & COLLIDABLE) && (fj & COLLIDABLE) &&
+                        ((fi | fj) & (MOVABLE | ROTATABLE)) && !excluded(pi.excl, lc) &&
+                        !excluded(pj.excl, la);
+  const bool cand = eligible && si != LINE && sj != LINE && dist <= Ri + Rj + a.band;
+  int64_t row = r;
+  if (a.row_of) {
+    // compact mode: candidates take consecutive rows, one atomic per wavefront
+    const uint64_t bal = __ballot(cand);
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)bal) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(a.count, __popcll(bal));
+    base = __shfl(base, leader < 0 ? 0 : leader);
+    const int off = __popcll(bal & ((1ull << lane) - 1ull));
+    a.row_of[r] = cand ? base + off : -1;
+    if (!cand) return;
+    row = base + off;
+  }
+  float* f = a.feat + row * 12;
   f[0] = dist / FEAT_L;
-  f[1] = (dist - (Ri + Rj)) / GAP_L;
+  f[1] = fmaxf((dist - (Ri + Rj)) / GAP_L, -4.0f);
   f[2] = fmaf(ci, ex.x, sni * ex.y);    // cos(theta_i - phi)
   f[3] = fmaf(sni, ex.x, -ci * ex.y);   // sin(theta_i - phi)
   f[4] = fmaf(cj, ex.x, snj * ex.y);
@@ -103,10 +131,7 @@ __global__ void k_pair_features(FeatArgs a) {
   f[9] = pj.d1 / FEAT_L;
   f[10] = 0.5f * (float)si;  // SPHERE 0, BOX 1, LINE 2
   f[11] = 0.5f * (float)sj;
-  const bool eligible = (fi & COLLIDABLE) && (fj & COLLIDABLE) &&
-                        ((fi | fj) & (MOVABLE | ROTATABLE)) && !excluded(pi.excl, lc) &&
-                        !excluded(pj.excl, la);
-  const bool cand = eligible && dist <= Ri + Rj + a.band;
+  if (a.row_of) return;
   uint8_t fl = cand ? 1 : 0;
   float tx = 0.0f, ty = 0.0f;
   if (cand) {
@@ -136,8 +161,8 @@ __global__ void k_pair_features(FeatArgs a) {
 
 struct SurArgs {
   StepArgs s;             // plan, state, actions (T = 1), forces
-  const float* yhat;      // [P][2] MLP outputs (force on lo in the pair frame / (c Lf))
-  const uint8_t* cand;    // [P] candidate flags (bit 0)
+  const float* yhat;      // [rows][2] MLP outputs (force on lo in the pair frame / (c Lf))
+  const int32_t* row_of;  // [P] row of each candidate slot in yhat, -1 if no candidate
   float fallback_frac;    // exact fallback when predicted penetration > frac * r
   int32_t* n_fallback;    // device counter, or NULL
 };
@@ -194,11 +219,19 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
       const int b = q - r.lo;
       const int ia = min(myloc, b), ib = max(myloc, b);
       const int64_t slot = a.pair_off[r.env] + (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
-      if (!(sa.cand[slot] & 1)) continue;
       const float4 P = pose[q];
       const float4 S = stat[q];
+      if (shape == LINE || (__float_as_int(S.w) & 0xff) == LINE) {
+        // segments: exact narrow phase (same eligibility as the exact step)
+        const int of = (__float_as_int(S.w) >> 8) & 0xff;
+        if ((of & COLLIDABLE) && !(p.excl != -1 && excluded(p.excl, b)))
+          pair_force<false>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
+        continue;
+      }
+      const int row = sa.row_of[slot];
+      if (row < 0) continue;
       // surrogate force on lo, in the pair frame -> world
-      const float hx = sa.yhat[2 * slot] * FS, hy = sa.yhat[2 * slot + 1] * FS;
+      const float hx = sa.yhat[2 * (int64_t)row] * FS, hy = sa.yhat[2 * (int64_t)row + 1] * FS;
       const float sgn = myloc < b ? 1.0f : -1.0f;  // e points from hi to lo
       const float ddx = sgn * (x - P.x), ddy = sgn * (y - P.y);
       const float dd = sqrtf(fmaf(ddx, ddx, ddy * ddy));
@@ -276,15 +309,27 @@ hipError_t launch_pair_features(const float* state, const EntParam* ent, const i
                                 float band, float* feat, float* target, uint8_t* flags,
                                 int n_envs, const WorldK& w, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  FeatArgs a{state, ent, env_off, pair_off, slots, m, band, feat, target, flags, n_envs, w};
+  FeatArgs a{state, ent, env_off, pair_off, slots, m, band, feat, target, flags, nullptr, nullptr,
+             n_envs, w};
   hipLaunchKernelGGL(k_pair_features, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat, const uint8_t* cand,
+hipError_t launch_candidate_features(const float* state, const EntParam* ent,
+                                     const int32_t* env_off, const int64_t* pair_off, int64_t P,
+                                     float band, float* feat, int32_t* row_of, int32_t* count,
+                                     int n_envs, const WorldK& w, hipStream_t s) {
+  if (P <= 0) return hipSuccess;
+  FeatArgs a{state, ent, env_off, pair_off, nullptr, P, band, feat, nullptr, nullptr, row_of,
+             count, n_envs, w};
+  hipLaunchKernelGGL(k_pair_features, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat, const int32_t* row_of,
                                  float frac, int32_t* n_fallback, int groups, int block,
                                  hipStream_t s) {
-  SurArgs sa{a, yhat, cand, frac, n_fallback};
+  SurArgs sa{a, yhat, row_of, frac, n_fallback};
   const size_t shm = (size_t)a.max_stage * 2 * sizeof(float4);
   hipLaunchKernelGGL(k_step_surrogate, dim3(groups), dim3(block), shm, s, sa);
   return hipGetLastError();

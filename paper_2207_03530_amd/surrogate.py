@@ -15,8 +15,24 @@ import numpy as np
 from . import binding as B
 from . import workloads as W
 
-BAND = 0.05          # candidate reach beyond touching bounding circles
+BAND = 0.01          # candidate reach beyond touching bounding circles
 FALLBACK = 0.5       # exact step when the predicted penetration exceeds 0.5 r
+FEAT_L, FORCE_L = 0.1, 0.02   # feature length scale and target force scale c * FORCE_L
+
+
+def _half_size(dims_over_l, code):
+    """Length that the fallback rule compares penetration with: sphere r,
+    box half its shorter side, line half its length (features -> metres)."""
+    import torch
+    d0, d1 = dims_over_l[:, 0] * FEAT_L, dims_over_l[:, 1] * FEAT_L
+    return torch.where(code == 0, d0, torch.where(code == 0.5, 0.5 * torch.minimum(d0, d1), 0.5 * d0))
+
+
+def penetration_of(y, c: float, k: float):
+    """Penetration implied by a target / output through the inverse of Eq. (2)."""
+    import torch
+    mag = torch.linalg.norm(y, dim=1).double() * c * FORCE_L
+    return (k * torch.log(torch.expm1(mag / (c * k)))).float()
 
 
 def make_dataset(world, T: int, stride: int, max_samples: int, seed: int = 0, device: int = 0):
@@ -45,9 +61,21 @@ def make_dataset(world, T: int, stride: int, max_samples: int, seed: int = 0, de
         y = torch.zeros(cand.size, 2, device=dev)
         fl = torch.zeros(cand.size, dtype=torch.uint8, device=dev)
         b.pair_features(s_t, f, fl, targets=y, slots=slots, band=BAND)
+        # contacts deeper than twice the fallback threshold are taught as
+        # exactly that deep: their prediction only has to trigger the exact
+        # fallback, so the network need not fit the unbounded force there
+        rr = torch.minimum(_half_size(f[:, 6:8], f[:, 10]), _half_size(f[:, 8:10], f[:, 11]))
+        c, k = world.contact_force, world.contact_margin
+        pen = penetration_of(y, c, k)
+        cap = 2.0 * FALLBACK * rr
+        deep = ((fl & 2) != 0) & (pen > cap)
+        if bool(deep.any()):
+            m_cap = c * k * torch.nn.functional.softplus(cap[deep].double() / k) / (c * FORCE_L)
+            m = torch.linalg.norm(y[deep], dim=1).double()
+            y[deep] = y[deep] * (m_cap / m).float().unsqueeze(1)
         feats.append(f)
         targs.append(y)
-        total += cand.size
+        total += f.shape[0]
         if total >= max_samples:
             break
     b.close()
