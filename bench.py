@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 KERNEL_SRC = os.path.join(ROOT, "paper_2207_03530_amd", "csrc", "vmas_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rollout_sph_spread30k_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
 
 # Algorithmic bytes of one environment-step / one entity of the spread
 # workload (see the roofline section of the design notes):
@@ -52,11 +52,16 @@ def algorithmic_bytes(n_envs, agents, landmarks, T):
             + A * STATE_WRITE_PER_ACTIVE + N * STATIC_PER_ENTITY)
 
 
-def traffic_per_launch():
+def kernel_of(schedule: str) -> str:
+    """Device function that runs a rollout under the given schedule."""
+    return "k_rollout_quad" if schedule.startswith("quad") else "k_rollout_sph"
+
+
+def traffic_per_launch(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, if it was taken on the current kernel source; else None."""
+    summary of `kernel`, if it was taken on the current kernel source; else None."""
     try:
-        d = json.load(open(TRAFFIC_FILE))
+        d = json.load(open(os.path.join(PROFILES, f"{kernel}_spread30k_traffic.json")))
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_sha") != kernel_sha():
@@ -154,7 +159,8 @@ def main():
     if args.drawn_actions:
         nbytes -= T * w.n_agents_total * ACTION_BYTES_PER_AGENT_STEP
     achieved = nbytes / (kernel_ms * 1e-3) / 1e9
-    traffic = traffic_per_launch() if not (args.drawn_actions or args.graph) else None
+    kernel = kernel_of(batch.schedule_name(plan))
+    traffic = traffic_per_launch(kernel) if not (args.drawn_actions or args.graph) else None
     out = {
         "metric": "agent-steps/s at 30k envs x 4 agents",
         "value": value,
@@ -180,7 +186,7 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_rollout_sph", "kernel_ms": kernel_ms,
+            "kernel": kernel, "kernel_ms": kernel_ms,
             "algorithmic_bytes_per_launch": nbytes,
             "algorithmic_bytes_per_env_step": nbytes / (w.n_envs * T),
         },

@@ -58,6 +58,16 @@ struct WorldK {
   int32_t pad[2];
 };
 
+// One environment of the quad schedule (sphere-only batches whose
+// environments have at most 4 entities that move or rotate and at most 4
+// static collidable ones): its movers sit on one aligned quad of lanes.
+struct QuadEnv {
+  int32_t agent_row;    // action row of the environment's first agent
+  int32_t n_agents;     // agents are local entities 0 .. n_agents - 1
+  int8_t lane_loc[4];   // local index of the entity on quad lane q, -1: idle lane
+  int8_t stat_loc[4];   // local index of the s-th static collidable entity, -1: none
+};
+
 // Arguments of the step / rollout kernels.
 struct StepArgs {
   float* state;            // [6][N]
@@ -78,8 +88,19 @@ struct StepArgs {
   const int32_t* grp_maxn;   // [groups] size of the largest environment of each group
   int32_t max_stage;         // LDS slots per group
   int32_t max_n;             // size of the largest environment of the plan
+  const QuadEnv* quad;       // [n_envs] quad schedule, or NULL
+  const int32_t* env_off;    // [n_envs + 1] first entity of each environment
+  int32_t n_envs;
+  int32_t pad;
   WorldK w;
 };
+
+// Waits until this wavefront's global loads have returned (s_waitcnt
+// vmcnt(0), the other counters untouched). Placed after the first action
+// chunk is loaded, it keeps that load from being outstanding at the top of
+// the step loop, where the compiler would otherwise wait for every load in
+// flight -- the next chunk's prefetch included -- at the start of each chunk.
+__device__ __forceinline__ void wait_global_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // Workgroup barrier for LDS traffic only: waits for this wavefront's LDS
 // operations, then meets the other wavefronts. Unlike __syncthreads() it does
@@ -113,8 +134,9 @@ hipError_t launch_rollout(const StepArgs& a, int groups, int block, bool spheres
 hipError_t launch_backward(const BackArgs& a, int groups, int block, hipStream_t s);
 // Device function of the rollout kernel launched by launch_rollout (for
 // explicit graph construction) and its dynamic LDS size.
-const void* rollout_kernel(bool spheres_only, int block, int max_n, float min_dist);
-size_t rollout_lds_bytes(int max_stage, bool spheres_only, int block, int max_n);
+const void* rollout_kernel(bool spheres_only, bool quad, int block, int max_n, float min_dist,
+                           bool out);
+size_t rollout_lds_bytes(int max_stage, bool spheres_only, bool quad, int block, int max_n);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);

@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
 // variant and as the sphere path of k_rollout.
 constexpr int KCH = 8;
 
-template <int MAXB, int NB, bool MD>
+template <int MAXB, int NB, bool MD, bool OUT>
 __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
   extern __shared__ float2 lds2[];
   const int E = a.max_stage + NB;  // slots per array, padding included
@@ -294,6 +294,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
     }
   };
   load_chunk(cur, 0);
+  wait_global_loads();
   __syncthreads();
   // squared contact distance of each partner slot (-1: never in contact)
   float dm2[NB > 0 ? NB : 1];
@@ -318,7 +319,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
           lds_barrier();
         }
         float fx = cur[k].x + p.mgx, fy = cur[k].y + p.mgy;
-        uint8_t* mk = (t == T - 1 && a.mask) ? a.mask : nullptr;
+        uint8_t* mk = (OUT && t == T - 1 && a.mask) ? a.mask : nullptr;
         // contact force of partner slot q (in contact), and its mask entry
         auto contact = [&](int q) {
           const float2 P = cb[q];
@@ -381,7 +382,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
             }
           }
         }
-        if (t == T - 1 && a.forces && act) {
+        if (OUT && t == T - 1 && a.forces && act) {
           a.forces[r.ent] = fx;
           a.forces[N + r.ent] = fy;
           a.forces[2 * N + r.ent] = 0.0f;
@@ -405,7 +406,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
           om = fmaf(0.0f * p.inv_I, w.dt, w.damp * om);
           th = fmaf(om, w.dt, th);
         }
-        if (a.traj && act) {
+        if (OUT && a.traj && act) {
           float* o = a.traj + (size_t)(t + 1) * 6 * N;
           o[r.ent] = x;
           o[N + r.ent] = y;
@@ -430,6 +431,222 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
   }
 }
 
+// Quad schedule for sphere-only batches whose environments have at most 4
+// entities that move or rotate and at most 4 static collidable entities
+// (e.g. 4 agents and 2 landmarks): the movers of an environment sit on one
+// aligned quad of lanes and read each other's centres with DPP quad
+// permutations, so a step needs no LDS traffic and no barrier. Static
+// entities never move; their centres, like every contact distance, are
+// loaded into registers once. Contacts are visited in partner order (local
+// index) with the arithmetic of the other sphere kernels, so results are
+// bitwise those of every other schedule.
+template <int CTRL>
+__device__ __forceinline__ float quad_perm(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+template <bool MD, int NS, bool OUT>
+__global__ void __launch_bounds__(256) k_rollout_quad(StepArgs a) {
+  const int gl = blockIdx.x * blockDim.x + threadIdx.x;
+  const int env = gl >> 2, qp = gl & 3;
+  const int N = a.w.N;
+  QuadEnv Q;
+  Q.agent_row = 0;
+  Q.n_agents = 0;
+  for (int u = 0; u < 4; ++u) Q.lane_loc[u] = Q.stat_loc[u] = -1;
+  int o = 0, n = 0;
+  if (env < a.n_envs) {
+    Q = a.quad[env];
+    o = a.env_off[env];
+    n = a.env_off[env + 1] - o;
+  }
+  const int myloc = Q.lane_loc[qp];
+  const bool act = myloc >= 0;
+  const int e = o + myloc;
+  float x = 0, y = 0, vx = 0, vy = 0, th = 0, om = 0;
+  EntParam p{};
+  if (act) {
+    x = a.state[e];
+    y = a.state[N + e];
+    vx = a.state[2 * N + e];
+    vy = a.state[3 * N + e];
+    th = a.state[4 * N + e];
+    om = a.state[5 * N + e];
+    p = a.ent[e];
+  }
+  const int fl = (p.sf >> 8) & 0xff;
+  const bool movable = act && (fl & MOVABLE) != 0, rotatable = act && (fl & ROTATABLE) != 0;
+  const bool collide = act && (fl & COLLIDABLE) != 0;
+  const bool agent = act && myloc < Q.n_agents;
+  const WorldK w = a.w;
+  // partners: quad lanes qp ^ 1, qp ^ 2, qp ^ 3, then NS static entities
+  // (NS: the most any environment of the batch has); bit (1 << local index)
+  // of each, its radius, flags and contact distance squared (-1: never in
+  // contact)
+  constexpr int NP = 3 + NS;
+  uint32_t bit[NP];
+  float rad[NP], dm2[NP], sx[NS > 0 ? NS : 1], sy[NS > 0 ? NS : 1];
+  int pfl[NP];
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    const int loc = u < 3 ? Q.lane_loc[qp ^ (u + 1)] : Q.stat_loc[u - 3];
+    bit[u] = loc >= 0 ? 1u << loc : 0u;
+    rad[u] = 0.0f;
+    pfl[u] = 0;
+    dm2[u] = -1.0f;
+    if (u >= 3) {
+      sx[u - 3] = 0.0f;
+      sy[u - 3] = 0.0f;
+    }
+    if (loc >= 0) {
+      const EntParam q = a.ent[o + loc];
+      rad[u] = q.rho;
+      pfl[u] = (q.sf >> 8) & 0xff;
+      if (u >= 3) {
+        sx[u - 3] = a.state[o + loc];
+        sy[u - 3] = a.state[N + o + loc];
+      }
+      if (collide && (pfl[u] & COLLIDABLE)) {
+        float dmin = p.rho + q.rho;
+        if (MD) dmin += w.min_dist;
+        dm2[u] = __fmul_rn(dmin, dmin);
+      }
+    }
+  }
+  const int T = a.T;
+  const size_t A = (size_t)w.A;
+  const int arow = Q.agent_row + (agent ? myloc : 0);
+  const bool drawn = a.actions == nullptr;  // uniform
+  const float2* ap = reinterpret_cast<const float2*>(a.actions) + arow;
+  float2 cur[KCH], nxt[KCH];
+  auto load_chunk = [&](float2* dst, int c) {
+#pragma unroll
+    for (int k = 0; k < KCH; ++k) dst[k] = make_float2(0.0f, 0.0f);
+    if (!drawn) {
+#pragma unroll
+      for (int k = 0; k < KCH; ++k)
+        if (agent && c + k < T) dst[k] = ap[(size_t)(c + k) * A];
+    } else {
+#pragma unroll
+      for (int k = 0; k < KCH; ++k) {
+        if (agent && c + k < T) {
+          const uint64_t base = ((uint64_t)(a.t0 + c + k) * (uint64_t)w.A + (uint64_t)arow) * 2ull;
+          dst[k] = make_float2(draw_sym(a.key, base), draw_sym(a.key, base + 1));
+        }
+      }
+    }
+  };
+  load_chunk(cur, 0);
+  wait_global_loads();
+  for (int c = 0; c < T; c += KCH) {
+    if (c + KCH < T) load_chunk(nxt, c + KCH);
+#pragma unroll
+    for (int k = 0; k < KCH; ++k) {
+      const int t = c + k;
+      if (t < T) {  // uniform
+        // centres of the quad partners (every lane takes part)
+        float px[NP], py[NP];
+        px[0] = quad_perm<0xB1>(x);  // lane ^ 1
+        py[0] = quad_perm<0xB1>(y);
+        px[1] = quad_perm<0x4E>(x);  // lane ^ 2
+        py[1] = quad_perm<0x4E>(y);
+        px[2] = quad_perm<0x1B>(x);  // lane ^ 3
+        py[2] = quad_perm<0x1B>(y);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          px[3 + s] = sx[s];
+          py[3 + s] = sy[s];
+        }
+        float fx = cur[k].x + p.mgx, fy = cur[k].y + p.mgy;
+        uint8_t* mk = (OUT && t == T - 1 && a.mask) ? a.mask : nullptr;
+        if (collide) {
+          uint32_t hits = 0;
+#pragma unroll
+          for (int u = 0; u < NP; ++u) {
+            const float dx = x - px[u], dy = y - py[u];
+            const bool hit = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)) <= dm2[u];
+            hits |= hit ? bit[u] : 0u;
+          }
+          while (hits) {  // partner order: lowest local index first
+            const uint32_t b1 = hits & (0u - hits);
+            hits ^= b1;
+            const int ploc = __builtin_ctz(b1);
+            float PX = 0.0f, PY = 0.0f, PR = 0.0f;
+            int PF = 0;
+#pragma unroll
+            for (int u = 0; u < NP; ++u) {
+              if (bit[u] == b1) {
+                PX = px[u];
+                PY = py[u];
+                PR = rad[u];
+                PF = pfl[u];
+              }
+            }
+            float dmin = p.rho + PR;
+            if (MD) dmin += w.min_dist;
+            const float dx = x - PX, dy = y - PY;
+            const float sq = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
+            V2 nrm;
+            float d;
+            sphere_normal(dx, dy, sq, myloc < ploc, &d, &nrm);
+            const float F = contact_mag(dmin, d, w);
+            fx = fmaf(F, nrm.x, fx);
+            fy = fmaf(F, nrm.y, fy);
+            if (mk && (myloc < ploc || (PF & (MOVABLE | ROTATABLE)) == 0)) {
+              const int ia = min(myloc, ploc), ib = max(myloc, ploc);
+              const int64_t idx = (int64_t)ia * n - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
+              mk[a.pair_off[env] + idx] = 1;
+            }
+          }
+        }
+        if (OUT && t == T - 1 && a.forces && act) {
+          a.forces[e] = fx;
+          a.forces[N + e] = fy;
+          a.forces[2 * N + e] = 0.0f;
+        }
+        if (movable) {
+          const float ax = fx * p.inv_m, ay = fy * p.inv_m;
+          vx = fmaf(ax, w.dt, w.damp * vx);
+          vy = fmaf(ay, w.dt, w.damp * vy);
+          if (p.vmax > 0.0f) {
+            const float sp = sqrtf(fmaf(vx, vx, vy * vy));
+            if (sp > p.vmax) {
+              const float sc = p.vmax / sp;
+              vx *= sc;
+              vy *= sc;
+            }
+          }
+          x = fmaf(vx, w.dt, x);
+          y = fmaf(vy, w.dt, y);
+        }
+        if (rotatable) {
+          om = fmaf(0.0f * p.inv_I, w.dt, w.damp * om);
+          th = fmaf(om, w.dt, th);
+        }
+        if (OUT && a.traj && act) {
+          float* out = a.traj + (size_t)(t + 1) * 6 * N;
+          out[e] = x;
+          out[N + e] = y;
+          out[2 * N + e] = vx;
+          out[3 * N + e] = vy;
+          out[4 * N + e] = th;
+          out[5 * N + e] = om;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KCH; ++k) cur[k] = nxt[k];
+  }
+  if (act && T > 0) {
+    a.state[e] = x;
+    a.state[N + e] = y;
+    a.state[2 * N + e] = vx;
+    a.state[3 * N + e] = vy;
+    a.state[4 * N + e] = th;
+    a.state[5 * N + e] = om;
+  }
+}
+
 // Partner-slot bound of the sphere kernel for a plan whose largest
 // environment has max_n entities (0: the any-size loop).
 int sph_nb(int max_n) {
@@ -438,20 +655,27 @@ int sph_nb(int max_n) {
   return 0;
 }
 
-template <int NB>
-const void* sph_pick(bool md) {
-  return md ? (const void*)k_rollout_sph<256, NB, true> : (const void*)k_rollout_sph<256, NB, false>;
+template <int MAXB, int NB>
+const void* sph_pick(bool md, bool out) {
+  if (md) return out ? (const void*)k_rollout_sph<MAXB, NB, true, true> : (const void*)k_rollout_sph<MAXB, NB, true, false>;
+  return out ? (const void*)k_rollout_sph<MAXB, NB, false, true> : (const void*)k_rollout_sph<MAXB, NB, false, false>;
 }
 
-const void* sph_kernel256(int nb, bool md) {
+const void* sph_kernel256(int nb, bool md, bool out) {
   switch (nb) {
-    case 4: return sph_pick<4>(md);
-    case 6: return sph_pick<6>(md);
-    case 8: return sph_pick<8>(md);
-    case 16: return sph_pick<16>(md);
-    case 32: return sph_pick<32>(md);
-    default: return sph_pick<0>(md);
+    case 4: return sph_pick<256, 4>(md, out);
+    case 6: return sph_pick<256, 6>(md, out);
+    case 8: return sph_pick<256, 8>(md, out);
+    case 16: return sph_pick<256, 16>(md, out);
+    case 32: return sph_pick<256, 32>(md, out);
+    default: return sph_pick<256, 0>(md, out);
   }
+}
+
+template <int NS>
+const void* quad_pick(bool md, bool out) {
+  if (md) return out ? (const void*)k_rollout_quad<true, NS, true> : (const void*)k_rollout_quad<true, NS, false>;
+  return out ? (const void*)k_rollout_quad<false, NS, true> : (const void*)k_rollout_quad<false, NS, false>;
 }
 
 __global__ void k_fill_u8(uint8_t* p, int64_t n) {
@@ -491,25 +715,28 @@ int grid_for(int64_t n) {
 // Padding slots of the sphere kernel chosen for a launch shape.
 int sph_pad(int block, int max_n) { return block <= 256 ? sph_nb(max_n) : 0; }
 
-const void* rollout_kernel(bool spheres_only, int block, int max_n, float min_dist) {
-  if (spheres_only) {
-    const bool md = min_dist != 0.0f;
-    if (block > 256)
-      return md ? (const void*)k_rollout_sph<1024, 0, true> : (const void*)k_rollout_sph<1024, 0, false>;
-    return sph_kernel256(sph_pad(block, max_n), md);
-  }
+const void* rollout_kernel(bool spheres_only, bool quad, int block, int max_n, float min_dist,
+                           bool out) {
+  const bool md = min_dist != 0.0f;
+  // quad: max_n carries the most static collidable entities of an environment
+  if (quad) return max_n <= 2 ? quad_pick<2>(md, out) : quad_pick<4>(md, out);
+  if (spheres_only)
+    return block > 256 ? sph_pick<1024, 0>(md, out) : sph_kernel256(sph_pad(block, max_n), md, out);
   return block <= 256 ? (const void*)k_rollout<false, 256> : (const void*)k_rollout<false, 1024>;
 }
 
-size_t rollout_lds_bytes(int max_stage, bool spheres_only, int block, int max_n) {
+size_t rollout_lds_bytes(int max_stage, bool spheres_only, bool quad, int block, int max_n) {
+  if (quad) return 0;
   if (!spheres_only) return (size_t)max_stage * 3 * sizeof(float4);
   return (size_t)(max_stage + sph_pad(block, max_n)) * 3 * sizeof(float2);
 }
 
 hipError_t launch_rollout(const StepArgs& a, int groups, int block, bool spheres_only,
                           hipStream_t s) {
-  const void* f = rollout_kernel(spheres_only, block, a.max_n, a.w.min_dist);
-  const size_t shm = rollout_lds_bytes(a.max_stage, spheres_only, block, a.max_n);
+  const bool quad = a.quad != nullptr;
+  const bool out = a.traj || a.mask || a.forces;
+  const void* f = rollout_kernel(spheres_only, quad, block, a.max_n, a.w.min_dist, out);
+  const size_t shm = rollout_lds_bytes(a.max_stage, spheres_only, quad, block, a.max_n);
   StepArgs args = a;
   void* kargs[1] = {&args};
   return hipLaunchKernel(f, dim3(groups), dim3(block), kargs, shm, s);

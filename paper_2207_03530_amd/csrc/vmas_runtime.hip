@@ -56,6 +56,8 @@ struct Plan {
   int groups = 0;
   int max_stage = 0;
   int max_n = 0;  // largest environment of the plan
+  bool quad = false;          // quad schedule (d_quad), no lane records
+  QuadEnv* d_quad = nullptr;
   LaneRec* d_lanes = nullptr;
   int32_t* d_stage_off = nullptr;
   int32_t* d_stage = nullptr;
@@ -107,6 +109,7 @@ struct vmas_batch {
   int32_t* d_rows = nullptr;   // [P] candidate row of each pair slot, then [1] the count
   std::vector<Plan> plans;
   int cur = 0;
+  int lane_plan = 0;  // an entity-lane plan (kernels that need lane records)
   Plan back;  // adjoint plan: every entity has a lane
   // checkpoint workspace of the adjoint driver and the autotuner scratch
   float* d_ws = nullptr;
@@ -126,6 +129,8 @@ void free_plan(Plan& p) {
   if (p.d_stage_off) (void)hipFree(p.d_stage_off);
   if (p.d_stage) (void)hipFree(p.d_stage);
   if (p.d_maxn) (void)hipFree(p.d_maxn);
+  if (p.d_quad) (void)hipFree(p.d_quad);
+  p.d_quad = nullptr;
   p.d_maxn = nullptr;
   p.d_lanes = nullptr;
   p.d_stage_off = nullptr;
@@ -363,6 +368,48 @@ vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8
   return VMAS_OK;
 }
 
+// Builds the quad schedule (sphere-only batches; every environment has at
+// most 4 entities that move or rotate, at most 4 static collidable ones and
+// at most 32 entities); p.valid stays false when the batch does not qualify.
+vmas_status build_quad_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8_t>& flags,
+                            Plan& p) {
+  p.name = "quad/256";
+  p.block = 256;
+  p.quad = true;
+  p.valid = false;
+  if (!b->spheres_only) return VMAS_OK;
+  const int E = b->n_envs;
+  std::vector<QuadEnv> q(std::max(E, 1));
+  int max_static = 0;
+  for (int e = 0; e < E; ++e) {
+    const int o = h.off[e], n = h.off[e + 1] - o;
+    if (n > 32) return VMAS_OK;
+    QuadEnv& r = q[e];
+    r.agent_row = (int32_t)h.agent_off[e];
+    r.n_agents = h.nag[e];
+    for (int u = 0; u < 4; ++u) r.lane_loc[u] = r.stat_loc[u] = -1;
+    int nl = 0, nsx = 0;
+    for (int i = 0; i < n; ++i) {
+      const uint8_t f = flags[o + i];
+      if (f & (MOVABLE | ROTATABLE)) {
+        if (nl == 4) return VMAS_OK;
+        r.lane_loc[nl++] = (int8_t)i;
+      } else if (f & COLLIDABLE) {
+        if (nsx == 4) return VMAS_OK;
+        r.stat_loc[nsx++] = (int8_t)i;
+      }
+    }
+    max_static = std::max(max_static, nsx);
+  }
+  if ((int64_t)E * 4 > INT32_MAX - 256) return VMAS_OK;
+  vmas_status s = upload(&p.d_quad, q.data(), q.size());
+  if (s != VMAS_OK) return s;
+  p.groups = (int)(((int64_t)E * 4 + 255) / 256);
+  p.max_n = max_static;  // the quad kernels size their static slots by it
+  p.valid = E > 0;
+  return VMAS_OK;
+}
+
 StepArgs make_args(vmas_batch* b, const Plan& p) {
   StepArgs a{};
   a.ent = b->d_ent;
@@ -376,6 +423,9 @@ StepArgs make_args(vmas_batch* b, const Plan& p) {
   a.grp_maxn = p.d_maxn;
   a.max_stage = p.max_stage;
   a.max_n = p.max_n;
+  a.quad = p.quad ? p.d_quad : nullptr;
+  a.env_off = b->d_env_off;
+  a.n_envs = b->n_envs;
   a.w = b->w;
   return a;
 }
@@ -579,6 +629,16 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
     return fail(VMAS_ERR_UNSUPPORTED, "an environment is too large to stage in LDS");
   }
   b->cur = first_valid;
+  b->lane_plan = first_valid;
+  {
+    Plan p;
+    if ((s = build_quad_plan(b, h, flags, p)) != VMAS_OK) {
+      free_plan(p);
+      free_batch(b);
+      return s;
+    }
+    b->plans.push_back(p);
+  }
   {
     int need = 64;
     for (int e = 0; e < E; ++e)
@@ -704,10 +764,11 @@ vmas_status vmas_rollout_graph(vmas_batch* b, float* state, const float* actions
   const bool drawn = actions == nullptr;
   void* args[1] = {&a};
   hipKernelNodeParams kp{};
-  kp.func = const_cast<void*>(rollout_kernel(b->spheres_only, p.block, p.max_n, b->w.min_dist));
+  kp.func = const_cast<void*>(
+      rollout_kernel(b->spheres_only, p.quad, p.block, p.max_n, b->w.min_dist, false));
   kp.gridDim = dim3(p.groups);
   kp.blockDim = dim3(p.block);
-  kp.sharedMemBytes = (unsigned)rollout_lds_bytes(p.max_stage, b->spheres_only, p.block, p.max_n);
+  kp.sharedMemBytes = (unsigned)rollout_lds_bytes(p.max_stage, b->spheres_only, p.quad, p.block, p.max_n);
   kp.kernelParams = args;
   kp.extra = nullptr;
   if (!b->gexec || b->graph_T != T || b->graph_plan != b->cur || b->graph_drawn != drawn) {
@@ -930,7 +991,7 @@ vmas_status vmas_step_surrogate(vmas_batch* b, vmas_mlp* mlp, float* state, cons
     vmas_status st = mlp_forward_counted(mlp, b->d_feat, b->P, count, b->d_yhat, s);
     if (st != VMAS_OK) return st;
   }
-  const Plan& p = b->plans[b->cur];
+  const Plan& p = b->plans[b->lane_plan];  // lane records are needed
   if (p.groups == 0) return VMAS_OK;
   StepArgs a = make_args(b, p);
   a.state = state;
