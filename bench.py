@@ -92,8 +92,8 @@ def cpu_baseline(w, acts, T):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--envs", type=int, default=30000)
     ap.add_argument("--T", type=int, default=100)
     ap.add_argument("--graph", action="store_true", help="replay a captured hipGraph")
@@ -119,7 +119,7 @@ def main():
     batch = binding.vmas_create_batch(w, 0)
     state = torch.as_tensor(w.state0).to(dev).contiguous()
     acts = torch.as_tensor(acts_np).to(dev).contiguous()
-    plan = batch.autotune(state, 10)
+    plan = batch.autotune(state, T)
     stream = torch.cuda.current_stream(dev)
 
     if args.pmc_calibration:
@@ -131,11 +131,11 @@ def main():
         print(f"calibration copy: {src.numel() * 4} bytes read and written per launch",
               file=sys.stderr, flush=True)
 
-    def one_step():
-        if args.drawn_actions:
-            batch.rollout(state, None, T=T, seed=w.seed, graph=args.graph)
-        else:
-            batch.rollout(state, acts, graph=args.graph)
+    # one step = one T-step rollout of the whole batch; arguments marshalled once
+    if args.drawn_actions:
+        one_step = batch.prepare_rollout(state, None, T=T, seed=w.seed, graph=args.graph)
+    else:
+        one_step = batch.prepare_rollout(state, acts, graph=args.graph)
 
     for _ in range(args.warmup):
         one_step()

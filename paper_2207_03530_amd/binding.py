@@ -263,6 +263,30 @@ class Batch:
             _dptr(grad_state, 6 * self.N, f, "grad_state_t"),
             _dptr(grad_actions, 2 * self.A, f, "grad_actions_t"), _stream(self.device)))
 
+    def prepare_rollout(self, state, actions=None, T: Optional[int] = None, seed: int = 0,
+                        t0: int = 0, graph: bool = False):
+        """A zero-argument callable that runs vmas_rollout (or
+        vmas_rollout_graph) on the given tensors and the current stream.
+        The arguments are checked and marshalled here, once; each call is one
+        C call, for tight loops where per-call Python work would leave the
+        GPU waiting. The tensors must stay alive while the callable is used."""
+        import torch
+        if actions is not None:
+            T = actions.shape[0] if T is None else T
+            _dptr(actions, T * 2 * self.A, torch.float32, "actions")
+        if T is None:
+            raise ValueError("T is required when actions are drawn in the kernel")
+        fn = lib().vmas_rollout_graph if graph else lib().vmas_rollout
+        args = (self.handle, _dptr(state, 6 * self.N, torch.float32, "state"),
+                _dptr(actions, None, torch.float32, "actions"), ctypes.c_uint64(seed),
+                ctypes.c_int32(t0), ctypes.c_int32(T), None, None, _stream(self.device))
+
+        def run():
+            st = fn(*args)
+            if st != VMAS_OK:
+                _check(st)
+        return run
+
     def rollout_backward(self, state0, actions, grad_final, ckpt_every: int = 10,
                          grad_state0=None, grad_actions=None) -> None:
         import torch

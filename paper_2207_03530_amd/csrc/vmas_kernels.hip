@@ -42,7 +42,20 @@ __device__ __forceinline__ float draw_sym(uint64_t key, uint64_t idx) {
   return (float)(k - (1 << 23)) * (1.0f / 8388608.0f);
 }
 
+// Radius of the circle about an entity's centre that holds the whole shape
+// (sphere r, box half diagonal, segment half length).
+__device__ __forceinline__ float bounding_radius(int shape, float d0, float d1) {
+  if (shape == SPHERE) return d0;
+  if (shape == BOX) return 0.5f * sqrtf(d0 * d0 + d1 * d1);
+  return 0.5f * d0;
+}
+
 // Persistent rollout: T steps of every environment of the group.
+// Broad phase: a partner whose bounding circle stays farther than d_min plus
+// a safety margin (1e-4 + 1e-5 (|x| + |y|), far above the FP32 error of the
+// narrow-phase distance) from the lane's own cannot be in contact, so only
+// the other partners run the narrow phase -- in partner order, with the
+// same arithmetic, hence with the results of testing every partner.
 template <bool SPH, int MAXB>
 __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
   extern __shared__ float4 lds[];
@@ -50,6 +63,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
   float4* buf0 = lds;
   float4* buf1 = lds + E;
   float4* stat = lds + 2 * E;
+  float* brad = reinterpret_cast<float*>(lds + 3 * E);  // bounding radius, NaN: not collidable
   const int g = blockIdx.x, l = threadIdx.x, B = blockDim.x;
   const int N = a.w.N;
   const int s0 = a.stage_off[g], ns = a.stage_off[g + 1] - s0;
@@ -62,6 +76,8 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
     buf1[s] = P;
     const EntParam p = a.ent[e];
     stat[s] = make_float4(p.d0, p.d1, p.rho, __int_as_float(p.sf));
+    brad[s] = ((p.sf >> 8) & COLLIDABLE) ? bounding_radius(p.sf & 0xff, p.d0, p.d1)
+                                         : __int_as_float(0x7fc00000);
   }
   const LaneRec r = a.lanes[(size_t)g * B + l];
   const bool act = r.ent >= 0;
@@ -122,23 +138,38 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
       self.d0 = p.d0;
       self.d1 = p.d1;
       self.shape = SPH ? SPHERE : shape;
-      for (int q = r.lo; q < r.hi; ++q) {
-        if (q == r.slot) continue;
-        const float4 S = stat[q];
-        const int of = (__float_as_int(S.w) >> 8) & 0xff;
-        if (!(of & COLLIDABLE)) continue;
-        const int b = q - r.lo;
-        if (!SPH && p.excl != -1 && excluded(p.excl, b)) continue;
-        const float4 P = cur[q];
-        const bool hit = pair_force<SPH>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
-        if (mk && hit) {
-          // The lower index writes the slot, or the higher one when the
-          // lower entity has no lane (neither movable nor rotatable).
-          const bool other_active = (of & (MOVABLE | ROTATABLE)) != 0;
-          if (myloc < b || !other_active) {
-            const int ia = min(myloc, b), ib = max(myloc, b);
-            const int64_t idx = (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
-            mk[a.pair_off[r.env] + idx] = 1;
+      const float rs = bounding_radius(self.shape, p.d0, p.d1);
+      const float reach = w.min_dist + 1e-4f + 1e-5f * (fabsf(x) + fabsf(y));
+      for (int base = 0; base < nloc; base += 32) {
+        const int cnt = min(32, nloc - base);
+        uint32_t cand = 0;
+        for (int u = 0; u < cnt; ++u) {
+          const int q = r.lo + base + u;
+          const float4 P = cur[q];
+          const float dx = x - P.x, dy = y - P.y;
+          const float lim = (rs + brad[q]) + reach;
+          cand |= (dx * dx + dy * dy <= lim * lim ? 1u : 0u) << u;
+        }
+        if (myloc >= base && myloc < base + 32) cand &= ~(1u << (myloc - base));
+        while (cand) {
+          const int u = __builtin_ctz(cand);
+          cand &= cand - 1;
+          const int q = r.lo + base + u;
+          const int b = base + u;
+          const float4 S = stat[q];
+          const int of = (__float_as_int(S.w) >> 8) & 0xff;
+          if (!SPH && p.excl != -1 && excluded(p.excl, b)) continue;
+          const float4 P = cur[q];
+          const bool hit = pair_force<SPH>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
+          if (mk && hit) {
+            // The lower index writes the slot, or the higher one when the
+            // lower entity has no lane (neither movable nor rotatable).
+            const bool other_active = (of & (MOVABLE | ROTATABLE)) != 0;
+            if (myloc < b || !other_active) {
+              const int ia = min(myloc, b), ib = max(myloc, b);
+              const int64_t idx = (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
+              mk[a.pair_off[r.env] + idx] = 1;
+            }
           }
         }
       }
@@ -727,7 +758,7 @@ const void* rollout_kernel(bool spheres_only, bool quad, int block, int max_n, f
 
 size_t rollout_lds_bytes(int max_stage, bool spheres_only, bool quad, int block, int max_n) {
   if (quad) return 0;
-  if (!spheres_only) return (size_t)max_stage * 3 * sizeof(float4);
+  if (!spheres_only) return (size_t)max_stage * (3 * sizeof(float4) + sizeof(float));
   return (size_t)(max_stage + sph_pad(block, max_n)) * 3 * sizeof(float2);
 }
 

@@ -297,7 +297,7 @@ vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
       return (h.off[x + 1] - h.off[x]) > (h.off[y + 1] - h.off[y]);
     });
-  const int stage_cap = std::min(1360, std::max(4 * block, b->max_env));
+  const int stage_cap = std::min(1260, std::max(4 * block, b->max_env));  // 52 B of LDS per slot
   std::vector<std::vector<int>> groups;
   int lanes = 0, staged = 0;
   for (int e : order) {
