@@ -273,12 +273,17 @@ vmas_status vmas_pair_features(vmas_batch* batch, const float* state, float band
                                uint8_t* flags, void* stream);
 
 /* One step whose contact forces come from the surrogate network for every
- * candidate pair (bit 0 above), except that a pair whose predicted
- * penetration k log(expm1(|f|/(c k))) (the inverse of Eq. 2) exceeds
- * fallback_frac times its radius (sphere r; box / line half of the smaller
- * extent) takes the exact narrow phase and Eq. (2) force. The surrogate
- * gives no torque. forces: device [3][N] or NULL; n_fallback: device int32
- * counter or NULL (incremented by the number of fallback pair sides). */
+ * candidate pair (bit 0 above), read through Eq. (2): a pair whose predicted
+ * penetration k log(expm1(|f|/(c k))) exceeds fallback_frac times its half
+ * size (sphere r; box half of the smaller side) takes the exact narrow phase
+ * and Eq. (2) force; otherwise f is replaced by the nearest force Eq. (2) can
+ * produce: 0 when |f| < F0/2, else f scaled up to at least F0 = c k ln 2 (the
+ * force at zero penetration). Pairs
+ * with a segment always take the exact narrow phase; joints are exact. The
+ * surrogate gives no torque. forces: device [3][N] or NULL; n_fallback:
+ * device int32 counter or NULL (incremented by the number of fallback pair
+ * sides). The first call allocates a workspace of P x 60 bytes. Errors:
+ * VMAS_ERR_INVALID_ARGUMENT (NULL handles, band < 0, 2^31 or more pair slots). */
 vmas_status vmas_step_surrogate(vmas_batch* batch, vmas_mlp* mlp, float* state,
                                 const float* actions, float band, float fallback_frac,
                                 float* forces, int32_t* n_fallback, void* stream);

@@ -149,13 +149,11 @@ hipError_t launch_pair_features(const float* state, const EntParam* ent, const i
                                 int n_envs, const WorldK& w, hipStream_t s);
 vmas_status mlp_forward_counted(vmas_mlp* m, const float* X, int64_t max_n, const int32_t* d_n,
                                 float* Y, hipStream_t s);
-hipError_t launch_candidate_features(const float* state, const EntParam* ent,
-                                     const int32_t* env_off, const int64_t* pair_off, int64_t P,
-                                     float band, float* feat, int32_t* row_of, int32_t* count,
-                                     int n_envs, const WorldK& w, hipStream_t s);
+hipError_t launch_candidate_features(const StepArgs& a, int groups, int block, float band,
+                                     float* feat, int32_t* row_of, int32_t* count, hipStream_t s);
 hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat, const int32_t* row_of,
-                                 float frac, int32_t* n_fallback, int groups, int block,
-                                 hipStream_t s);
+                                 float band, float frac, int32_t* n_fallback, int groups,
+                                 int block, hipStream_t s);
 
 // Host-side SplitMix64 key of (seed, stream): mix64(seed + (stream + 1) * golden).
 uint64_t action_key(uint64_t seed);

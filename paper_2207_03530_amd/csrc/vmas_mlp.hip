@@ -68,12 +68,28 @@ struct MlpArgs {
   const float* b3;           // [NO]
 };
 
-// Stages the three weight matrices of one network into LDS.
+// Stages the three weight matrices of one network into LDS, 8 BF16 values
+// (16 bytes) per load and store; every row length (16, 128) and LDS row
+// stride (LDI, LDH) is a multiple of 8 elements, so each access is aligned.
 __device__ void stage_weights(const MlpArgs& m, unsigned short* w1, unsigned short* w2,
                               unsigned short* w3) {
-  for (int i = threadIdx.x; i < NH * NIP; i += blockDim.x) w1[(i / NIP) * LDI + i % NIP] = m.W1[i];
-  for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) w2[(i / NH) * LDH + i % NH] = m.W2[i];
-  for (int i = threadIdx.x; i < NOP * NH; i += blockDim.x) w3[(i / NH) * LDH + i % NH] = m.W3[i];
+  using u4 = uint4;
+  const u4* g1 = reinterpret_cast<const u4*>(m.W1);
+  const u4* g2 = reinterpret_cast<const u4*>(m.W2);
+  const u4* g3 = reinterpret_cast<const u4*>(m.W3);
+  for (int i = threadIdx.x; i < NH * NIP / 8; i += blockDim.x) {
+    const int row = i / (NIP / 8), col = (i % (NIP / 8)) * 8;
+    *reinterpret_cast<u4*>(w1 + row * LDI + col) = g1[i];
+  }
+#pragma unroll 4
+  for (int i = threadIdx.x; i < NH * NH / 8; i += blockDim.x) {
+    const int row = i / (NH / 8), col = (i % (NH / 8)) * 8;
+    *reinterpret_cast<u4*>(w2 + row * LDH + col) = g2[i];
+  }
+  for (int i = threadIdx.x; i < NOP * NH / 8; i += blockDim.x) {
+    const int row = i / (NH / 8), col = (i % (NH / 8)) * 8;
+    *reinterpret_cast<u4*>(w3 + row * LDH + col) = g3[i];
+  }
 }
 
 // Forward pass over 64-row tiles. X [n][12] -> Y [n][2]; optionally the FP32
@@ -168,18 +184,20 @@ __global__ void __launch_bounds__(256) k_mlp_backward(MlpArgs m, const float* __
   __shared__ __attribute__((aligned(16))) unsigned short dyT[NOP * LDR], dz2T[NH * LDR], dz1T[NH * LDR];
   __shared__ __attribute__((aligned(16))) unsigned short h1T[NH * LDR], xT[NIP * LDR];
   __shared__ float bsum[4][NH + NH + NOP];
-  for (int i = threadIdx.x; i < NH * NIP; i += blockDim.x) {
-    const int o = i / NIP, k = i % NIP;
-    w1t[k * LDH + o] = m.W1[i];
-  }
-  for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) {
-    const int o = i / NH, k = i % NH;
-    w2t[k * LDH + o] = m.W2[i];
-  }
-  for (int i = threadIdx.x; i < NOP * NH; i += blockDim.x) {
-    const int o = i / NH, k = i % NH;
-    w3t[k * LDI + o] = m.W3[i];
-  }
+  // 8 consecutive weights of a row per 16-byte load, stored transposed
+  auto stage_t = [&](const unsigned short* W, int rows, int cols, unsigned short* dst, int ld) {
+    const uint4* g = reinterpret_cast<const uint4*>(W);
+    for (int i = threadIdx.x; i < rows * cols / 8; i += blockDim.x) {
+      const int o = i / (cols / 8), k0 = (i % (cols / 8)) * 8;
+      const uint4 v = g[i];
+      const unsigned short* e = reinterpret_cast<const unsigned short*>(&v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dst[(k0 + j) * ld + o] = e[j];
+    }
+  };
+  stage_t(m.W1, NH, NIP, w1t, LDH);
+  stage_t(m.W2, NH, NH, w2t, LDH);
+  stage_t(m.W3, NOP, NH, w3t, LDI);
   const int64_t row0 = (int64_t)blockIdx.x * ROWS;
   for (int i = threadIdx.x; i < ROWS * NH; i += blockDim.x) {
     const int r = i / NH, c = i % NH;

@@ -982,23 +982,24 @@ vmas_status vmas_step_surrogate(vmas_batch* b, vmas_mlp* mlp, float* state, cons
       return fail(VMAS_ERR_OUT_OF_MEMORY, "surrogate workspace: %s", hipGetErrorString(e));
   }
   if (forces) HIPCHK(launch_fill_f32(forces, 3 * (int64_t)b->N, 0.0f, s));
-  if (b->P > 0) {
-    // candidates' features into consecutive rows, the network on those rows only
-    int32_t* count = b->d_rows + b->P;
-    HIPCHK(launch_fill_i32(count, 1, 0, s));
-    HIPCHK(launch_candidate_features(state, b->d_ent, b->d_env_off, b->d_pair_off, b->P, band,
-                                     b->d_feat, b->d_rows, count, b->n_envs, b->w, s));
-    vmas_status st = mlp_forward_counted(mlp, b->d_feat, b->P, count, b->d_yhat, s);
-    if (st != VMAS_OK) return st;
-  }
   const Plan& p = b->plans[b->lane_plan];  // lane records are needed
   if (p.groups == 0) return VMAS_OK;
+  if (p.block > 256)
+    return fail(VMAS_ERR_UNSUPPORTED, "surrogate step: environments with more than 256 movers");
   StepArgs a = make_args(b, p);
   a.state = state;
   a.actions = actions;
   a.T = 1;
   a.forces = forces;
-  HIPCHK(launch_step_surrogate(a, b->d_yhat, b->d_rows, fallback_frac, n_fallback, p.groups,
+  if (b->P > 0) {
+    // candidates' features into consecutive rows, the network on those rows only
+    int32_t* count = b->d_rows + b->P;
+    HIPCHK(launch_fill_i32(count, 1, 0, s));
+    HIPCHK(launch_candidate_features(a, p.groups, p.block, band, b->d_feat, b->d_rows, count, s));
+    vmas_status st = mlp_forward_counted(mlp, b->d_feat, b->P, count, b->d_yhat, s);
+    if (st != VMAS_OK) return st;
+  }
+  HIPCHK(launch_step_surrogate(a, b->d_yhat, b->d_rows, band, fallback_frac, n_fallback, p.groups,
                                p.block, s));
   return VMAS_OK;
 }

@@ -7,8 +7,9 @@
 // angle of e (12 values of O(1) scale, invariant under rigid motions):
 //   |c_i - c_j| / L, g / Lg with g = |c_i - c_j| - R_i - R_j (R: bounding
 //   radius, sphere r, box half diagonal, line L/2), cos and sin of
-//   (theta_i - phi), cos and sin of (theta_j - phi), dims_i / L, dims_j / L,
-//   shape code of i and of j (sphere 0, box 0.5, line 1);
+//   (theta_i - phi), cos and sin of (theta_j - phi) (1 and 0 for a sphere,
+//   which has no orientation), dims_i / L, dims_j / L, shape code of i and
+//   of j (sphere 0, box 0.5, line 1);
 // L = 0.1, Lg = 0.01. Target: the Eq. (2) force on i in the pair frame
 // (along e, along the left normal of e) divided by c * Lf, Lf = 0.02 (zero
 // when the pair is not in contact). The gap feature is clamped below at -4
@@ -18,10 +19,10 @@
 // their bounding circles (sphere r, box half diagonal) come within `band` of
 // each other. A segment has no thickness, so the fallback rule (penetration
 // beyond half the smaller size) has no meaning for it: pairs with a segment
-// always take the exact narrow phase. The surrogate step
-// compacts the candidates' features into consecutive rows (one atomic per
-// wavefront; the row order varies between runs, the per-row network output
-// does not) so that the network runs on candidates only.
+// always take the exact narrow phase. The surrogate step compacts the
+// candidates' features into consecutive rows (atomics per wavefront; the row
+// order varies between runs, the per-row network output does not) so that
+// the network runs on candidates only.
 
 #include "vmas_geom.h"
 #include "vmas_internal.h"
@@ -50,6 +51,41 @@ __device__ __forceinline__ void pair_of(int q, int n, int* a, int* c) {
   *c = aa + 1 + (q - base);
 }
 
+// Network candidate decision of the pair (lo, hi), lo the lower local
+// index; eligibility (both collidable, not excluded) is the caller's. The
+// feature kernels and the surrogate step call it with the same arguments in
+// the same order, so they decide alike to the bit.
+__device__ __forceinline__ bool net_candidate(float xlo, float ylo, float rlo, int slo, float xhi,
+                                              float yhi, float rhi, int shi, float band) {
+  if (slo == LINE || shi == LINE) return false;
+  const float dx = xlo - xhi, dy = ylo - yhi;
+  const float reach = (rlo + rhi) + band;
+  return dx * dx + dy * dy <= reach * reach;
+}
+
+// The 12 features of the pair (i = lo, j = hi) into f.
+__device__ __forceinline__ void write_features(float* f, float xi, float yi, float ci, float sni,
+                                               float d0i, float d1i, int si, float xj, float yj,
+                                               float cj, float snj, float d0j, float d1j, int sj) {
+  const float dx = xi - xj, dy = yi - yj;
+  const float dist = sqrtf(dx * dx + dy * dy);
+  const float ex = dist > 0.0f ? dx / dist : 1.0f, ey = dist > 0.0f ? dy / dist : 0.0f;
+  const float Ri = bound_radius(si, d0i, d1i), Rj = bound_radius(sj, d0j, d1j);
+  f[0] = dist / FEAT_L;
+  f[1] = fmaxf((dist - (Ri + Rj)) / GAP_L, -4.0f);
+  // cos and sin of (theta - phi); a sphere has no orientation: (1, 0)
+  f[2] = si == SPHERE ? 1.0f : fmaf(ci, ex, sni * ey);
+  f[3] = si == SPHERE ? 0.0f : fmaf(sni, ex, -ci * ey);
+  f[4] = sj == SPHERE ? 1.0f : fmaf(cj, ex, snj * ey);
+  f[5] = sj == SPHERE ? 0.0f : fmaf(snj, ex, -cj * ey);
+  f[6] = d0i / FEAT_L;
+  f[7] = d1i / FEAT_L;
+  f[8] = d0j / FEAT_L;
+  f[9] = d1j / FEAT_L;
+  f[10] = 0.5f * (float)si;  // SPHERE 0, BOX 1, LINE 2
+  f[11] = 0.5f * (float)sj;
+}
+
 struct FeatArgs {
   const float* state;
   const EntParam* ent;
@@ -60,9 +96,7 @@ struct FeatArgs {
   float band;
   float* feat;              // [m][12]
   float* target;            // [m][2] or NULL
-  uint8_t* flags;           // [m]: 1 candidate, 2 exact contact (NULL in compact mode)
-  int32_t* row_of;          // compact mode: [m] feature row of each slot, -1 if no candidate
-  int32_t* count;           // compact mode: number of candidate rows (starts at 0)
+  uint8_t* flags;           // [m]: 1 candidate, 2 exact contact
   int n_envs;
   WorldK w;
 };
@@ -93,49 +127,23 @@ __global__ void k_pair_features(FeatArgs a) {
   const int si = pi.sf & 0xff, sj = pj.sf & 0xff, fi = (pi.sf >> 8) & 0xff, fj = (pj.sf >> 8) & 0xff;
   const float xi = a.state[i], yi = a.state[N + i], ti = a.state[4 * N + i];
   const float xj = a.state[j], yj = a.state[N + j], tj = a.state[4 * N + j];
-  float ci, sni, cj, snj;
-  sincosf(ti, &sni, &ci);
-  sincosf(tj, &snj, &cj);
-  const V2T<float> dl = {xi - xj, yi - yj};
-  const float dist = sqrtf(vdot(dl, dl));
-  const V2T<float> ex = dist > 0.0f ? V2T<float>{dl.x / dist, dl.y / dist} : V2T<float>{1.0f, 0.0f};
+  float ci = 1.0f, sni = 0.0f, cj = 1.0f, snj = 0.0f;
+  if (si != SPHERE) sincosf(ti, &sni, &ci);
+  if (sj != SPHERE) sincosf(tj, &snj, &cj);
   const float Ri = bound_radius(si, pi.d0, pi.d1), Rj = bound_radius(sj, pj.d0, pj.d1);
   const bool eligible = (fi & COLLIDABLE) && (fj & COLLIDABLE) &&
                         ((fi | fj) & (MOVABLE | ROTATABLE)) && !excluded(pi.excl, lc) &&
                         !excluded(pj.excl, la);
-  const bool cand = eligible && si != LINE && sj != LINE && dist <= Ri + Rj + a.band;
-  int64_t row = r;
-  if (a.row_of) {
-    // compact mode: candidates take consecutive rows, one atomic per wavefront
-    const uint64_t bal = __ballot(cand);
-    const int lane = __lane_id();
-    const int leader = __ffsll((unsigned long long)bal) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(a.count, __popcll(bal));
-    base = __shfl(base, leader < 0 ? 0 : leader);
-    const int off = __popcll(bal & ((1ull << lane) - 1ull));
-    a.row_of[r] = cand ? base + off : -1;
-    if (!cand) return;
-    row = base + off;
-  }
-  float* f = a.feat + row * 12;
-  f[0] = dist / FEAT_L;
-  f[1] = fmaxf((dist - (Ri + Rj)) / GAP_L, -4.0f);
-  f[2] = fmaf(ci, ex.x, sni * ex.y);    // cos(theta_i - phi)
-  f[3] = fmaf(sni, ex.x, -ci * ex.y);   // sin(theta_i - phi)
-  f[4] = fmaf(cj, ex.x, snj * ex.y);
-  f[5] = fmaf(snj, ex.x, -cj * ex.y);
-  f[6] = pi.d0 / FEAT_L;
-  f[7] = pi.d1 / FEAT_L;
-  f[8] = pj.d0 / FEAT_L;
-  f[9] = pj.d1 / FEAT_L;
-  f[10] = 0.5f * (float)si;  // SPHERE 0, BOX 1, LINE 2
-  f[11] = 0.5f * (float)sj;
-  if (a.row_of) return;
+  const bool cand = eligible && net_candidate(xi, yi, Ri, si, xj, yj, Rj, sj, a.band);
+  write_features(a.feat + r * 12, xi, yi, ci, sni, pi.d0, pi.d1, si, xj, yj, cj, snj, pj.d0, pj.d1,
+                 sj);
+  const float dxe = xi - xj, dye = yi - yj;
+  const float dist = sqrtf(dxe * dxe + dye * dye);
+  const V2T<float> ex = dist > 0.0f ? V2T<float>{dxe / dist, dye / dist} : V2T<float>{1.0f, 0.0f};
   uint8_t fl = cand ? 1 : 0;
   float tx = 0.0f, ty = 0.0f;
   if (cand) {
-    GeoT<float> gi, gj;
+    GeoT<float> gi;
     gi.c = {xi, yi};
     gi.cs = ci;
     gi.sn = sni;
@@ -159,16 +167,113 @@ __global__ void k_pair_features(FeatArgs a) {
   }
 }
 
+struct CandArgs {
+  StepArgs s;          // plan and state
+  float band;
+  float* feat;         // [P][12] candidate rows
+  int32_t* row_of;     // [P] row of each candidate slot (other slots untouched)
+  int32_t* count;      // number of candidate rows (starts at 0)
+};
+
+// Candidate features for the surrogate step, in consecutive rows: lane per
+// entity that can move or rotate, poses staged in LDS as in the exact step.
+// A pair is written by its lower entity, or by the higher one when the lower
+// one has no lane. Rows: each lane counts its candidates, the workgroup
+// scans the counts in LDS and takes its block of rows with one atomic, then
+// every lane writes its candidates in partner order.
+__global__ void __launch_bounds__(256) k_cand_features(CandArgs ca) {
+  const StepArgs& a = ca.s;
+  extern __shared__ float4 lds[];
+  __shared__ int scan[256];
+  __shared__ int gbase;
+  const int E = a.max_stage;
+  float4* pose = lds;
+  float4* stat = lds + E;
+  const int g = blockIdx.x, l = threadIdx.x, B = blockDim.x;
+  const int N = a.w.N;
+  const int s0 = a.stage_off[g], ns = a.stage_off[g + 1] - s0;
+  for (int s = l; s < ns; s += B) {
+    const int e = a.stage[s0 + s];
+    const EntParam p = a.ent[e];
+    float cs = 1.0f, sn = 0.0f;
+    if ((p.sf & 0xff) != SPHERE) sincosf(a.state[4 * N + e], &sn, &cs);
+    pose[s] = make_float4(a.state[e], a.state[N + e], cs, sn);
+    stat[s] = make_float4(p.d0, p.d1, p.rho, __int_as_float(p.sf));
+  }
+  const LaneRec r = a.lanes[(size_t)g * B + l];
+  __syncthreads();
+  EntParam p{};
+  p.excl = -1;
+  if (r.ent >= 0) p = a.ent[r.ent];
+  const int shape = p.sf & 0xff;
+  const bool live = r.ent >= 0 && ((p.sf >> 8) & COLLIDABLE);
+  const float4 me = live ? pose[r.slot] : make_float4(0.0f, 0.0f, 1.0f, 0.0f);
+  const float rme = bound_radius(shape, p.d0, p.d1);
+  const int myloc = r.slot - r.lo, nloc = r.hi - r.lo;
+  // whether partner slot q is a candidate written by this lane
+  auto mine = [&](int q) {
+    const int b = q - r.lo;
+    if (b == myloc) return false;
+    const float4 S = stat[q];
+    const int so = __float_as_int(S.w) & 0xff, of = (__float_as_int(S.w) >> 8) & 0xff;
+    if (!(myloc < b || !(of & (MOVABLE | ROTATABLE)))) return false;
+    if (!(of & COLLIDABLE) || (p.excl != -1 && excluded(p.excl, b))) return false;
+    const float4 P = pose[q];
+    const float ro = bound_radius(so, S.x, S.y);
+    return myloc < b ? net_candidate(me.x, me.y, rme, shape, P.x, P.y, ro, so, ca.band)
+                     : net_candidate(P.x, P.y, ro, so, me.x, me.y, rme, shape, ca.band);
+  };
+  int cnt = 0;
+  if (live)
+    for (int q = r.lo; q < r.hi; ++q) cnt += mine(q) ? 1 : 0;
+  // inclusive scan of the lane counts over the workgroup
+  scan[l] = cnt;
+  __syncthreads();
+  for (int off = 1; off < B; off <<= 1) {
+    const int v = l >= off ? scan[l - off] : 0;
+    __syncthreads();
+    scan[l] += v;
+    __syncthreads();
+  }
+  if (l == B - 1) gbase = scan[B - 1] > 0 ? atomicAdd(ca.count, scan[B - 1]) : 0;
+  __syncthreads();
+  if (!live || cnt == 0) return;
+  int row = gbase + scan[l] - cnt;
+  const int64_t poff = a.pair_off[r.env];
+  for (int q = r.lo; q < r.hi; ++q) {
+    if (!mine(q)) continue;
+    const int b = q - r.lo;
+    const float4 P = pose[q];
+    const float4 S = stat[q];
+    const int so = __float_as_int(S.w) & 0xff;
+    const int ia = min(myloc, b), ib = max(myloc, b);
+    const int64_t slot = poff + (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
+    ca.row_of[slot] = row;
+    float* f = ca.feat + (int64_t)row * 12;
+    if (myloc < b)
+      write_features(f, me.x, me.y, me.z, me.w, p.d0, p.d1, shape, P.x, P.y, P.z, P.w, S.x, S.y, so);
+    else
+      write_features(f, P.x, P.y, P.z, P.w, S.x, S.y, so, me.x, me.y, me.z, me.w, p.d0, p.d1, shape);
+    ++row;
+  }
+}
+
 struct SurArgs {
   StepArgs s;             // plan, state, actions (T = 1), forces
   const float* yhat;      // [rows][2] MLP outputs (force on lo in the pair frame / (c Lf))
-  const int32_t* row_of;  // [P] row of each candidate slot in yhat, -1 if no candidate
+  const int32_t* row_of;  // [P] row of each candidate slot in yhat (read for candidates only)
+  float band;             // candidate reach, as given to the feature kernel
   float fallback_frac;    // exact fallback when predicted penetration > frac * r
   int32_t* n_fallback;    // device counter, or NULL
 };
 
 // One step with surrogate contact forces (lane per entity that can move or
-// rotate, poses staged in LDS as in the exact step).
+// rotate, poses staged in LDS as in the exact step). The network's force f is
+// read through Eq. (2): where its penetration k log(expm1(|f| / (c k))) is
+// beyond fallback_frac times the smaller half size, the exact pair force is
+// used instead; otherwise f is replaced by the nearest force Eq. (2) can
+// produce, 0 when |f| < F0 / 2 and at least F0 = c k ln 2 (the force at zero
+// penetration) along f otherwise.
 __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
   const StepArgs& a = sa.s;
   extern __shared__ float4 lds[];
@@ -180,10 +285,10 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
   const int s0 = a.stage_off[g], ns = a.stage_off[g + 1] - s0;
   for (int s = l; s < ns; s += B) {
     const int e = a.stage[s0 + s];
-    float cs, sn;
-    sincosf(a.state[4 * N + e], &sn, &cs);
-    pose[s] = make_float4(a.state[e], a.state[N + e], cs, sn);
     const EntParam p = a.ent[e];
+    float cs = 1.0f, sn = 0.0f;
+    if ((p.sf & 0xff) != SPHERE) sincosf(a.state[4 * N + e], &sn, &cs);
+    pose[s] = make_float4(a.state[e], a.state[N + e], cs, sn);
     stat[s] = make_float4(p.d0, p.d1, p.rho, __int_as_float(p.sf));
   }
   const LaneRec r = a.lanes[(size_t)g * B + l];
@@ -196,8 +301,8 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
   float th = a.state[4 * N + e], om = a.state[5 * N + e];
   const EntParam p = a.ent[e];
   const int shape = p.sf & 0xff, fl = (p.sf >> 8) & 0xff;
-  float cs, sn;
-  sincosf(th, &sn, &cs);
+  float cs = 1.0f, sn = 0.0f;
+  if (shape != SPHERE) sincosf(th, &sn, &cs);
   float fx = p.mgx, fy = p.mgy, tq = 0.0f;
   if (r.agent >= 0) {
     fx += a.actions[2 * (size_t)r.agent];
@@ -205,6 +310,8 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
   }
   const int myloc = r.slot - r.lo, nloc = r.hi - r.lo;
   const float FS = w.ck * w.inv_k * FORCE_L;  // c Lf
+  const float rme = bound_radius(shape, p.d0, p.d1);
+  const float F0 = w.ck * 0.69314718f;  // Eq. (2) at zero penetration: c k ln 2
   int fallbacks = 0;
   if (fl & COLLIDABLE) {
     GeoT<float> self;
@@ -221,15 +328,19 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
       const int64_t slot = a.pair_off[r.env] + (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
       const float4 P = pose[q];
       const float4 S = stat[q];
-      if (shape == LINE || (__float_as_int(S.w) & 0xff) == LINE) {
+      const int so = __float_as_int(S.w) & 0xff, of = (__float_as_int(S.w) >> 8) & 0xff;
+      if (!(of & COLLIDABLE) || (p.excl != -1 && excluded(p.excl, b))) continue;
+      if (shape == LINE || so == LINE) {
         // segments: exact narrow phase (same eligibility as the exact step)
-        const int of = (__float_as_int(S.w) >> 8) & 0xff;
-        if ((of & COLLIDABLE) && !(p.excl != -1 && excluded(p.excl, b)))
-          pair_force<false>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
+        pair_force<false>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
         continue;
       }
+      // the candidate decision of the feature kernel, repeated bit for bit
+      const float ro = bound_radius(so, S.x, S.y);
+      const bool cand = myloc < b ? net_candidate(x, y, rme, shape, P.x, P.y, ro, so, sa.band)
+                                  : net_candidate(P.x, P.y, ro, so, x, y, rme, shape, sa.band);
+      if (!cand) continue;
       const int row = sa.row_of[slot];
-      if (row < 0) continue;
       // surrogate force on lo, in the pair frame -> world
       const float hx = sa.yhat[2 * (int64_t)row] * FS, hy = sa.yhat[2 * (int64_t)row + 1] * FS;
       const float sgn = myloc < b ? 1.0f : -1.0f;  // e points from hi to lo
@@ -240,18 +351,23 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
       // predicted penetration from the inverse of Eq. (2): k log(expm1(|f| / (c k)))
       const float mag = sqrtf(flo.x * flo.x + flo.y * flo.y);
       const float pen = mag > 0.0f ? logf(expm1f(mag / w.ck)) / w.inv_k : -INFINITY;
-      const int so = __float_as_int(S.w) & 0xff;
       const float rr = fminf(shape == SPHERE ? p.d0 : 0.5f * fminf(p.d0, shape == BOX ? p.d1 : p.d0),
                              so == SPHERE ? S.x : 0.5f * fminf(S.x, so == BOX ? S.y : S.x));
       if (pen > sa.fallback_frac * rr) {
         ++fallbacks;
         pair_force<false>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
-      } else if (myloc < b) {
-        fx += flo.x;
-        fy += flo.y;
+        continue;
+      }
+      // nearest force Eq. (2) can produce: 0, or at least the onset force
+      // F0 = c k ln 2 (zero penetration), along the predicted direction
+      if (!(mag >= 0.5f * F0)) continue;
+      const float sc = mag < F0 ? F0 / mag : 1.0f;
+      if (myloc < b) {
+        fx = fmaf(sc, flo.x, fx);
+        fy = fmaf(sc, flo.y, fy);
       } else {
-        fx -= flo.x;
-        fy -= flo.y;
+        fx = fmaf(-sc, flo.x, fx);
+        fy = fmaf(-sc, flo.y, fy);
       }
     }
   }
@@ -309,27 +425,24 @@ hipError_t launch_pair_features(const float* state, const EntParam* ent, const i
                                 float band, float* feat, float* target, uint8_t* flags,
                                 int n_envs, const WorldK& w, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  FeatArgs a{state, ent, env_off, pair_off, slots, m, band, feat, target, flags, nullptr, nullptr,
-             n_envs, w};
+  FeatArgs a{state, ent, env_off, pair_off, slots, m, band, feat, target, flags, n_envs, w};
   hipLaunchKernelGGL(k_pair_features, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_candidate_features(const float* state, const EntParam* ent,
-                                     const int32_t* env_off, const int64_t* pair_off, int64_t P,
-                                     float band, float* feat, int32_t* row_of, int32_t* count,
-                                     int n_envs, const WorldK& w, hipStream_t s) {
-  if (P <= 0) return hipSuccess;
-  FeatArgs a{state, ent, env_off, pair_off, nullptr, P, band, feat, nullptr, nullptr, row_of,
-             count, n_envs, w};
-  hipLaunchKernelGGL(k_pair_features, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, a);
+hipError_t launch_candidate_features(const StepArgs& a, int groups, int block, float band,
+                                     float* feat, int32_t* row_of, int32_t* count, hipStream_t s) {
+  if (groups <= 0) return hipSuccess;
+  CandArgs ca{a, band, feat, row_of, count};
+  const size_t shm = (size_t)a.max_stage * 2 * sizeof(float4);
+  hipLaunchKernelGGL(k_cand_features, dim3(groups), dim3(block), shm, s, ca);
   return hipGetLastError();
 }
 
 hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat, const int32_t* row_of,
-                                 float frac, int32_t* n_fallback, int groups, int block,
-                                 hipStream_t s) {
-  SurArgs sa{a, yhat, row_of, frac, n_fallback};
+                                 float band, float frac, int32_t* n_fallback, int groups,
+                                 int block, hipStream_t s) {
+  SurArgs sa{a, yhat, row_of, band, frac, n_fallback};
   const size_t shm = (size_t)a.max_stage * 2 * sizeof(float4);
   hipLaunchKernelGGL(k_step_surrogate, dim3(groups), dim3(block), shm, s, sa);
   return hipGetLastError();

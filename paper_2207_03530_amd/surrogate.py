@@ -86,21 +86,25 @@ def make_dataset(world, T: int, stride: int, max_samples: int, seed: int = 0, de
 
 
 def train(mlp: "B.Mlp", X, Y, epochs: int, batch: int = 8192, lr: float = 2e-3,
-          lr_final: float = 1e-4, log=None):
-    """Adam over shuffled minibatches, learning rate decayed geometrically
-    from lr to lr_final; returns the per-epoch mean loss."""
+          lr_final: float = 1e-4, seed: int = 0, log=None):
+    """Adam over minibatches reshuffled every epoch (seeded), learning rate
+    decayed geometrically from lr to lr_final; returns the per-epoch mean loss."""
     import torch
     n = X.shape[0]
     nb = n // batch
     loss = torch.zeros(1, device=X.device)
+    gen = torch.Generator(device=X.device)
+    gen.manual_seed(seed)
     hist = []
     steps = epochs * nb
     k = 0
     for ep in range(epochs):
+        order = torch.randperm(n, device=X.device, generator=gen)
         acc = torch.zeros(1, device=X.device)
         for q in range(nb):
+            idx = order[q * batch:(q + 1) * batch]
             rate = lr * (lr_final / lr) ** (k / max(1, steps - 1))
-            mlp.train_step(X[q * batch:(q + 1) * batch], Y[q * batch:(q + 1) * batch], rate, loss)
+            mlp.train_step(X[idx], Y[idx], rate, loss)
             acc += loss
             k += 1
         hist.append(float(acc.item()) / max(1, nb))
@@ -109,7 +113,20 @@ def train(mlp: "B.Mlp", X, Y, epochs: int, batch: int = 8192, lr: float = 2e-3,
     return hist
 
 
-def contact_force_error(world, mlp: "B.Mlp", steps: int = 5, device: int = 0):
+def training_set(parts, seed: int = 0):
+    """Concatenates (X, Y) datasets and shuffles the rows with a seeded
+    generator."""
+    import torch
+    X = torch.cat([p[0] for p in parts])
+    Y = torch.cat([p[1] for p in parts])
+    gen = torch.Generator(device=X.device)
+    gen.manual_seed(seed)
+    perm = torch.randperm(X.shape[0], device=X.device, generator=gen)
+    return X[perm].contiguous(), Y[perm].contiguous()
+
+
+def contact_force_error(world, mlp: "B.Mlp", steps: int = 5, device: int = 0,
+                        fallback: float = FALLBACK):
     """Normwise relative error ||F_sur - F||_2 / ||F||_2 of the contact forces
     (total force minus action and gravity) of the surrogate step against the
     exact step, from the same states along an exact trajectory; also the
@@ -129,7 +146,7 @@ def contact_force_error(world, mlp: "B.Mlp", steps: int = 5, device: int = 0):
         s_exact = st.clone()
         b.step(s_exact, acts[t], None, fe)
         s_sur = st.clone()
-        b.step_surrogate(mlp, s_sur, acts[t], BAND, FALLBACK, fs, nfb)
+        b.step_surrogate(mlp, s_sur, acts[t], BAND, fallback, fs, nfb)
         torch.cuda.synchronize()
         Fe = fe.view(3, N)[0:2].clone()
         Fs = fs.view(3, N)[0:2].clone()
@@ -142,7 +159,7 @@ def contact_force_error(world, mlp: "B.Mlp", steps: int = 5, device: int = 0):
     return errs, fbs
 
 
-def time_steps(world, mlp: "B.Mlp", reps: int = 20, device: int = 0):
+def time_steps(world, mlp: "B.Mlp", reps: int = 20, device: int = 0, fallback: float = FALLBACK):
     """Mean milliseconds of one exact step and of one surrogate step."""
     import torch
     dev = torch.device("cuda", device)
@@ -151,7 +168,7 @@ def time_steps(world, mlp: "B.Mlp", reps: int = 20, device: int = 0):
     st = torch.as_tensor(world.state0).to(dev).contiguous()
     out = {}
     for name, fn in (("exact", lambda s: b.step(s, act)),
-                     ("surrogate", lambda s: b.step_surrogate(mlp, s, act, BAND, FALLBACK))):
+                     ("surrogate", lambda s: b.step_surrogate(mlp, s, act, BAND, fallback))):
         s = st.clone()
         for _ in range(3):
             fn(s)

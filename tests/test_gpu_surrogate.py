@@ -42,9 +42,10 @@ def test_pair_features_and_targets():
         return np.where(w.shape[q] == 0, w.dims[q, 0],
                         np.where(w.shape[q] == 1, 0.5 * np.hypot(w.dims[q, 0], w.dims[q, 1]),
                                  0.5 * w.dims[q, 0]))
+    sph_i, sph_j = w.shape[I] == 0, w.shape[J] == 0      # spheres have no orientation
     ref = np.stack([dist / FEAT_L, np.maximum((dist - bound(I) - bound(J)) / GAP_L, -4.0),
-                    np.cos(s[4, I] - phi), np.sin(s[4, I] - phi),
-                    np.cos(s[4, J] - phi), np.sin(s[4, J] - phi),
+                    np.where(sph_i, 1.0, np.cos(s[4, I] - phi)), np.where(sph_i, 0.0, np.sin(s[4, I] - phi)),
+                    np.where(sph_j, 1.0, np.cos(s[4, J] - phi)), np.where(sph_j, 0.0, np.sin(s[4, J] - phi)),
                     w.dims[I, 0] / FEAT_L, w.dims[I, 1] / FEAT_L, w.dims[J, 0] / FEAT_L,
                     w.dims[J, 1] / FEAT_L, 0.5 * w.shape[I], 0.5 * w.shape[J]], 1)
     np.testing.assert_allclose(feat, ref, rtol=2e-5, atol=3e-5)
@@ -97,18 +98,23 @@ def test_surrogate_step_with_full_fallback_is_the_exact_step(world):
 
 @pytest.fixture(scope="module")
 def trained():
-    """Surrogate trained on 10M pair samples of mixed-shape rollouts
-    (16,384 environments of 16 spheres + 4 boxes + 8 lines + 2 joints)."""
+    """Surrogate trained on 10M pair samples: 6M from mixed-shape rollouts
+    (16,384 environments of 16 spheres + 4 boxes + 8 lines + 2 joints) and
+    4M from sphere rollouts (65,536 environments of 16 spheres, r = 0.03,
+    another seed than the evaluation batch)."""
     import time
     from paper_2207_03530_amd import binding as B, surrogate as S
     t = time.time()
-    X, Y = S.make_dataset(W.mixed(16384, seed=21), T=600, stride=1, max_samples=10_000_000)
+    X, Y = S.training_set([
+        S.make_dataset(W.mixed(16384, seed=21), T=600, stride=1, max_samples=6_000_000),
+        S.make_dataset(W.uneven(65536, lo=16, hi=16, radius=0.03, seed=22), T=300, stride=1,
+                       max_samples=4_000_000)])
     t_data = time.time() - t
     nv = X.shape[0] // 20                     # held out
     Xv, Yv, X, Y = X[:nv], Y[:nv], X[nv:], Y[nv:]
     net = B.Mlp(seed=0)
     t = time.time()
-    hist = S.train(net, X, Y, epochs=100, batch=8192, lr=3e-3, lr_final=3e-5)
+    hist = S.train(net, X, Y, epochs=300, batch=8192, lr=3e-3, lr_final=1e-5)
     torch.cuda.synchronize()
     t_train = time.time() - t
     Yh = torch.zeros_like(Yv)
@@ -128,17 +134,28 @@ def trained():
 
 def test_surrogate_force_error_and_speed(trained):
     """65,536 environments x 16 sphere agents: contact-force error of the
-    surrogate step against the exact step, and both step times."""
+    surrogate step against the exact step over 5 steps of an exact
+    trajectory, and both step times, at the fallback rule's 0.5 r and at
+    stricter fractions (more pairs on the exact path): the speed at a fixed
+    error of 1e-2 is that of the largest fraction that meets it."""
     from paper_2207_03530_amd import surrogate as S
     net, hist = trained
     assert hist[-1] < hist[0]
     w = S.inference_world(65536)
-    errs, fbs = S.contact_force_error(w, net, steps=5)
-    times = S.time_steps(w, net)
-    print(f"surrogate on 65536x16 spheres: rel force err per step {np.round(errs, 4)}, "
-          f"fallback pair sides {fbs}, exact {times['exact']:.3f} ms, surrogate "
-          f"{times['surrogate']:.3f} ms, speedup {times['exact'] / times['surrogate']:.3f}")
-    assert np.max(errs) <= 5e-2
+    best = None
+    for frac in (0.5, 0.25, 0.1):
+        errs, fbs = S.contact_force_error(w, net, steps=5, fallback=frac)
+        times = S.time_steps(w, net, fallback=frac)
+        print(f"surrogate on 65536x16 spheres, fallback beyond {frac} r: rel force err per step "
+              f"{np.round(errs, 4)}, fallback pair sides {fbs}, exact {times['exact']:.3f} ms, "
+              f"surrogate {times['surrogate']:.3f} ms, speedup "
+              f"{times['exact'] / times['surrogate']:.3f}")
+        if frac == 0.5:
+            assert np.max(errs) <= 3e-2
+        if best is None and np.max(errs) <= 1e-2:
+            best = (frac, times['exact'] / times['surrogate'])
+    print(f"at <= 1e-2 relative force error: {best}")
+    assert best is not None
 
 
 def test_surrogate_gradient_sees_contact_onset(trained):
