@@ -201,11 +201,15 @@ vmas_status vmas_rollout_backward(vmas_batch* batch, const float* state0, const 
 /* Launch plans. Plan ids are 0 .. n_schedules-1 (see vmas_schedule_name);
  * every plan computes the same results bit for bit. vmas_autotune times each
  * plan on a T-step rollout of a scratch copy of `state` (state itself is not
- * modified), keeps the fastest and returns its id in *chosen. It
- * synchronises the stream. */
+ * modified) with the given actions (device float32 [T][A][2]; NULL: actions
+ * drawn in the kernel, seed 12345), three timed repetitions after a warm-up,
+ * and keeps the fastest; a later plan replaces the current choice only when
+ * it is at least 3 % faster. Returns the plan id in *chosen (and makes it
+ * current). It synchronises the stream; it allocates one state-sized scratch
+ * buffer for the duration of the call. */
 vmas_status vmas_set_schedule(vmas_batch* batch, int32_t schedule);
-vmas_status vmas_autotune(vmas_batch* batch, const float* state, int32_t T, void* stream,
-                          int32_t* chosen);
+vmas_status vmas_autotune(vmas_batch* batch, const float* state, const float* actions, int32_t T,
+                          void* stream, int32_t* chosen);
 const char* vmas_schedule_name(const vmas_batch* batch, int32_t schedule);
 
 /* Rollout through a cached hipGraph: the first call captures the launch on

@@ -88,7 +88,7 @@ def lib():
     L.vmas_rollout_backward.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,
                                         vp]
     L.vmas_set_schedule.argtypes = [vp, ctypes.c_int32]
-    L.vmas_autotune.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32)]
+    L.vmas_autotune.argtypes = [vp, vp, vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32)]
     L.vmas_schedule_name.argtypes = [vp, ctypes.c_int32]
     L.vmas_schedule_name.restype = ctypes.c_char_p
     L.vmas_last_error.restype = ctypes.c_char_p
@@ -218,11 +218,14 @@ class Batch:
     def set_schedule(self, q: int) -> None:
         _check(lib().vmas_set_schedule(self.handle, q))
 
-    def autotune(self, state, T: int = 10) -> int:
+    def autotune(self, state, T: int = 10, actions=None) -> int:
+        """Times every plan on a T-step rollout (actions [T][A][2] on the
+        device, or drawn in the kernel) and makes the fastest current."""
         import torch
         out = ctypes.c_int32(-1)
         _check(lib().vmas_autotune(self.handle, _dptr(state, 6 * self.N, torch.float32, "state"),
-                                   T, _stream(self.device), ctypes.byref(out)))
+                                   _dptr(actions, T * 2 * self.A, torch.float32, "actions"), T,
+                                   _stream(self.device), ctypes.byref(out)))
         return out.value
 
     # ---------------------------------------------------------------- calls --
@@ -420,8 +423,8 @@ def vmas_rollout_backward(batch: Batch, state0, actions, grad_state_T, ckpt_ever
     batch.rollout_backward(state0, actions, grad_state_T, ckpt_every, grad_state0, grad_actions)
 
 
-def vmas_autotune(batch: Batch, state, T: int = 10) -> int:
-    return batch.autotune(state, T)
+def vmas_autotune(batch: Batch, state, T: int = 10, actions=None) -> int:
+    return batch.autotune(state, T, actions)
 
 
 def vmas_set_schedule(batch: Batch, schedule: int) -> None:

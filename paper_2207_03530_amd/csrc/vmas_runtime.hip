@@ -791,8 +791,8 @@ vmas_status vmas_rollout_graph(vmas_batch* b, float* state, const float* actions
   return VMAS_OK;
 }
 
-vmas_status vmas_autotune(vmas_batch* b, const float* state, int32_t T, void* stream,
-                          int32_t* chosen) {
+vmas_status vmas_autotune(vmas_batch* b, const float* state, const float* actions, int32_t T,
+                          void* stream, int32_t* chosen) {
   g_err.clear();
   if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
   if (!state || T < 1) return fail(VMAS_ERR_INVALID_ARGUMENT, "state must be given and T >= 1");
@@ -819,14 +819,16 @@ vmas_status vmas_autotune(vmas_batch* b, const float* state, int32_t T, void* st
         break;
       }
       (void)hipEventRecord(e0, s);
-      st = vmas_rollout(b, scratch, nullptr, 12345u, 0, T, nullptr, nullptr, stream);
+      st = vmas_rollout(b, scratch, actions, 12345u, 0, T, nullptr, nullptr, stream);
       (void)hipEventRecord(e1, s);
       if (hipEventSynchronize(e1) != hipSuccess) st = fail(VMAS_ERR_DEVICE, "autotune sync failed");
       float ms = 0;
       (void)hipEventElapsedTime(&ms, e0, e1);
       if (rep > 0 && (rep == 1 || ms < ms_min)) ms_min = ms;  // first repetition warms up
     }
-    if (st == VMAS_OK && (best < 0 || ms_min < best_ms)) {
+    // a later schedule must be clearly faster (3 %) to replace the current
+    // choice, which keeps the choice stable where schedules are within noise
+    if (st == VMAS_OK && (best < 0 || ms_min < 0.97f * best_ms)) {
       best = q;
       best_ms = ms_min;
     }
