@@ -262,3 +262,66 @@ def test_autograd_rollout_matches_direct_call():
     out = AG.step(b, s1, _dev(w.actions(1)[0]))
     out.sum().backward()
     assert s1.grad is not None and torch.isfinite(s1.grad).all()
+
+
+def test_uneven16384_rollout_gradient_sampled():
+    """The adjoint configuration at full size: d/d actions of sum |x_T|^2
+    through a 50-step rollout of 16,384 environments of 2..64 spheres,
+    checkpoint every 10 steps, on the GPU; for 64 sampled environments one
+    action component each against FP64 central differences (eps = 1e-6) of
+    the oracle on those environments."""
+    w = W.uneven(16384, lo=2, hi=64, seed=0)
+    T, k, eps = 50, 10, 1e-6
+    acts = w.actions(T)
+    b = _batch(w)
+    st = _dev(w.state0)
+    b.rollout(st, _dev(acts))
+    torch.cuda.synchronize()
+    xT = st.cpu().numpy().reshape(6, -1)
+    gT = np.zeros_like(xT)
+    gT[0:2] = 2 * xT[0:2]
+    ga = torch.zeros(acts.size, device="cuda:0")
+    b.rollout_backward(_dev(w.state0), _dev(acts), _dev(gT), k, None, ga)
+    torch.cuda.synchronize()
+    ga = ga.cpu().numpy().reshape(acts.shape)
+    n = np.diff(w.env_offset)
+    order = np.argsort(n, kind="stable")
+    envs = np.unique(order[np.linspace(0, len(order) - 1, 64).round().astype(int)])
+    ws = W.subset(w, envs)
+    first = np.concatenate([[0], np.cumsum(w.n_agents)[:-1]])
+    rows = np.concatenate([first[e] + np.arange(w.n_agents[e]) for e in envs])
+    acts_s = acts[:, rows]
+    ow = O.OracleWorld(ws)
+    _, m0 = _oracle_masks(ow, ws.state0, acts_s)
+    hor = PU.horizon(ow, ws.state0, acts_s, tol=1e-3)
+    seg = _seg(ws)
+    penv = PU.pair_env(ws.env_offset)
+    rng = np.random.default_rng(1)
+    sub_first = np.concatenate([[0], np.cumsum(ws.n_agents)[:-1]])
+    compared = flipped = 0
+    worst = 0.0
+    for rep in range(3):
+        t_e = rng.integers(0, T, ws.n_envs)
+        comp_e = rng.integers(0, 2, ws.n_envs)
+        agent_e = sub_first + (rng.random(ws.n_envs) * ws.n_agents).astype(int)
+        vals = []
+        flips = np.zeros(ws.n_envs, bool)
+        for sgn in (+1, -1):
+            a = acts_s.astype(np.float64).copy()
+            a[t_e, agent_e, comp_e] += sgn * eps
+            sT, ms = _oracle_masks(ow, ws.state0, a)
+            L = np.zeros(ws.n_envs)
+            np.add.at(L, seg, (sT[0:2] ** 2).sum(0))
+            vals.append(L)
+            flips[np.unique(penv[(ms != m0).any(0)])] = True
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        g = ga[t_e, rows[agent_e], comp_e].astype(np.float64)
+        ok = ~flips & (hor >= T)
+        flipped += flips.sum()
+        rel = np.abs(g - fd) / np.maximum(np.abs(fd), 1e-2)
+        worst = max(worst, rel[ok].max() if ok.any() else 0.0)
+        compared += ok.sum()
+        assert rel[ok].max() <= 2e-3, (rep, rel[ok].max())
+    print(f"uneven16384 FD check: compared {compared}, excluded for contact flips {flipped}, "
+          f"beyond horizon {(hor < T).sum()} envs, worst rel err {worst:.3g}")
+    assert compared >= 0.3 * 3 * ws.n_envs

@@ -449,3 +449,64 @@ def test_trajectory_output():
         assert torch.equal(tr.view(T + 1, -1)[t + 1], s2.view(-1)), t
     assert torch.equal(tr.view(T + 1, -1)[0], _dev(w.state0).view(-1))
     assert torch.equal(s, s2)
+
+
+# ------------------------------------------- uneven batch at full size ------
+
+def _sample_envs(w, k, seed=0):
+    """k environments spread over the size range, the smallest and largest
+    included."""
+    n = np.diff(w.env_offset)
+    order = np.argsort(n, kind="stable")
+    pick = order[np.linspace(0, len(order) - 1, k).round().astype(int)]
+    return np.unique(pick)
+
+
+def _actions_of(w, envs, T, t0=0):
+    """The in-kernel action stream of the agents of `envs` ([T, A_sub, 2]),
+    drawn from its definition by global agent row."""
+    first = np.concatenate([[0], np.cumsum(w.n_agents)[:-1]])
+    rows = np.concatenate([first[e] + np.arange(w.n_agents[e]) for e in envs]).astype(np.uint64)
+    A = np.uint64(w.n_agents_total)
+    t = np.arange(t0, t0 + T, dtype=np.uint64)[:, None, None]
+    c = np.arange(2, dtype=np.uint64)[None, None, :]
+    idx = (t * A + rows[None, :, None]) * np.uint64(2) + c
+    return W.draw_sym(w.seed, W.STREAM_ACT, idx)
+
+
+def test_uneven16384_graph_rollout_500_steps():
+    """16,384 environments of 2..64 spheres in one persistent 500-step
+    rollout replayed from a hipGraph with actions drawn in the kernel (the
+    uneven-batching configuration at full size): bitwise equal to 500 single
+    steps at t0 = 0..499, and 64 sampled environments (all sizes) followed
+    step by step against the oracle up to each one's cutoff. Dense
+    environments (up to 64 spheres of r = 0.05 in [-1, 1]^2) are chaotic: the
+    FP64 trajectory itself moves by more than tol/10 under a 1e-7 perturbation
+    after a median of about 40 steps, so half of the sample is required to
+    stay comparable for 20 steps, every step before a cutoff within 1e-3."""
+    w = W.uneven(16384, lo=2, hi=64, seed=0)
+    T = 500
+    b = _batch(w)
+    q = b.autotune(_dev(w.state0), 20)
+    st = _dev(w.state0)
+    b.rollout(st, None, T=T, seed=w.seed, graph=True)
+    envs = _sample_envs(w, 64)
+    ids = np.concatenate([np.arange(w.env_offset[e], w.env_offset[e + 1]) for e in envs])
+    n = np.diff(w.env_offset).astype(np.int64)
+    poff = np.concatenate([[0], np.cumsum(n * (n - 1) // 2)])
+    slots = np.concatenate([np.arange(poff[e], poff[e + 1]) for e in envs])
+    s = _dev(w.state0)
+    ids_t, sl_t = torch.as_tensor(ids, device="cuda:0"), torch.as_tensor(slots, device="cuda:0")
+    mk = torch.zeros(b.P, dtype=torch.uint8, device="cuda:0")
+    trs, mks = [s.view(6, -1)[:, ids_t].cpu().numpy()], []
+    for t in range(T):
+        b.rollout(s, None, T=1, seed=w.seed, t0=t, final_mask=mk)
+        trs.append(s.view(6, -1)[:, ids_t].cpu().numpy())
+        mks.append(mk[sl_t].cpu().numpy())
+    torch.cuda.synchronize()
+    assert torch.equal(s, st)
+    ws = W.subset(w, envs)
+    print(f"uneven16384 plan {b.schedule_name(q)}, sampled sizes {np.diff(ws.env_offset).min()}.."
+          f"{np.diff(ws.env_offset).max()}")
+    _free_run_check(ws, O.OracleWorld(ws), np.stack(trs), np.stack(mks), _actions_of(w, envs, T),
+                    "uneven16384 sample", min_full=0.5, min_steps=20)
