@@ -31,8 +31,8 @@
 // of the branch that is taken.
 //
 // Parity notes: the contact predicate between two spheres is decided in FP32
-// as fl(dx*dx) + fl(dy*dy) <= fl(d_min * d_min) with dx, dy, d_min rounded
-// exactly as written; for the other pair types the FP32 decision uses this
+// as fl(dx*dx + fl(dy*dy)) <= fl(d_min * d_min) (one fused multiply-add) with
+// dx, dy, d_min rounded exactly as written; for the other pair types the FP32 decision uses this
 // file's own FP32 geometry and is comparable to the GPU's only outside a band
 // around d_min (see the tests). Parity unpinned: the values of c and k, the
 // joint model and the tie-breaking order between equally close features are
@@ -569,7 +569,7 @@ bool contact_fp32(const oracle_world* w, int a, int b, double xa, double ya, dou
   if (sa == SPHERE && sb == SPHERE) {
     float dx = (float)xa - (float)xb;
     float dy = (float)ya - (float)yb;
-    float s = dx * dx + dy * dy;
+    float s = std::fma(dx, dx, dy * dy);
     return s <= dmin * dmin;
   }
   Pose<float> pa, pb;

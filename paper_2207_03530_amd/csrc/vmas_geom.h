@@ -497,9 +497,10 @@ __device__ __forceinline__ void sphere_normal(S dx, S dy, S sq, bool self_lo, S*
 }
 
 // Contact predicate of Eq. (2) between two spheres, decided in FP32 on the
-// squared lengths: fl(dx*dx) + fl(dy*dy) <= fl(d_min * d_min).
+// squared lengths: fl(dx*dx + fl(dy*dy)) <= fl(d_min * d_min), one fused
+// multiply-add.
 __device__ __forceinline__ bool sphere_contact(float dx, float dy, float dmin, float* sq) {
-  *sq = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
+  *sq = fmaf(dx, dx, __fmul_rn(dy, dy));
   return *sq <= __fmul_rn(dmin, dmin);
 }
 
@@ -516,7 +517,7 @@ __device__ __forceinline__ bool pair_force(const GeoT<float>& self, float rho_s,
   if (SPH || (self.shape == SPHERE && so == SPHERE)) {
     // Both spheres: x_ij joins the centres; decision on squared lengths.
     const float dx = self.c.x - P.x, dy = self.c.y - P.y;
-    const float s = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
+    const float s = fmaf(dx, dx, __fmul_rn(dy, dy));
     if (!(s <= __fmul_rn(dmin, dmin))) return false;
     V2T<float> n;
     float d;
@@ -591,7 +592,7 @@ __device__ __forceinline__ void pair_grad(const GeoT<D3>& self, float rho_s, boo
   const float dmin = (rho_s + rho_o) + w.min_dist;
   if (self.shape == SPHERE && other.shape == SPHERE) {
     const D3 dx = self.c.x - other.c.x, dy = self.c.y - other.c.y;
-    const D3 sq = dx * dx + dy * dy;
+    const D3 sq = s_fma(dx, dx, dy * dy);
     V2T<D3> n;
     D3 d;
     sphere_normal(dx, dy, sq, self_lo, &d, &n);

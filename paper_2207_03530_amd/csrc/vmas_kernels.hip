@@ -248,14 +248,15 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
 // statically.
 //
 // NB > 0: every environment of the plan has at most NB entities. A lane's
-// partner slots are fixed for the whole rollout, so the squared contact
-// distance of each slot, fl((r_i + r_j [+ d_min])^2), is computed once into
-// registers, -1 for slots that must never report contact (the lane itself,
-// slots past its environment, which read neighbours or padding). The
-// per-step test of slot u is then the FP32 rule
-// fl(dx^2) + fl(dy^2) <= dmin2[u]. NB = 0: any size, one partner at a time. MD: the world has a nonzero minimum distance. The
-// arithmetic of a contact is the same, operation for operation, in every
-// variant and as the sphere path of k_rollout.
+// partners are the NB - 1 slots of its environment other than its own (slot
+// u' + [u' >= own slot] for partner u'), fixed for the whole rollout, so their
+// LDS addresses and squared contact distances fl((r_i + r_j [+ d_min])^2) are
+// computed once into registers, -1 for partners past the environment (they
+// read neighbours or padding). The per-step test of a partner is then the
+// FP32 rule fl(dx^2 + fl(dy^2)) <= dmin2 (one fused multiply-add). NB = 0:
+// any size, one partner at a time. MD: the world has a nonzero minimum
+// distance. The arithmetic of a contact is the same, operation for operation,
+// in every variant and as the sphere path of k_rollout.
 constexpr int KCH = 8;
 
 template <int MAXB, int NB, bool MD, bool OUT>
@@ -327,13 +328,17 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
   load_chunk(cur, 0);
   wait_global_loads();
   __syncthreads();
-  // squared contact distance of each partner slot (-1: never in contact)
-  float dm2[NB > 0 ? NB : 1];
+  // partner u' sits in slot u' + [u' >= own slot]; its squared contact
+  // distance (-1: never in contact)
+  constexpr int NP = NB > 1 ? NB - 1 : 1;
+  int sl[NP];
+  float dm2[NP];
 #pragma unroll
-  for (int u = 0; u < (NB > 0 ? NB : 1); ++u) {
+  for (int u = 0; u < NP; ++u) {
+    sl[u] = u + (u >= myloc ? 1 : 0);
     dm2[u] = -1.0f;
-    if (NB > 0 && collide && u < nloc && u != myloc) {
-      float dmin = p.rho + stat[r.lo + u].x;
+    if (NB > 0 && collide && sl[u] < nloc) {
+      float dmin = p.rho + stat[r.lo + sl[u]].x;
       if (MD) dmin += w.min_dist;
       dm2[u] = __fmul_rn(dmin, dmin);
     }
@@ -358,7 +363,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
           float dmin = p.rho + S.x;
           if (MD) dmin += w.min_dist;
           const float dx = x - P.x, dy = y - P.y;
-          const float sq = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
+          const float sq = fmaf(dx, dx, __fmul_rn(dy, dy));
           V2 n;
           float d;
           sphere_normal(dx, dy, sq, r.slot < q, &d, &n);
@@ -377,21 +382,20 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
         };
         if (collide) {
           if constexpr (NB > 0) {
-            // Pass 1: the test of every partner slot into a bit mask (slot u
-            // -> bit u). Pass 2: forces for the set bits only, first partner
-            // first, so a wavefront runs the force code as often as its
-            // busiest lane has contacts.
-            const float2* pb = cb + r.lo;
+            // Pass 1: the test of every partner into a bit mask (partner u'
+            // -> bit u'). Pass 2: forces for the set bits only, first
+            // partner first, so a wavefront runs the force code as often as
+            // its busiest lane has contacts.
+            const float2* pb = ((k & 1) ? pos1 : pos0) + r.lo;  // KCH is even
             uint32_t hits = 0;
 #pragma unroll
-            for (int blk = 0; blk < NB; blk += 8) {
-              if (blk < gmaxn) {  // uniform over the block
-                constexpr int W8 = NB < 8 ? NB : 8;
+            for (int blk = 0; blk < NP; blk += 8) {
+              if (blk < gmaxn - 1) {  // uniform over the block
 #pragma unroll
-                for (int v = 0; v < W8; ++v) {
-                  const float2 P = pb[blk + v];
+                for (int v = 0; v < 8 && blk + v < NP; ++v) {
+                  const float2 P = pb[sl[blk + v]];
                   const float dx = x - P.x, dy = y - P.y;
-                  const bool hit = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)) <= dm2[blk + v];
+                  const bool hit = fmaf(dx, dx, __fmul_rn(dy, dy)) <= dm2[blk + v];
                   hits |= (hit ? 1u : 0u) << (blk + v);
                 }
               }
@@ -399,7 +403,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
             while (hits) {
               const int u = __builtin_ctz(hits);
               hits &= hits - 1;
-              contact(r.lo + u);
+              contact(r.lo + u + (u >= myloc ? 1 : 0));
             }
           } else {
             for (int u = 0; u < gmaxn; ++u) {
@@ -408,7 +412,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
               float dmin = p.rho + stat[q].x;
               if (MD) dmin += w.min_dist;
               const float dx = x - P.x, dy = y - P.y;
-              const float sq = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
+              const float sq = fmaf(dx, dx, __fmul_rn(dy, dy));
               if ((sq <= __fmul_rn(dmin, dmin)) & (u < nloc) & (u != myloc)) contact(q);
             }
           }
@@ -595,7 +599,7 @@ __global__ void __launch_bounds__(256) k_rollout_quad(StepArgs a) {
 #pragma unroll
           for (int u = 0; u < NP; ++u) {
             const float dx = x - px[u], dy = y - py[u];
-            const bool hit = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)) <= dm2[u];
+            const bool hit = fmaf(dx, dx, __fmul_rn(dy, dy)) <= dm2[u];
             hits |= hit ? bit[u] : 0u;
           }
           while (hits) {  // partner order: lowest local index first
@@ -616,7 +620,7 @@ __global__ void __launch_bounds__(256) k_rollout_quad(StepArgs a) {
             float dmin = p.rho + PR;
             if (MD) dmin += w.min_dist;
             const float dx = x - PX, dy = y - PY;
-            const float sq = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
+            const float sq = fmaf(dx, dx, __fmul_rn(dy, dy));
             V2 nrm;
             float d;
             sphere_normal(dx, dy, sq, myloc < ploc, &d, &nrm);

@@ -109,7 +109,7 @@ struct vmas_batch {
   int32_t* d_rows = nullptr;   // [P] candidate row of each pair slot, then [1] the count
   std::vector<Plan> plans;
   int cur = 0;
-  int lane_plan = 0;  // an entity-lane plan (kernels that need lane records)
+  int lane_plan = 0;  // entity-lane plan of the surrogate kernels: the largest block up to 256
   Plan back;  // adjoint plan: every entity has a lane
   // checkpoint workspace of the adjoint driver and the autotuner scratch
   float* d_ws = nullptr;
@@ -629,7 +629,13 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
     return fail(VMAS_ERR_UNSUPPORTED, "an environment is too large to stage in LDS");
   }
   b->cur = first_valid;
+  // the surrogate's candidate kernel takes one atomic per workgroup: prefer
+  // the largest workgroups (fewest atomics on one counter)
   b->lane_plan = first_valid;
+  for (int q = 0; q < (int)b->plans.size(); ++q)
+    if (b->plans[q].valid && !b->plans[q].quad && b->plans[q].block <= 256 &&
+        b->plans[q].block > b->plans[b->lane_plan].block)
+      b->lane_plan = q;
   {
     Plan p;
     if ((s = build_quad_plan(b, h, flags, p)) != VMAS_OK) {

@@ -189,6 +189,7 @@ __global__ void __launch_bounds__(256) k_cand_features(CandArgs ca) {
   const int E = a.max_stage;
   float4* pose = lds;
   float4* stat = lds + E;
+  float* brad = reinterpret_cast<float*>(lds + 2 * E);  // bounding radius of each slot
   const int g = blockIdx.x, l = threadIdx.x, B = blockDim.x;
   const int N = a.w.N;
   const int s0 = a.stage_off[g], ns = a.stage_off[g + 1] - s0;
@@ -199,6 +200,7 @@ __global__ void __launch_bounds__(256) k_cand_features(CandArgs ca) {
     if ((p.sf & 0xff) != SPHERE) sincosf(a.state[4 * N + e], &sn, &cs);
     pose[s] = make_float4(a.state[e], a.state[N + e], cs, sn);
     stat[s] = make_float4(p.d0, p.d1, p.rho, __int_as_float(p.sf));
+    brad[s] = bound_radius(p.sf & 0xff, p.d0, p.d1);
   }
   const LaneRec r = a.lanes[(size_t)g * B + l];
   __syncthreads();
@@ -219,7 +221,7 @@ __global__ void __launch_bounds__(256) k_cand_features(CandArgs ca) {
     if (!(myloc < b || !(of & (MOVABLE | ROTATABLE)))) return false;
     if (!(of & COLLIDABLE) || (p.excl != -1 && excluded(p.excl, b))) return false;
     const float4 P = pose[q];
-    const float ro = bound_radius(so, S.x, S.y);
+    const float ro = brad[q];
     return myloc < b ? net_candidate(me.x, me.y, rme, shape, P.x, P.y, ro, so, ca.band)
                      : net_candidate(P.x, P.y, ro, so, me.x, me.y, rme, shape, ca.band);
   };
@@ -280,6 +282,7 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
   const int E = a.max_stage;
   float4* pose = lds;
   float4* stat = lds + E;
+  float* brad = reinterpret_cast<float*>(lds + 2 * E);  // bounding radius of each slot
   const int g = blockIdx.x, l = threadIdx.x, B = blockDim.x;
   const int N = a.w.N;
   const int s0 = a.stage_off[g], ns = a.stage_off[g + 1] - s0;
@@ -290,6 +293,7 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
     if ((p.sf & 0xff) != SPHERE) sincosf(a.state[4 * N + e], &sn, &cs);
     pose[s] = make_float4(a.state[e], a.state[N + e], cs, sn);
     stat[s] = make_float4(p.d0, p.d1, p.rho, __int_as_float(p.sf));
+    brad[s] = bound_radius(p.sf & 0xff, p.d0, p.d1);
   }
   const LaneRec r = a.lanes[(size_t)g * B + l];
   const bool act = r.ent >= 0;
@@ -324,8 +328,6 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
     for (int q = r.lo; q < r.hi; ++q) {
       if (q == r.slot) continue;
       const int b = q - r.lo;
-      const int ia = min(myloc, b), ib = max(myloc, b);
-      const int64_t slot = a.pair_off[r.env] + (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
       const float4 P = pose[q];
       const float4 S = stat[q];
       const int so = __float_as_int(S.w) & 0xff, of = (__float_as_int(S.w) >> 8) & 0xff;
@@ -336,10 +338,12 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
         continue;
       }
       // the candidate decision of the feature kernel, repeated bit for bit
-      const float ro = bound_radius(so, S.x, S.y);
+      const float ro = brad[q];
       const bool cand = myloc < b ? net_candidate(x, y, rme, shape, P.x, P.y, ro, so, sa.band)
                                   : net_candidate(P.x, P.y, ro, so, x, y, rme, shape, sa.band);
       if (!cand) continue;
+      const int ia = min(myloc, b), ib = max(myloc, b);
+      const int64_t slot = a.pair_off[r.env] + (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
       const int row = sa.row_of[slot];
       // surrogate force on lo, in the pair frame -> world
       const float hx = sa.yhat[2 * (int64_t)row] * FS, hy = sa.yhat[2 * (int64_t)row + 1] * FS;
@@ -434,7 +438,7 @@ hipError_t launch_candidate_features(const StepArgs& a, int groups, int block, f
                                      float* feat, int32_t* row_of, int32_t* count, hipStream_t s) {
   if (groups <= 0) return hipSuccess;
   CandArgs ca{a, band, feat, row_of, count};
-  const size_t shm = (size_t)a.max_stage * 2 * sizeof(float4);
+  const size_t shm = (size_t)a.max_stage * (2 * sizeof(float4) + sizeof(float));
   hipLaunchKernelGGL(k_cand_features, dim3(groups), dim3(block), shm, s, ca);
   return hipGetLastError();
 }
@@ -443,7 +447,7 @@ hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat, const int
                                  float band, float frac, int32_t* n_fallback, int groups,
                                  int block, hipStream_t s) {
   SurArgs sa{a, yhat, row_of, band, frac, n_fallback};
-  const size_t shm = (size_t)a.max_stage * 2 * sizeof(float4);
+  const size_t shm = (size_t)a.max_stage * (2 * sizeof(float4) + sizeof(float));
   hipLaunchKernelGGL(k_step_surrogate, dim3(groups), dim3(block), shm, s, sa);
   return hipGetLastError();
 }

@@ -73,6 +73,13 @@ def make_dataset(world, T: int, stride: int, max_samples: int, seed: int = 0, de
             m_cap = c * k * torch.nn.functional.softplus(cap[deep].double() / k) / (c * FORCE_L)
             m = torch.linalg.norm(y[deep], dim=1).double()
             y[deep] = y[deep] * (m_cap / m).float().unsqueeze(1)
+        # contacts within 2 k of onset, where Eq. (2) jumps and bends, are
+        # taught four times as often
+        pen = penetration_of(y, c, k)
+        near = ((fl & 2) != 0) & (pen <= 2.0 * k)
+        if bool(near.any()):
+            f = torch.cat([f] + [f[near]] * 3)
+            y = torch.cat([y] + [y[near]] * 3)
         feats.append(f)
         targs.append(y)
         total += f.shape[0]
