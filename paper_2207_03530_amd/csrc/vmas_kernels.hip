@@ -406,14 +406,30 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
               contact(r.lo + u + (u >= myloc ? 1 : 0));
             }
           } else {
-            for (int u = 0; u < gmaxn; ++u) {
-              const int q = min(r.lo + u, r.hi - 1);
-              const float2 P = cb[q];
-              float dmin = p.rho + stat[q].x;
-              if (MD) dmin += w.min_dist;
-              const float dx = x - P.x, dy = y - P.y;
-              const float sq = fmaf(dx, dx, __fmul_rn(dy, dy));
-              if ((sq <= __fmul_rn(dmin, dmin)) & (u < nloc) & (u != myloc)) contact(q);
+            // any size: 32 partners per pass, tested into a bit mask, then the
+            // force code for the set bits; the trip count is the largest
+            // environment of the group (uniform over the workgroup), an index
+            // past the lane's own environment is clamped to a valid slot and
+            // masked out
+            for (int base = 0; base < gmaxn; base += 32) {
+              const int cnt = min(32, gmaxn - base);
+              uint32_t hits = 0;
+              for (int u = 0; u < cnt; ++u) {
+                const int q = min(r.lo + base + u, r.hi - 1);
+                const float2 P = cb[q];
+                float dmin = p.rho + stat[q].x;
+                if (MD) dmin += w.min_dist;
+                const float dx = x - P.x, dy = y - P.y;
+                const bool hit = (fmaf(dx, dx, __fmul_rn(dy, dy)) <= __fmul_rn(dmin, dmin)) &
+                                 (base + u < nloc);
+                hits |= (hit ? 1u : 0u) << u;
+              }
+              if (myloc >= base && myloc < base + 32) hits &= ~(1u << (myloc - base));
+              while (hits) {
+                const int u = __builtin_ctz(hits);
+                hits &= hits - 1;
+                contact(r.lo + base + u);
+              }
             }
           }
         }
