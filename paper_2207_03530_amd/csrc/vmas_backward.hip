@@ -44,7 +44,8 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
   const LaneRec r = a.lanes[(size_t)g * B + l];
   const bool act = r.ent >= 0;
   const WorldK w = a.w;
-  float x = 0, y = 0, vx = 0, vy = 0, th = 0, om = 0;
+  // omega itself is not needed: its step is linear (damping and torque)
+  float x = 0, y = 0, vx = 0, vy = 0, th = 0;
   EntParam p{};
   float gx = 0, gy = 0, gvx = 0, gvy = 0, gth = 0, gom = 0;
   if (act) {
@@ -54,7 +55,6 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
     vx = a.state[2 * N + e];
     vy = a.state[3 * N + e];
     th = a.state[4 * N + e];
-    om = a.state[5 * N + e];
     p = a.ent[e];
     gx = a.gnext[e];
     gy = a.gnext[N + e];

@@ -56,7 +56,7 @@ __device__ __forceinline__ float bounding_radius(int shape, float d0, float d1) 
 // narrow-phase distance) from the lane's own cannot be in contact, so only
 // the other partners run the narrow phase -- in partner order, with the
 // same arithmetic, hence with the results of testing every partner.
-template <bool SPH, int MAXB>
+template <int MAXB>
 __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
   extern __shared__ float4 lds[];
   const int E = a.max_stage;
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
   for (int s = l; s < ns; s += B) {
     const int e = a.stage[s0 + s];
     float cs = 1.0f, sn = 0.0f;
-    if (!SPH) sincosf(a.state[4 * N + e], &sn, &cs);
+    sincosf(a.state[4 * N + e], &sn, &cs);
     const float4 P = make_float4(a.state[e], a.state[N + e], cs, sn);
     buf0[s] = P;
     buf1[s] = P;
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
   for (int t = 0; t < a.T; ++t) {
     float4* cur = (t & 1) ? buf1 : buf0;
     float cs = 1.0f, sn = 0.0f;
-    if (!SPH && act && shape != SPHERE) sincosf(th, &sn, &cs);
+    if (act && shape != SPHERE) sincosf(th, &sn, &cs);
     if (t > 0) {
       if (act) cur[r.slot] = make_float4(x, y, cs, sn);
       __syncthreads();
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
       self.sn = sn;
       self.d0 = p.d0;
       self.d1 = p.d1;
-      self.shape = SPH ? SPHERE : shape;
+      self.shape = shape;
       const float rs = bounding_radius(self.shape, p.d0, p.d1);
       const float reach = w.min_dist + 1e-4f + 1e-5f * (fabsf(x) + fabsf(y));
       for (int base = 0; base < nloc; base += 32) {
@@ -158,9 +158,9 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
           const int b = base + u;
           const float4 S = stat[q];
           const int of = (__float_as_int(S.w) >> 8) & 0xff;
-          if (!SPH && p.excl != -1 && excluded(p.excl, b)) continue;
+          if (p.excl != -1 && excluded(p.excl, b)) continue;
           const float4 P = cur[q];
-          const bool hit = pair_force<SPH>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
+          const bool hit = pair_force<false>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
           if (mk && hit) {
             // The lower index writes the slot, or the higher one when the
             // lower entity has no lane (neither movable nor rotatable).
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
         }
       }
     }
-    if (!SPH && act) {
+    if (act) {
       // Joints: spring between world anchors, evaluated in joint order.
       const int j0 = a.joff[r.ent], j1 = a.joff[r.ent + 1];
       for (int jj = j0; jj < j1; ++jj) {
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
 // FP32 rule fl(dx^2 + fl(dy^2)) <= dmin2 (one fused multiply-add). NB = 0:
 // any size, one partner at a time. MD: the world has a nonzero minimum
 // distance. The arithmetic of a contact is the same, operation for operation,
-// in every variant and as the sphere path of k_rollout.
+// in every variant and as the sphere path of k_rollout (pair_force on two spheres).
 constexpr int KCH = 8;
 
 template <int MAXB, int NB, bool MD, bool OUT>
@@ -708,8 +708,11 @@ int sph_nb(int max_n) {
 
 template <int MAXB, int NB>
 const void* sph_pick(bool md, bool out) {
-  if (md) return out ? (const void*)k_rollout_sph<MAXB, NB, true, true> : (const void*)k_rollout_sph<MAXB, NB, true, false>;
-  return out ? (const void*)k_rollout_sph<MAXB, NB, false, true> : (const void*)k_rollout_sph<MAXB, NB, false, false>;
+  if (md)
+    return out ? (const void*)k_rollout_sph<MAXB, NB, true, true>
+               : (const void*)k_rollout_sph<MAXB, NB, true, false>;
+  return out ? (const void*)k_rollout_sph<MAXB, NB, false, true>
+             : (const void*)k_rollout_sph<MAXB, NB, false, false>;
 }
 
 const void* sph_kernel256(int nb, bool md, bool out) {
@@ -725,8 +728,11 @@ const void* sph_kernel256(int nb, bool md, bool out) {
 
 template <int NS>
 const void* quad_pick(bool md, bool out) {
-  if (md) return out ? (const void*)k_rollout_quad<true, NS, true> : (const void*)k_rollout_quad<true, NS, false>;
-  return out ? (const void*)k_rollout_quad<false, NS, true> : (const void*)k_rollout_quad<false, NS, false>;
+  if (md)
+    return out ? (const void*)k_rollout_quad<true, NS, true>
+               : (const void*)k_rollout_quad<true, NS, false>;
+  return out ? (const void*)k_rollout_quad<false, NS, true>
+             : (const void*)k_rollout_quad<false, NS, false>;
 }
 
 __global__ void k_fill_u8(uint8_t* p, int64_t n) {
@@ -773,7 +779,7 @@ const void* rollout_kernel(bool spheres_only, bool quad, int block, int max_n, f
   if (quad) return max_n <= 2 ? quad_pick<2>(md, out) : quad_pick<4>(md, out);
   if (spheres_only)
     return block > 256 ? sph_pick<1024, 0>(md, out) : sph_kernel256(sph_pad(block, max_n), md, out);
-  return block <= 256 ? (const void*)k_rollout<false, 256> : (const void*)k_rollout<false, 1024>;
+  return block <= 256 ? (const void*)k_rollout<256> : (const void*)k_rollout<1024>;
 }
 
 size_t rollout_lds_bytes(int max_stage, bool spheres_only, bool quad, int block, int max_n) {
