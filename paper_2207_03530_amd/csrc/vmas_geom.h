@@ -507,13 +507,15 @@ __device__ __forceinline__ bool sphere_contact(float dx, float dy, float dmin, f
 // Contact of the lane's entity (self, environment-local index a) with the
 // partner in LDS slot q (local index b). Accumulates the lane's force and
 // torque and reports the contact bit.
-template <bool SPH>
+// OTHER >= 0 fixes the partner's shape at compile time (the caller knows it),
+// which leaves only that shape's narrow-phase routines in the code.
+template <bool SPH, int OTHER = -1>
 __device__ __forceinline__ bool pair_force(const GeoT<float>& self, float rho_s, int a, const float4 P,
                                            const float4 S, int b, const WorldK& w, float& fx,
                                            float& fy, float& tq) {
   const float rho_o = S.z;
   const float dmin = (rho_s + rho_o) + w.min_dist;
-  const int so = SPH ? SPHERE : (__float_as_int(S.w) & 0xff);
+  const int so = SPH ? SPHERE : (OTHER >= 0 ? OTHER : (__float_as_int(S.w) & 0xff));
   if (SPH || (self.shape == SPHERE && so == SPHERE)) {
     // Both spheres: x_ij joins the centres; decision on squared lengths.
     const float dx = self.c.x - P.x, dy = self.c.y - P.y;

@@ -20,6 +20,8 @@
 // multiply-add is written out, so different kernels and plans agree bit for
 // bit.
 
+#include <type_traits>
+
 #include "vmas_geom.h"
 #include "vmas_internal.h"
 
@@ -50,7 +52,9 @@ __device__ __forceinline__ float bounding_radius(int shape, float d0, float d1) 
   return 0.5f * d0;
 }
 
-// Persistent rollout: T steps of every environment of the group.
+// Persistent rollout: T steps of every environment of the group. A lane's
+// contacts are accumulated partner class by partner class (spheres, boxes,
+// segments), each class in partner order.
 // Broad phase: a partner whose bounding circle stays farther than d_min plus
 // a safety margin (1e-4 + 1e-5 (|x| + |y|), far above the FP32 error of the
 // narrow-phase distance) from the lane's own cannot be in contact, so only
@@ -110,6 +114,13 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
     }
   }
   __syncthreads();
+  // shape classes of the first 32 partners (static for the whole rollout)
+  uint32_t cls_sph0 = 0, cls_box0 = 0;
+  for (int u = 0; u < min(32, nloc); ++u) {
+    const int so = __float_as_int(stat[r.lo + u].w) & 0xff;
+    cls_sph0 |= (so == SPHERE ? 1u : 0u) << u;
+    cls_box0 |= (so == BOX ? 1u : 0u) << u;
+  }
   for (int t = 0; t < a.T; ++t) {
     float4* cur = (t & 1) ? buf1 : buf0;
     float cs = 1.0f, sn = 0.0f;
@@ -142,7 +153,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
       const float reach = w.min_dist + 1e-4f + 1e-5f * (fabsf(x) + fabsf(y));
       for (int base = 0; base < nloc; base += 32) {
         const int cnt = min(32, nloc - base);
-        uint32_t cand = 0;
+        uint32_t cand = 0, msph = 0, mbox = 0;
         for (int u = 0; u < cnt; ++u) {
           const int q = r.lo + base + u;
           const float4 P = cur[q];
@@ -151,27 +162,46 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
           cand |= (dx * dx + dy * dy <= lim * lim ? 1u : 0u) << u;
         }
         if (myloc >= base && myloc < base + 32) cand &= ~(1u << (myloc - base));
-        while (cand) {
-          const int u = __builtin_ctz(cand);
-          cand &= cand - 1;
-          const int q = r.lo + base + u;
-          const int b = base + u;
-          const float4 S = stat[q];
-          const int of = (__float_as_int(S.w) >> 8) & 0xff;
-          if (p.excl != -1 && excluded(p.excl, b)) continue;
-          const float4 P = cur[q];
-          const bool hit = pair_force<false>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
-          if (mk && hit) {
-            // The lower index writes the slot, or the higher one when the
-            // lower entity has no lane (neither movable nor rotatable).
-            const bool other_active = (of & (MOVABLE | ROTATABLE)) != 0;
-            if (myloc < b || !other_active) {
-              const int ia = min(myloc, b), ib = max(myloc, b);
-              const int64_t idx = (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
-              mk[a.pair_off[r.env] + idx] = 1;
-            }
+        if (base == 0) {
+          msph = cls_sph0;
+          mbox = cls_box0;
+        } else {
+          for (int u = 0; u < cnt; ++u) {
+            const int so = __float_as_int(stat[r.lo + base + u].w) & 0xff;
+            msph |= (so == SPHERE ? 1u : 0u) << u;
+            mbox |= (so == BOX ? 1u : 0u) << u;
           }
         }
+        // candidates class by class (sphere, box, line partners), each in
+        // partner order: the lanes of a wavefront run one narrow-phase
+        // routine at a time
+        auto run = [&](auto cls, uint32_t cm) {
+          constexpr int OTHER = decltype(cls)::value;
+          while (cm) {
+            const int u = __builtin_ctz(cm);
+            cm &= cm - 1;
+            const int q = r.lo + base + u;
+            const int b = base + u;
+            const float4 S = stat[q];
+            const int of = (__float_as_int(S.w) >> 8) & 0xff;
+            if (p.excl != -1 && excluded(p.excl, b)) continue;
+            const float4 P = cur[q];
+            const bool hit = pair_force<false, OTHER>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
+            if (mk && hit) {
+              // The lower index writes the slot, or the higher one when the
+              // lower entity has no lane (neither movable nor rotatable).
+              const bool other_active = (of & (MOVABLE | ROTATABLE)) != 0;
+              if (myloc < b || !other_active) {
+                const int ia = min(myloc, b), ib = max(myloc, b);
+                const int64_t idx = (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
+                mk[a.pair_off[r.env] + idx] = 1;
+              }
+            }
+          }
+        };
+        run(std::integral_constant<int, SPHERE>{}, cand & msph);
+        run(std::integral_constant<int, BOX>{}, cand & mbox);
+        run(std::integral_constant<int, LINE>{}, cand & ~(msph | mbox));
       }
     }
     if (act) {

@@ -325,12 +325,16 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
     self.d0 = p.d0;
     self.d1 = p.d1;
     self.shape = shape;
-    for (int q = r.lo; q < r.hi; ++q) {
+    // partners class by class (spheres, boxes, segments), each in partner
+    // order: the accumulation order of the exact step
+    for (int q0 = 0; q0 < 3 * (r.hi - r.lo); ++q0) {
+      const int cls = q0 / (r.hi - r.lo), q = r.lo + q0 % (r.hi - r.lo);
       if (q == r.slot) continue;
       const int b = q - r.lo;
-      const float4 P = pose[q];
       const float4 S = stat[q];
       const int so = __float_as_int(S.w) & 0xff, of = (__float_as_int(S.w) >> 8) & 0xff;
+      if (so != cls) continue;
+      const float4 P = pose[q];
       if (!(of & COLLIDABLE) || (p.excl != -1 && excluded(p.excl, b))) continue;
       if (shape == LINE || so == LINE) {
         // segments: exact narrow phase (same eligibility as the exact step)
