@@ -477,9 +477,21 @@ template <class S> __device__ HitT<S> narrow(const GeoT<S>& lo, const GeoT<S>& h
 // form max(z, 0) + log(1 + e^{-|z|}); the second term lies in (0, ln 2] and
 // is evaluated with the hardware exp2/log2 (about 1 ulp each), an absolute
 // error of a few 1e-8 against max(z, 0) >= 0.
+// log(1 + e^-a) for a >= 0. The logarithm's argument lies in (1, 2], where
+// the hardware base-2 logarithm needs no range or denormal handling.
+__device__ __forceinline__ float softplus_tail(float a) {
+  return __builtin_amdgcn_logf(1.0f + __expf(-a)) * 0.69314718f;
+}
+__device__ __forceinline__ D3 softplus_tail(D3 p) {
+  const float e = __expf(-p.v);
+  const float v = __builtin_amdgcn_logf(1.0f + e) * 0.69314718f;
+  const float dv = -e / (1.0f + e);
+  return D3(v, dv * p.a, dv * p.b, dv * p.c);
+}
+
 template <class S> __device__ __forceinline__ S contact_mag(S dmin, S d, const WorldK& w) {
   const S z = (dmin - d) * S(w.inv_k);
-  return S(w.ck) * (s_max(z, S(0.0f)) + s_log(S(1.0f) + s_exp(-s_abs(z))));
+  return S(w.ck) * (s_max(z, S(0.0f)) + softplus_tail(s_abs(z)));
 }
 
 // Distance and unit normal along (dx, dy) from the squared length sq, with
