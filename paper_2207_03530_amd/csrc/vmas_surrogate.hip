@@ -326,56 +326,61 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
     self.d1 = p.d1;
     self.shape = shape;
     // partners class by class (spheres, boxes, segments), each in partner
-    // order: the accumulation order of the exact step
-    for (int q0 = 0; q0 < 3 * (r.hi - r.lo); ++q0) {
-      const int cls = q0 / (r.hi - r.lo), q = r.lo + q0 % (r.hi - r.lo);
-      if (q == r.slot) continue;
-      const int b = q - r.lo;
-      const float4 S = stat[q];
-      const int so = __float_as_int(S.w) & 0xff, of = (__float_as_int(S.w) >> 8) & 0xff;
-      if (so != cls) continue;
-      const float4 P = pose[q];
-      if (!(of & COLLIDABLE) || (p.excl != -1 && excluded(p.excl, b))) continue;
-      if (shape == LINE || so == LINE) {
-        // segments: exact narrow phase (same eligibility as the exact step)
-        pair_force<false>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
-        continue;
-      }
-      // the candidate decision of the feature kernel, repeated bit for bit
-      const float ro = brad[q];
-      const bool cand = myloc < b ? net_candidate(x, y, rme, shape, P.x, P.y, ro, so, sa.band)
-                                  : net_candidate(P.x, P.y, ro, so, x, y, rme, shape, sa.band);
-      if (!cand) continue;
-      const int ia = min(myloc, b), ib = max(myloc, b);
-      const int64_t slot = a.pair_off[r.env] + (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
-      const int row = sa.row_of[slot];
-      // surrogate force on lo, in the pair frame -> world
-      const float hx = sa.yhat[2 * (int64_t)row] * FS, hy = sa.yhat[2 * (int64_t)row + 1] * FS;
-      const float sgn = myloc < b ? 1.0f : -1.0f;  // e points from hi to lo
-      const float ddx = sgn * (x - P.x), ddy = sgn * (y - P.y);
-      const float dd = sqrtf(fmaf(ddx, ddx, ddy * ddy));
-      const V2T<float> ex = dd > 0.0f ? V2T<float>{ddx / dd, ddy / dd} : V2T<float>{1.0f, 0.0f};
-      const V2T<float> flo = {fmaf(hx, ex.x, -hy * ex.y), fmaf(hx, ex.y, hy * ex.x)};
-      // predicted penetration from the inverse of Eq. (2): k log(expm1(|f| / (c k)))
-      const float mag = sqrtf(flo.x * flo.x + flo.y * flo.y);
-      const float pen = mag > 0.0f ? logf(expm1f(mag / w.ck)) / w.inv_k : -INFINITY;
-      const float rr = fminf(shape == SPHERE ? p.d0 : 0.5f * fminf(p.d0, shape == BOX ? p.d1 : p.d0),
-                             so == SPHERE ? S.x : 0.5f * fminf(S.x, so == BOX ? S.y : S.x));
-      if (pen > sa.fallback_frac * rr) {
-        ++fallbacks;
-        pair_force<false>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
-        continue;
-      }
-      // nearest force Eq. (2) can produce: 0, or at least the onset force
-      // F0 = c k ln 2 (zero penetration), along the predicted direction
-      if (!(mag >= 0.5f * F0)) continue;
-      const float sc = mag < F0 ? F0 / mag : 1.0f;
-      if (myloc < b) {
-        fx = fmaf(sc, flo.x, fx);
-        fy = fmaf(sc, flo.y, fy);
-      } else {
-        fx = fmaf(-sc, flo.x, fx);
-        fy = fmaf(-sc, flo.y, fy);
+    // order: the accumulation order of the exact step; classes absent from
+    // the environment are skipped
+    unsigned present = 0;
+    for (int q = r.lo; q < r.hi; ++q) present |= 1u << (__float_as_int(stat[q].w) & 0xff);
+    for (int cls = 0; cls < 3; ++cls) {
+      if (!(present & (1u << cls))) continue;
+      for (int q = r.lo; q < r.hi; ++q) {
+        if (q == r.slot) continue;
+        const int b = q - r.lo;
+        const float4 S = stat[q];
+        const int so = __float_as_int(S.w) & 0xff, of = (__float_as_int(S.w) >> 8) & 0xff;
+        if (so != cls) continue;
+        const float4 P = pose[q];
+        if (!(of & COLLIDABLE) || (p.excl != -1 && excluded(p.excl, b))) continue;
+        if (shape == LINE || so == LINE) {
+          // segments: exact narrow phase (same eligibility as the exact step)
+          pair_force<false>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
+          continue;
+        }
+        // the candidate decision of the feature kernel, repeated bit for bit
+        const float ro = brad[q];
+        const bool cand = myloc < b ? net_candidate(x, y, rme, shape, P.x, P.y, ro, so, sa.band)
+                                    : net_candidate(P.x, P.y, ro, so, x, y, rme, shape, sa.band);
+        if (!cand) continue;
+        const int ia = min(myloc, b), ib = max(myloc, b);
+        const int64_t slot = a.pair_off[r.env] + (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
+        const int row = sa.row_of[slot];
+        // surrogate force on lo, in the pair frame -> world
+        const float hx = sa.yhat[2 * (int64_t)row] * FS, hy = sa.yhat[2 * (int64_t)row + 1] * FS;
+        const float sgn = myloc < b ? 1.0f : -1.0f;  // e points from hi to lo
+        const float ddx = sgn * (x - P.x), ddy = sgn * (y - P.y);
+        const float dd = sqrtf(fmaf(ddx, ddx, ddy * ddy));
+        const V2T<float> ex = dd > 0.0f ? V2T<float>{ddx / dd, ddy / dd} : V2T<float>{1.0f, 0.0f};
+        const V2T<float> flo = {fmaf(hx, ex.x, -hy * ex.y), fmaf(hx, ex.y, hy * ex.x)};
+        // predicted penetration from the inverse of Eq. (2): k log(expm1(|f| / (c k)))
+        const float mag = sqrtf(flo.x * flo.x + flo.y * flo.y);
+        const float pen = mag > 0.0f ? logf(expm1f(mag / w.ck)) / w.inv_k : -INFINITY;
+        const float rr = fminf(shape == SPHERE ? p.d0 : 0.5f * fminf(p.d0, shape == BOX ? p.d1 : p.d0),
+                               so == SPHERE ? S.x : 0.5f * fminf(S.x, so == BOX ? S.y : S.x));
+        if (pen > sa.fallback_frac * rr) {
+          ++fallbacks;
+          pair_force<false>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
+          continue;
+        }
+        // nearest force Eq. (2) can produce: 0, or at least the onset force
+        // F0 = c k ln 2 (zero penetration), along the predicted direction
+        if (!(mag >= 0.5f * F0)) continue;
+        const float sc = mag < F0 ? F0 / mag : 1.0f;
+        if (myloc < b) {
+          fx = fmaf(sc, flo.x, fx);
+          fy = fmaf(sc, flo.y, fy);
+        } else {
+          fx = fmaf(-sc, flo.x, fx);
+          fy = fmaf(-sc, flo.y, fy);
+        }
       }
     }
   }
