@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--envs", type=int, default=30000)
     ap.add_argument("--T", type=int, default=100)
     ap.add_argument("--graph", action="store_true", help="replay a captured hipGraph")
+    ap.add_argument("--schedule", default=None,
+                    help="run this launch plan (vmas_schedule_name) instead of autotuning")
     ap.add_argument("--drawn-actions", action="store_true",
                     help="draw the actions in the kernel instead of reading them from HBM")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -119,7 +121,14 @@ def main():
     batch = binding.vmas_create_batch(w, 0)
     state = torch.as_tensor(w.state0).to(dev).contiguous()
     acts = torch.as_tensor(acts_np).to(dev).contiguous()
-    plan = batch.autotune(state, T, None if args.drawn_actions else acts)
+    if args.schedule:
+        names = [batch.schedule_name(q) for q in range(batch.n_schedules)]
+        if args.schedule not in names:
+            sys.exit(f"unknown schedule {args.schedule!r}; valid: {[n for n in names if n]}")
+        plan = names.index(args.schedule)
+        batch.set_schedule(plan)
+    else:
+        plan = batch.autotune(state, T, None if args.drawn_actions else acts)
     stream = torch.cuda.current_stream(dev)
 
     if args.pmc_calibration:

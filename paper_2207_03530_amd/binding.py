@@ -283,11 +283,13 @@ class Batch:
         args = (self.handle, _dptr(state, 6 * self.N, torch.float32, "state"),
                 _dptr(actions, None, torch.float32, "actions"), ctypes.c_uint64(seed),
                 ctypes.c_int32(t0), ctypes.c_int32(T), None, None, _stream(self.device))
+        keep = (state, actions, self)  # the callable keeps its tensors and handle alive
 
         def run():
             st = fn(*args)
             if st != VMAS_OK:
                 _check(st)
+        run.keep = keep
         return run
 
     def rollout_backward(self, state0, actions, grad_final, ckpt_every: int = 10,
