@@ -75,6 +75,10 @@ def test_null_arguments_rejected():
     assert st == 1
     assert B.lib().vmas_step(None, None, None, None, None, None) == 1
     assert B.lib().vmas_rollout(None, None, None, 0, 0, 1, None, None, None) == 1
+    out = ctypes.c_int32(-7)
+    assert B.lib().vmas_autotune(None, None, None, 10, None, ctypes.byref(out)) == 1
+    assert out.value == -7
+    assert B.lib().vmas_step_surrogate(None, None, None, None, 0.01, 0.5, None, None, None) == 1
     assert B.lib().vmas_destroy_batch(None) == 0
 
 
@@ -134,3 +138,15 @@ def test_python_binding_names_match_c():
     for n in ("vmas_create_batch", "vmas_step", "vmas_rollout", "vmas_step_backward",
               "vmas_rollout_backward"):
         assert callable(getattr(B, n))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; --gpus above 1 exits (status 2) with a
+    message before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
