@@ -277,14 +277,15 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
 // the chunk loop is unrolled so every action register is addressed
 // statically.
 //
-// NB > 0: every environment of the plan has at most NB entities. A lane's
+// NB in 4..32: every environment of the plan has at most NB entities. A lane's
 // partners are the NB - 1 slots of its environment other than its own (slot
 // u' + [u' >= own slot] for partner u'), fixed for the whole rollout, so their
 // LDS addresses and squared contact distances fl((r_i + r_j [+ d_min])^2) are
 // computed once into registers, -1 for partners past the environment (they
 // read neighbours or padding). The per-step test of a partner is then the
-// FP32 rule fl(dx^2 + fl(dy^2)) <= dmin2 (one fused multiply-add). NB = 0:
-// any size, one partner at a time. MD: the world has a nonzero minimum
+// FP32 rule fl(dx^2 + fl(dy^2)) <= dmin2 (one fused multiply-add). NB = 64:
+// blocks of 8 slots unrolled, the contact distance from the staged radius,
+// a 64-bit hit mask. NB = 0: any size, 32 partners per pass. MD: the world has a nonzero minimum
 // distance. The arithmetic of a contact is the same, operation for operation,
 // in every variant and as the sphere path of k_rollout (pair_force on two spheres).
 constexpr int KCH = 8;
@@ -360,19 +361,22 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
   __syncthreads();
   // partner u' sits in slot u' + [u' >= own slot]; its squared contact
   // distance (-1: never in contact)
-  constexpr int NP = NB > 1 ? NB - 1 : 1;
+  constexpr bool HOIST = NB > 0 && NB <= 32;
+  constexpr int NP = HOIST ? NB - 1 : 1;
   int sl[NP];
   float dm2[NP];
 #pragma unroll
   for (int u = 0; u < NP; ++u) {
     sl[u] = u + (u >= myloc ? 1 : 0);
     dm2[u] = -1.0f;
-    if (NB > 0 && collide && sl[u] < nloc) {
+    if (HOIST && collide && sl[u] < nloc) {
       float dmin = p.rho + stat[r.lo + sl[u]].x;
       if (MD) dmin += w.min_dist;
       dm2[u] = __fmul_rn(dmin, dmin);
     }
   }
+  // NB == 64: slots u < nloc other than the lane's own
+  const uint64_t valid64 = (nloc >= 64 ? ~0ull : ((1ull << nloc) - 1ull)) & ~(1ull << (myloc & 63));
   for (int c = 0; c < T; c += KCH) {
     if (c + KCH < T) load_chunk(nxt, c + KCH);
 #pragma unroll
@@ -411,7 +415,34 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
           }
         };
         if (collide) {
-          if constexpr (NB > 0) {
+          if constexpr (NB == 64) {
+            // up to 64 slots, 8 per block (uniform guard), own slot and
+            // slots past the environment masked out once per rollout; the
+            // contact distance comes from the staged radius
+            const float2* pb = ((k & 1) ? pos1 : pos0) + r.lo;  // KCH is even
+            const float2* sb = stat + r.lo;
+            uint64_t hits = 0;
+#pragma unroll
+            for (int blk = 0; blk < 64; blk += 8) {
+              if (blk < gmaxn) {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                  const float2 P = pb[blk + v];
+                  float dmin = p.rho + sb[blk + v].x;
+                  if (MD) dmin += w.min_dist;
+                  const float dx = x - P.x, dy = y - P.y;
+                  const bool hit = fmaf(dx, dx, __fmul_rn(dy, dy)) <= __fmul_rn(dmin, dmin);
+                  hits |= (hit ? 1ull : 0ull) << (blk + v);
+                }
+              }
+            }
+            hits &= valid64;
+            while (hits) {
+              const int u = __builtin_ctzll(hits);
+              hits &= hits - 1;
+              contact(r.lo + u);
+            }
+          } else if constexpr (NB > 0) {
             // Pass 1: the test of every partner into a bit mask (partner u'
             // -> bit u'). Pass 2: forces for the set bits only, first
             // partner first, so a wavefront runs the force code as often as
@@ -731,7 +762,7 @@ __global__ void __launch_bounds__(256) k_rollout_quad(StepArgs a) {
 // Partner-slot bound of the sphere kernel for a plan whose largest
 // environment has max_n entities (0: the any-size loop).
 int sph_nb(int max_n) {
-  for (int nb : {4, 6, 8, 16, 32})
+  for (int nb : {4, 6, 8, 16, 32, 64})
     if (max_n <= nb) return nb;
   return 0;
 }
@@ -752,6 +783,7 @@ const void* sph_kernel256(int nb, bool md, bool out) {
     case 8: return sph_pick<256, 8>(md, out);
     case 16: return sph_pick<256, 16>(md, out);
     case 32: return sph_pick<256, 32>(md, out);
+    case 64: return sph_pick<256, 64>(md, out);
     default: return sph_pick<256, 0>(md, out);
   }
 }
