@@ -510,3 +510,30 @@ def test_uneven16384_graph_rollout_500_steps():
           f"{np.diff(ws.env_offset).max()}")
     _free_run_check(ws, O.OracleWorld(ws), np.stack(trs), np.stack(mks), _actions_of(w, envs, T),
                     "uneven16384 sample", min_full=0.5, min_steps=20)
+
+
+@pytest.mark.parametrize("lo,hi,E,r", [(65, 120, 24, 0.05), (300, 300, 2, 0.03)],
+                         ids=["65..120 (any-size loop)", "300 (1024-lane workgroups)"])
+def test_large_environments(lo, hi, E, r):
+    """Sphere environments beyond the unrolled paths: 65..120 entities (the
+    any-size loop, 32 partners per pass) and 300 (more movers than 256 lanes:
+    1024-lane workgroups). One step against the oracle (masks bit for bit),
+    the step loop bitwise equal to one rollout, and a short free run."""
+    w = W.uneven(E, lo=lo, hi=hi, radius=r, seed=5)
+    b = _batch(w)
+    print(f"sizes {np.diff(w.env_offset).min()}..{np.diff(w.env_offset).max()}, "
+          f"plan {b.schedule_name(0)}")
+    T = 20
+    acts = w.actions(T)
+    ow = O.OracleWorld(w)
+    g, gm, _ = _gpu_step(b, w.state0, acts[0])
+    o, om, _ = ow.step(w.state0, acts[0])
+    assert PU.env_err(g, o, w.env_offset, PU.group_scale(o)).max() <= 1e-5
+    assert np.array_equal(gm, om)
+    s, gtraj, gmasks = _gpu_run(b, w.state0, acts)
+    st = _dev(w.state0)
+    b.rollout(st, _dev(acts))
+    torch.cuda.synchronize()
+    assert torch.equal(s, st)
+    _free_run_check(w, ow, gtraj, gmasks, acts, f"large envs {lo}..{hi}", min_full=0.5,
+                    min_steps=5)
