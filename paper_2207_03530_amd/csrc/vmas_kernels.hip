@@ -14,7 +14,10 @@
 // cross-lane reduction (and no float atomic) is needed: results do not depend
 // on how environments are packed into groups. Lanes are sorted by shape
 // within a group so that a wavefront mostly runs one narrow-phase routine.
-// Poses are double-buffered in LDS: one barrier per step.
+// Poses are double-buffered in LDS: one barrier per step. Sphere batches have
+// their own kernels (k_rollout_sph: centres only in LDS, hoisted contact
+// distances; k_rollout_quad: environments of at most 4 movers on one lane
+// quad, centres exchanged by DPP, no LDS).
 //
 // Arithmetic is FP32 and compiled without implicit contraction; every fused
 // multiply-add is written out, so different kernels and plans agree bit for

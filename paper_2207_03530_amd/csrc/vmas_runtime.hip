@@ -7,8 +7,10 @@
 // the group is staged in LDS. Plans differ in the block size and in whether
 // environments are packed in their natural order or sorted by size (which
 // keeps the lanes of one wavefront on environments of similar size when
-// sizes are uneven). The per-lane arithmetic does not depend on the packing,
-// so every plan returns the same bits.
+// sizes are uneven); sphere batches whose environments have at most 4 movers
+// also get the quad plan (one lane quad per environment). The per-lane
+// arithmetic does not depend on the packing, so every plan returns the same
+// bits; the autotuner picks the fastest on the caller's workload.
 
 #include <hip/hip_runtime.h>
 
@@ -17,7 +19,6 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <cmath>
 #include <string>
 #include <vector>
 
