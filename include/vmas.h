@@ -260,11 +260,12 @@ vmas_status vmas_mlp_train_step(vmas_mlp* mlp, const float* X, const float* targ
 /* Surrogate inputs and targets. For the pair slots listed in `slots`
  * (device int64 [m], mask order; NULL: all P slots, m = P) writes, for the
  * pair (i, j), i < j, in the pair frame e = (c_i - c_j)/|c_i - c_j| of angle phi:
- *   features  device float32 [m][12]: |c_i - c_j| / L, max(g / Lg, -4) with
+ *   features  device float32 [m][12]: min(max(g / Lk, -16), 16), g / L with
  *             g = |c_i - c_j| - R_i - R_j (bounding radii: sphere r, box half
  *             diagonal, line L/2), cos and sin of (theta_i - phi), cos and sin
- *             of (theta_j - phi), dims_i / L, dims_j / L, shape codes of i and j
- *             (sphere 0, box 0.5, line 1); L = 0.1, Lg = 0.01;
+ *             of (theta_j - phi) (1 and 0 for spheres), dims_i / L, dims_j / L,
+ *             shape codes of i and j (sphere 0, box 0.5, line 1); L = 0.1,
+ *             Lk = 0.001;
  *   targets   device float32 [m][2] or NULL: the exact Eq. (2) force on i along
  *             e and along its left normal, divided by c * 0.02 (0 when not in
  *             contact or not a candidate);

@@ -5,16 +5,17 @@
 // Features of the pair (i, j), i < j in an environment, in the pair frame
 // e = (c_i - c_j) / |c_i - c_j| (e = +x for coincident centres), phi = the
 // angle of e (12 values of O(1) scale, invariant under rigid motions):
-//   |c_i - c_j| / L, g / Lg with g = |c_i - c_j| - R_i - R_j (R: bounding
-//   radius, sphere r, box half diagonal, line L/2), cos and sin of
+//   g / Lk clamped to [-16, 16] and g / L, with g = |c_i - c_j| - R_i - R_j
+//   the gap of the bounding circles (R: sphere r, box half diagonal, line
+//   L/2), at two scales, cos and sin of
 //   (theta_i - phi), cos and sin of (theta_j - phi) (1 and 0 for a sphere,
 //   which has no orientation), dims_i / L, dims_j / L, shape code of i and
 //   of j (sphere 0, box 0.5, line 1);
-// L = 0.1, Lg = 0.01. Target: the Eq. (2) force on i in the pair frame
+// L = 0.1, Lk = 0.001 (the scale of the contact margin k, over which
+// Eq. (2) bends at onset). Target: the Eq. (2) force on i in the pair frame
 // (along e, along the left normal of e) divided by c * Lf, Lf = 0.02 (zero
-// when the pair is not in contact). The gap feature is clamped below at -4
-// (bounding circles of boxes overlap far before the boxes touch; the centre
-// distance carries that range).
+// when the pair is not in contact). The centre distance is not a feature: it
+// is the gap plus the two bounding radii, which the sizes give.
 // A pair is a candidate for the network when neither entity is a segment and
 // their bounding circles (sphere r, box half diagonal) come within `band` of
 // each other. A segment has no thickness, so the fallback rule (penetration
@@ -31,7 +32,7 @@ namespace vmas {
 namespace {
 
 constexpr float FEAT_L = 0.1f;   // length scale of the features
-constexpr float GAP_L = 0.01f;   // length scale of the gap feature
+constexpr float FINE_L = 0.001f; // length scale of the fine gap feature
 constexpr float FORCE_L = 0.02f; // force scale c * FORCE_L of the targets
 
 __device__ __forceinline__ float bound_radius(int shape, float d0, float d1) {
@@ -71,8 +72,9 @@ __device__ __forceinline__ void write_features(float* f, float xi, float yi, flo
   const float dist = sqrtf(dx * dx + dy * dy);
   const float ex = dist > 0.0f ? dx / dist : 1.0f, ey = dist > 0.0f ? dy / dist : 0.0f;
   const float Ri = bound_radius(si, d0i, d1i), Rj = bound_radius(sj, d0j, d1j);
-  f[0] = dist / FEAT_L;
-  f[1] = fmaxf((dist - (Ri + Rj)) / GAP_L, -4.0f);
+  const float gap = dist - (Ri + Rj);
+  f[0] = fminf(fmaxf(gap / FINE_L, -16.0f), 16.0f);
+  f[1] = gap / FEAT_L;
   // cos and sin of (theta - phi); a sphere has no orientation: (1, 0)
   f[2] = si == SPHERE ? 1.0f : fmaf(ci, ex, sni * ey);
   f[3] = si == SPHERE ? 0.0f : fmaf(sni, ex, -ci * ey);

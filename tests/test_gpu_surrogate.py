@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 FEAT_L = 0.1
-GAP_L = 0.01
+FINE_L = 0.001
 FORCE_L = 0.02
 
 
@@ -43,12 +43,15 @@ def test_pair_features_and_targets():
                         np.where(w.shape[q] == 1, 0.5 * np.hypot(w.dims[q, 0], w.dims[q, 1]),
                                  0.5 * w.dims[q, 0]))
     sph_i, sph_j = w.shape[I] == 0, w.shape[J] == 0      # spheres have no orientation
-    ref = np.stack([dist / FEAT_L, np.maximum((dist - bound(I) - bound(J)) / GAP_L, -4.0),
+    gap = dist - bound(I) - bound(J)
+    ref = np.stack([np.clip(gap / FINE_L, -16.0, 16.0), gap / FEAT_L,
                     np.where(sph_i, 1.0, np.cos(s[4, I] - phi)), np.where(sph_i, 0.0, np.sin(s[4, I] - phi)),
                     np.where(sph_j, 1.0, np.cos(s[4, J] - phi)), np.where(sph_j, 0.0, np.sin(s[4, J] - phi)),
                     w.dims[I, 0] / FEAT_L, w.dims[I, 1] / FEAT_L, w.dims[J, 0] / FEAT_L,
                     w.dims[J, 1] / FEAT_L, 0.5 * w.shape[I], 0.5 * w.shape[J]], 1)
-    np.testing.assert_allclose(feat, ref, rtol=2e-5, atol=3e-5)
+    # the fine gap magnifies the FP32 rounding of the gap (~1e-7 m) by 1 / 0.001
+    np.testing.assert_allclose(feat[:, 0], ref[:, 0], rtol=0, atol=1e-3)
+    np.testing.assert_allclose(feat[:, 1:], ref[:, 1:], rtol=2e-5, atol=3e-5)
     ow = O.OracleWorld(w)
     _, om, _ = ow.step(w.state0, np.zeros((w.n_agents_total, 2)))
     contact = (flags & 2) != 0
@@ -136,10 +139,9 @@ def test_surrogate_force_error_and_speed(trained):
     """65,536 environments x 16 sphere agents: contact-force error of the
     surrogate step against the exact step over 5 steps of an exact
     trajectory, and both step times, at the fallback rule's 0.5 r and at
-    stricter fractions (more pairs on the exact path). The bar is 3e-2 at
-    every step for 0.5 r; the largest error of each fraction and its speed
-    relative to the exact step are printed (the speed at 1e-2 is that of the
-    largest fraction whose error stays within 1e-2, if one does)."""
+    stricter fractions (more pairs on the exact path). Bars: 2e-2 at every
+    step for 0.5 r, and some fraction within 1e-2 at every step; the speed at
+    1e-2 is that of the largest such fraction."""
     from paper_2207_03530_amd import surrogate as S
     net, hist = trained
     assert hist[-1] < hist[0]
@@ -154,9 +156,12 @@ def test_surrogate_force_error_and_speed(trained):
               f"surrogate {times['surrogate']:.3f} ms, speedup {speed:.3f}")
         summary.append((frac, float(np.max(errs)), speed))
         if frac == 0.5:
-            assert np.max(errs) <= 3e-2
+            assert np.max(errs) <= 2e-2
     within = [x for x in summary if x[1] <= 1e-2]
     print(f"max error and speedup per fallback fraction: {summary}; within 1e-2: {within or 'none'}")
+    assert within, "no fallback fraction keeps the contact-force error within 1e-2"
+    print(f"surrogate speed at <= 1e-2 relative force error (fallback beyond {within[0][0]} r): "
+          f"{within[0][2]:.3f} x the exact step")
 
 
 def test_surrogate_gradient_sees_contact_onset(trained):
@@ -172,8 +177,8 @@ def test_surrogate_gradient_sees_contact_onset(trained):
     s = np.linspace(dmin + 0.004, dmin - 0.004, 801)        # centre distance, approaching
     n = s.size
     X = np.zeros((n, 12), np.float32)
-    X[:, 0] = s / FEAT_L                                      # i on the +x side of j, theta = 0
-    X[:, 1] = (s - dmin) / GAP_L
+    X[:, 0] = (s - dmin) / FINE_L                             # i on the +x side of j, theta = 0
+    X[:, 1] = (s - dmin) / FEAT_L
     X[:, 2] = 1.0
     X[:, 4] = 1.0
     X[:, 6] = r / FEAT_L
@@ -188,7 +193,7 @@ def test_surrogate_gradient_sees_contact_onset(trained):
     torch.cuda.synchronize()
     yhat = Y.cpu().numpy()[:, 0] * c * FORCE_L
     gx = dX.cpu().numpy()
-    dyds = (gx[:, 0] / FEAT_L + gx[:, 1] / GAP_L) * c * FORCE_L  # d(force along e)/ds
+    dyds = (gx[:, 0] / FINE_L + gx[:, 1] / FEAT_L) * c * FORCE_L  # d(force along e)/ds
     # exact force along the sweep and its pointwise derivative
     z = (dmin - s) / k
     F = np.where(s <= dmin, c * k * (np.maximum(z, 0) + np.log1p(np.exp(-np.abs(z)))), 0.0)
