@@ -169,32 +169,26 @@ __device__ __forceinline__ void consider(ClosestT<S>& b, V2T<S> e, V2T<S> p0, V2
                                          bool of_lo) {
   const V2T<S> r = vsub(e, p0);
   const S st = vdot(r, u);
-  if (val(st) > 0.0f && val(st) < len) {
-    const S sn = vcross(u, r);  // offset along the left normal (-u.y, u.x)
-    const S d2 = sn * sn;
-    if (val(d2) < b.d2v) {
-      b.d2v = val(d2);
-      b.d2 = d2;
-      b.d = s_abs(sn);
-      b.e = e;
-      b.q = {s_fma(u.x, st, p0.x), s_fma(u.y, st, p0.y)};
-      b.dir = val(sn) >= 0.0f ? V2T<S>{-u.y, u.x} : V2T<S>{u.y, -u.x};
-      b.exact = true;
-      b.of_lo = of_lo;
-    }
-  } else {
-    const V2T<S> q = val(st) <= 0.0f ? p0 : V2T<S>{s_fma(u.x, S(len), p0.x), s_fma(u.y, S(len), p0.y)};
-    const V2T<S> w = vsub(e, q);
-    const S d2 = vdot(w, w);
-    if (val(d2) < b.d2v) {
-      b.d2v = val(d2);
-      b.d2 = d2;
-      b.d = S(-1.0f);
-      b.e = e;
-      b.q = q;
-      b.exact = false;
-      b.of_lo = of_lo;
-    }
+  const bool inner = val(st) > 0.0f && val(st) < len;
+  // interior foot: offset along the left normal (-u.y, u.x)
+  const S sn = vcross(u, r);
+  const V2T<S> qi = {s_fma(u.x, st, p0.x), s_fma(u.y, st, p0.y)};
+  // foot at an end of the edge
+  const V2T<S> p1 = {s_fma(u.x, S(len), p0.x), s_fma(u.y, S(len), p0.y)};
+  const V2T<S> qe = val(st) <= 0.0f ? V2T<S>{p0.x, p0.y} : p1;
+  const V2T<S> we = vsub(e, qe);
+  const S d2 = inner ? sn * sn : vdot(we, we);
+  // one update of every field (values, no field chosen by address), so the
+  // running minimum stays in registers
+  if (val(d2) < b.d2v) {
+    b.d2v = val(d2);
+    b.d2 = d2;
+    b.d = inner ? s_abs(sn) : S(-1.0f);
+    b.e = e;
+    b.q = inner ? qi : qe;
+    b.dir = val(sn) >= 0.0f ? V2T<S>{-u.y, u.x} : V2T<S>{u.y, -u.x};
+    b.exact = inner;
+    b.of_lo = of_lo;
   }
 }
 
@@ -365,6 +359,20 @@ template <class S> __device__ __forceinline__ S proj_max(const PolyT<S>& p, V2T<
   return a;
 }
 
+// Axis k of the pair: lo's axes first, then hi's, chosen by value selects
+// (choosing between array elements by address keeps both polygons in
+// scratch memory instead of registers).
+template <class S>
+__device__ __forceinline__ V2T<S> pair_axis(const PolyT<S>& A, const PolyT<S>& B, int k) {
+  const V2T<S> a0 = A.ax[0], a1 = A.ax[1], b0 = B.ax[0], b1 = B.ax[1];
+  const bool in_a = k < A.na;
+  const bool first = in_a ? (k == 0) : (k - A.na == 0);
+  V2T<S> r;
+  r.x = in_a ? (first ? a0.x : a1.x) : (first ? b0.x : b1.x);
+  r.y = in_a ? (first ? a0.y : a1.y) : (first ? b0.y : b1.y);
+  return r;
+}
+
 // Line/box and box/box by the separating-axis test: apart -> exact distance
 // between the convex sets (vertex against edge, lo's vertices first);
 // overlapping -> smallest overlap over the axes (lo's first), contact point
@@ -380,7 +388,7 @@ template <class S> __device__ HitT<S> poly_poly(const GeoT<S>& I, const GeoT<S>&
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (k < A.na + B.na) {
-      const V2T<S> s = k < A.na ? A.ax[k] : B.ax[k - A.na];
+      const V2T<S> s = pair_axis(A, B, k);
       float mina, maxa, minb, maxb;
       project(A, s, &mina, &maxa);
       project(B, s, &minb, &maxb);
@@ -420,7 +428,7 @@ template <class S> __device__ HitT<S> poly_poly(const GeoT<S>& I, const GeoT<S>&
   V2T<S> s = A.ax[0];
 #pragma unroll
   for (int k = 1; k < 4; ++k)
-    if (k == best_k) s = k < A.na ? A.ax[k] : B.ax[k - A.na];
+    if (k == best_k) s = pair_axis(A, B, k);
   // overlap along the winning axis with derivatives
   h.d = best_plus ? -(proj_max(B, s) - proj_min(A, s)) : -(proj_max(A, s) - proj_min(B, s));
   h.n = best_plus ? s : vneg(s);

@@ -92,6 +92,12 @@ struct StepArgs {
   const int32_t* env_off;    // [n_envs + 1] first entity of each environment
   int32_t n_envs;
   int32_t pad;
+  // pair-queue plans (batches with boxes or segments, environments of at
+  // most 32 entities): queue capacity per pair class (sphere-box,
+  // sphere-segment, box-box, box-segment, segment-segment) and their sum;
+  // all 0 for the other plans
+  int32_t pq_cap[6];
+  int32_t pad2[2];
   WorldK w;
 };
 
@@ -134,9 +140,10 @@ hipError_t launch_rollout(const StepArgs& a, int groups, int block, bool spheres
 hipError_t launch_backward(const BackArgs& a, int groups, int block, hipStream_t s);
 // Device function of the rollout kernel launched by launch_rollout (for
 // explicit graph construction) and its dynamic LDS size.
-const void* rollout_kernel(bool spheres_only, bool quad, int block, int max_n, float min_dist,
-                           bool out);
-size_t rollout_lds_bytes(int max_stage, bool spheres_only, bool quad, int block, int max_n);
+const void* rollout_kernel(bool spheres_only, bool quad, bool pq, int block, int max_n,
+                           float min_dist, bool out);
+size_t rollout_lds_bytes(int max_stage, bool spheres_only, bool quad, int pq_total, int block,
+                         int max_n);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);

@@ -14,7 +14,15 @@
 // cross-lane reduction (and no float atomic) is needed: results do not depend
 // on how environments are packed into groups. Lanes are sorted by shape
 // within a group so that a wavefront mostly runs one narrow-phase routine.
-// Poses are double-buffered in LDS: one barrier per step. Sphere batches have
+// Poses are double-buffered in LDS: one barrier per step. The pair-queue
+// variant (PQ) evaluates every pair that involves a box or a segment once:
+// the lane that owns the pair (the lower index, or the one with a lane when
+// the other has none) appends it to a per-class queue in LDS, all lanes of
+// the group then work through the queues class by class (one narrow-phase
+// routine per wavefront most of the time), and each entity adds its side of
+// the results in the same class and partner order as the plain variant, bit
+// for bit. A pair that finds its class queue full is evaluated by both of its
+// lanes, as in the plain variant. Sphere batches have
 // their own kernels (k_rollout_sph: centres only in LDS, hoisted contact
 // distances; k_rollout_quad: environments of at most 4 movers on one lane
 // quad, centres exchanged by DPP, no LDS).
@@ -55,6 +63,63 @@ __device__ __forceinline__ float bounding_radius(int shape, float d0, float d1) 
   return 0.5f * d0;
 }
 
+// Pair classes of the queue (pairs with at least one box or segment).
+constexpr int PQ_SB = 0, PQ_SL = 1, PQ_BB = 2, PQ_BL = 3, PQ_LL = 4, PQ_CLASSES = 5;
+__device__ __forceinline__ int pair_class(int sa, int sb) {
+  const int lo = min(sa, sb), hi = max(sa, sb);  // SPHERE < BOX < LINE
+  if (lo == SPHERE) return hi == BOX ? PQ_SB : PQ_SL;
+  if (lo == BOX) return hi == BOX ? PQ_BB : PQ_BL;
+  return PQ_LL;
+}
+
+// narrow(lo, hi) for a pair of class C: the same routines in the same order,
+// with the shape pair fixed at compile time up to which side is the sphere.
+template <int C> __device__ __forceinline__ Hit narrow_class(const Geo& lo, const Geo& hi) {
+  if constexpr (C == PQ_SB || C == PQ_SL) {
+    if (lo.shape == SPHERE) return C == PQ_SL ? sphere_line(lo.c, hi) : sphere_box(lo.c, hi);
+    const Hit r = C == PQ_SL ? sphere_line(hi.c, lo) : sphere_box(hi.c, lo);
+    Hit o;
+    o.d = r.d;
+    o.n = vneg(r.n);
+    o.plo = r.phi;
+    o.phi = r.plo;
+    return o;
+  } else if constexpr (C == PQ_LL) {
+    return line_line(lo, hi);
+  } else {
+    return poly_poly(lo, hi);
+  }
+}
+
+__device__ __forceinline__ Geo staged_geo(const float4 P, const float4 S) {
+  Geo g;
+  g.c = V2{P.x, P.y};
+  g.cs = P.z;
+  g.sn = P.w;
+  g.d0 = S.x;
+  g.d1 = S.y;
+  g.shape = __float_as_int(S.w) & 0xff;
+  return g;
+}
+
+// One queued pair: contact test and force of Eq. (2) with the torques of
+// Eq. (3) for both sides, as pair_force computes them for each side (the
+// higher index receives the negated force). res = (f_lo, tq_lo, tq_hi).
+template <int C>
+__device__ __forceinline__ bool queued_pair(const float4* cur, const float4* stat, int qa, int qb,
+                                            const WorldK& w, float4* res) {
+  const float4 Sa = stat[qa], Sb = stat[qb];
+  const Geo lo = staged_geo(cur[qa], Sa), hi = staged_geo(cur[qb], Sb);
+  const float dmin = (Sa.z + Sb.z) + w.min_dist;
+  const Hit h = narrow_class<C>(lo, hi);
+  if (!(h.d <= dmin)) return false;
+  const float F = contact_mag(dmin, h.d, w);
+  const V2 flo = V2{F * h.n.x, F * h.n.y};
+  const V2 fhi = V2{-F * h.n.x, -F * h.n.y};
+  *res = make_float4(flo.x, flo.y, vcross(vsub(h.plo, lo.c), flo), vcross(vsub(h.phi, hi.c), fhi));
+  return true;
+}
+
 // Persistent rollout: T steps of every environment of the group. A lane's
 // contacts are accumulated partner class by partner class (spheres, boxes,
 // segments), each class in partner order.
@@ -63,14 +128,25 @@ __device__ __forceinline__ float bounding_radius(int shape, float d0, float d1) 
 // narrow-phase distance) from the lane's own cannot be in contact, so only
 // the other partners run the narrow phase -- in partner order, with the
 // same arithmetic, hence with the results of testing every partner.
-template <int MAXB>
+// PQ: every environment has at most 32 entities; a.pq_cap[c] is the queue
+// capacity of pair class c, a.pq_cap[PQ_CLASSES] their sum.
+template <int MAXB, bool PQ>
 __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
   extern __shared__ float4 lds[];
   const int E = a.max_stage;
   float4* buf0 = lds;
   float4* buf1 = lds + E;
   float4* stat = lds + 2 * E;
-  float* brad = reinterpret_cast<float*>(lds + 3 * E);  // bounding radius, NaN: not collidable
+  const int QT = PQ ? a.pq_cap[PQ_CLASSES] : 0;
+  float4* qres = lds + 3 * E;                                // [QT] queued pair results
+  float* brad = reinterpret_cast<float*>(lds + 3 * E + QT);  // bounding radius, NaN: not collidable
+  uint32_t* hitw = reinterpret_cast<uint32_t*>(brad + E);    // [E] queued partners in contact
+  uint32_t* selfw = hitw + E;                                // [E] partners the lane evaluates itself
+  int* qcnt = reinterpret_cast<int*>(selfw + E);             // [8] queue fill per class
+  int* qcap = qcnt + 8;                                      // [8] capacity per class
+  int* qbase = qcnt + 16;                                    // [8] first entry of each class
+  uint32_t* qent = reinterpret_cast<uint32_t*>(qcnt + 24);   // [QT] slot_lo | slot_hi << 11 | lo << 22 | hi << 27
+  uint16_t* qmap = reinterpret_cast<uint16_t*>(qent + QT);   // [E][32] queue entry of (entity, partner)
   const int g = blockIdx.x, l = threadIdx.x, B = blockDim.x;
   const int N = a.w.N;
   const int s0 = a.stage_off[g], ns = a.stage_off[g + 1] - s0;
@@ -85,6 +161,15 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
     stat[s] = make_float4(p.d0, p.d1, p.rho, __int_as_float(p.sf));
     brad[s] = ((p.sf >> 8) & COLLIDABLE) ? bounding_radius(p.sf & 0xff, p.d0, p.d1)
                                          : __int_as_float(0x7fc00000);
+  }
+  if (PQ && l == 0) {
+    int acc = 0;
+#pragma unroll
+    for (int c = 0; c < PQ_CLASSES; ++c) {
+      qcap[c] = a.pq_cap[c];
+      qbase[c] = acc;
+      acc += a.pq_cap[c];
+    }
   }
   const LaneRec r = a.lanes[(size_t)g * B + l];
   const bool act = r.ent >= 0;
@@ -118,17 +203,33 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
   }
   __syncthreads();
   // shape classes of the first 32 partners (static for the whole rollout)
-  uint32_t cls_sph0 = 0, cls_box0 = 0;
+  uint32_t cls_sph0 = 0, cls_box0 = 0, own0 = 0;
   for (int u = 0; u < min(32, nloc); ++u) {
-    const int so = __float_as_int(stat[r.lo + u].w) & 0xff;
+    const int sfo = __float_as_int(stat[r.lo + u].w);
+    const int so = sfo & 0xff;
     cls_sph0 |= (so == SPHERE ? 1u : 0u) << u;
     cls_box0 |= (so == BOX ? 1u : 0u) << u;
+    // PQ: pairs this lane owns (queues): higher partners, and partners without a lane
+    const bool other_lane = ((sfo >> 8) & (MOVABLE | ROTATABLE)) != 0;
+    if (PQ && (u > myloc || !other_lane) && !(p.excl != -1 && excluded(p.excl, u)))
+      own0 |= 1u << u;
   }
   for (int t = 0; t < a.T; ++t) {
     float4* cur = (t & 1) ? buf1 : buf0;
     float cs = 1.0f, sn = 0.0f;
     if (act && shape != SPHERE) sincosf(th, &sn, &cs);
-    if (t > 0) {
+    if (PQ) {
+      // A lane clears only its own words (another wavefront may still be
+      // reading its own ones from the previous step); the words of slots
+      // without a lane are written but never read.
+      if (act) {
+        if (t > 0) cur[r.slot] = make_float4(x, y, cs, sn);
+        hitw[r.slot] = 0u;
+        selfw[r.slot] = 0u;
+      }
+      if (l < 8) qcnt[l] = 0;
+      __syncthreads();
+    } else if (t > 0) {
       if (act) cur[r.slot] = make_float4(x, y, cs, sn);
       __syncthreads();
     }
@@ -144,7 +245,128 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
     }
     const bool last = t == a.T - 1;
     uint8_t* mk = (last && a.mask) ? a.mask : nullptr;
-    if (collide) {
+    if (PQ) {
+      // Broad phase of the lane's partners; the owned candidates of a pair
+      // class are queued (sphere pairs of a sphere lane stay on the lane).
+      uint32_t cand = 0;
+      if (collide) {
+        const float rs = bounding_radius(shape, p.d0, p.d1);
+        const float reach = w.min_dist + 1e-4f + 1e-5f * (fabsf(x) + fabsf(y));
+        for (int u = 0; u < nloc; ++u) {
+          const int q = r.lo + u;
+          const float4 P = cur[q];
+          const float dx = x - P.x, dy = y - P.y;
+          const float lim = (rs + brad[q]) + reach;
+          cand |= (dx * dx + dy * dy <= lim * lim ? 1u : 0u) << u;
+        }
+        cand &= ~(1u << myloc);
+        uint32_t own = cand & own0 & (shape == SPHERE ? ~cls_sph0 : ~0u);
+        while (own) {
+          const int u = __builtin_ctz(own);
+          own &= own - 1;
+          const int so = (cls_sph0 >> u) & 1 ? SPHERE : ((cls_box0 >> u) & 1 ? BOX : LINE);
+          const int c = pair_class(shape, so);
+          const int k = atomicAdd(&qcnt[c], 1);
+          const int qo = r.lo + u;
+          if (k < qcap[c]) {
+            const int e = qbase[c] + k;
+            const int sa = min(r.slot, qo), sb = max(r.slot, qo);
+            const int la = min(myloc, u), lb = max(myloc, u);
+            qent[e] = (uint32_t)sa | ((uint32_t)sb << 11) | ((uint32_t)la << 22) | ((uint32_t)lb << 27);
+            qmap[r.slot * 32 + u] = (uint16_t)e;
+            qmap[qo * 32 + myloc] = (uint16_t)e;
+          } else {
+            atomicOr(&selfw[r.slot], 1u << u);
+            atomicOr(&selfw[qo], 1u << myloc);
+          }
+        }
+      }
+      lds_barrier();
+      // Every lane of the group works through the queues, class by class.
+      int n_c[PQ_CLASSES], total = 0;
+#pragma unroll
+      for (int c = 0; c < PQ_CLASSES; ++c) {
+        n_c[c] = min(qcnt[c], a.pq_cap[c]);
+        total += n_c[c];
+      }
+      for (int i = l; i < total; i += B) {
+        // class of the i-th queued pair (classes back to back)
+        int c = 0, k = i;
+#pragma unroll
+        for (int cc = 0; cc < PQ_CLASSES - 1; ++cc) {
+          if (c == cc && k >= n_c[cc]) {
+            k -= n_c[cc];
+            c = cc + 1;
+          }
+        }
+        const int e = qbase[c] + k;
+        const uint32_t ent = qent[e];
+        const int qa = ent & 0x7ff, qb = (ent >> 11) & 0x7ff;
+        const int la = (ent >> 22) & 31, lb = ent >> 27;
+        float4 res;
+        bool hit;
+        switch (c) {
+          case PQ_SB: hit = queued_pair<PQ_SB>(cur, stat, qa, qb, w, &res); break;
+          case PQ_SL: hit = queued_pair<PQ_SL>(cur, stat, qa, qb, w, &res); break;
+          case PQ_BB: hit = queued_pair<PQ_BB>(cur, stat, qa, qb, w, &res); break;
+          case PQ_BL: hit = queued_pair<PQ_BL>(cur, stat, qa, qb, w, &res); break;
+          default: hit = queued_pair<PQ_LL>(cur, stat, qa, qb, w, &res); break;
+        }
+        if (hit) {
+          qres[e] = res;
+          atomicOr(&hitw[qa], 1u << lb);
+          atomicOr(&hitw[qb], 1u << la);
+        }
+      }
+      lds_barrier();
+      if (collide) {
+        const uint32_t hits = hitw[r.slot], mine = selfw[r.slot];
+        Geo self;
+        self.c = V2{x, y};
+        self.cs = cs;
+        self.sn = sn;
+        self.d0 = p.d0;
+        self.d1 = p.d1;
+        self.shape = shape;
+        // partners class by class (sphere, box, segment), each in partner
+        // order: queued results, or the lane's own evaluation
+        auto run = [&](auto cls, uint32_t cm, bool direct) {
+          constexpr int OTHER = decltype(cls)::value;
+          while (cm) {
+            const int u = __builtin_ctz(cm);
+            cm &= cm - 1;
+            const int q = r.lo + u;
+            bool hit = true;
+            if (direct || ((mine >> u) & 1u)) {
+              if (p.excl != -1 && excluded(p.excl, u)) continue;
+              hit = pair_force<false, OTHER>(self, p.rho, myloc, cur[q], stat[q], u, w, fx, fy, tq);
+            } else {
+              const float4 R = qres[qmap[r.slot * 32 + u]];
+              const bool lo_side = myloc < u;
+              fx += lo_side ? R.x : -R.x;
+              fy += lo_side ? R.y : -R.y;
+              tq += lo_side ? R.z : R.w;
+            }
+            if (mk && hit) {
+              const int of = (__float_as_int(stat[q].w) >> 8) & 0xff;
+              const bool other_active = (of & (MOVABLE | ROTATABLE)) != 0;
+              if (myloc < u || !other_active) {
+                const int ia = min(myloc, u), ib = max(myloc, u);
+                const int64_t idx = (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
+                mk[a.pair_off[r.env] + idx] = 1;
+              }
+            }
+          }
+        };
+        const uint32_t mline = ~(cls_sph0 | cls_box0);
+        if (shape == SPHERE)
+          run(std::integral_constant<int, SPHERE>{}, cand & cls_sph0, true);
+        else
+          run(std::integral_constant<int, SPHERE>{}, (hits | mine) & cls_sph0, false);
+        run(std::integral_constant<int, BOX>{}, (hits | mine) & cls_box0, false);
+        run(std::integral_constant<int, LINE>{}, (hits | mine) & mline, false);
+      }
+    } else if (collide) {
       Geo self;
       self.c = V2{x, y};
       self.cs = cs;
@@ -837,18 +1059,24 @@ int grid_for(int64_t n) {
 // Padding slots of the sphere kernel chosen for a launch shape.
 int sph_pad(int block, int max_n) { return block <= 256 ? sph_nb(max_n) : 0; }
 
-const void* rollout_kernel(bool spheres_only, bool quad, int block, int max_n, float min_dist,
-                           bool out) {
+const void* rollout_kernel(bool spheres_only, bool quad, bool pq, int block, int max_n,
+                           float min_dist, bool out) {
   const bool md = min_dist != 0.0f;
   // quad: max_n carries the most static collidable entities of an environment
   if (quad) return max_n <= 2 ? quad_pick<2>(md, out) : quad_pick<4>(md, out);
   if (spheres_only)
     return block > 256 ? sph_pick<1024, 0>(md, out) : sph_kernel256(sph_pad(block, max_n), md, out);
-  return block <= 256 ? (const void*)k_rollout<256> : (const void*)k_rollout<1024>;
+  if (pq) return block <= 256 ? (const void*)k_rollout<256, true> : (const void*)k_rollout<1024, true>;
+  return block <= 256 ? (const void*)k_rollout<256, false> : (const void*)k_rollout<1024, false>;
 }
 
-size_t rollout_lds_bytes(int max_stage, bool spheres_only, bool quad, int block, int max_n) {
+size_t rollout_lds_bytes(int max_stage, bool spheres_only, bool quad, int pq_total, int block,
+                         int max_n) {
   if (quad) return 0;
+  if (!spheres_only && pq_total > 0)
+    return (size_t)(3 * max_stage + pq_total) * sizeof(float4) +
+           (size_t)max_stage * (3 * sizeof(uint32_t) + 32 * sizeof(uint16_t)) + 24 * sizeof(int) +
+           (size_t)pq_total * sizeof(uint32_t);
   if (!spheres_only) return (size_t)max_stage * (3 * sizeof(float4) + sizeof(float));
   return (size_t)(max_stage + sph_pad(block, max_n)) * 3 * sizeof(float2);
 }
@@ -857,8 +1085,9 @@ hipError_t launch_rollout(const StepArgs& a, int groups, int block, bool spheres
                           hipStream_t s) {
   const bool quad = a.quad != nullptr;
   const bool out = a.traj || a.mask || a.forces;
-  const void* f = rollout_kernel(spheres_only, quad, block, a.max_n, a.w.min_dist, out);
-  const size_t shm = rollout_lds_bytes(a.max_stage, spheres_only, quad, block, a.max_n);
+  const int pq_total = a.pq_cap[PQ_CLASSES];
+  const void* f = rollout_kernel(spheres_only, quad, pq_total > 0, block, a.max_n, a.w.min_dist, out);
+  const size_t shm = rollout_lds_bytes(a.max_stage, spheres_only, quad, pq_total, block, a.max_n);
   StepArgs args = a;
   void* kargs[1] = {&args};
   return hipLaunchKernel(f, dim3(groups), dim3(block), kargs, shm, s);

@@ -58,6 +58,8 @@ struct Plan {
   int max_stage = 0;
   int max_n = 0;  // largest environment of the plan
   bool quad = false;          // quad schedule (d_quad), no lane records
+  bool pq = false;            // pair-queue variant of the entity-lane kernel
+  int32_t pq_cap[6] = {0, 0, 0, 0, 0, 0};  // queue capacity per pair class, then the sum
   QuadEnv* d_quad = nullptr;
   LaneRec* d_lanes = nullptr;
   int32_t* d_stage_off = nullptr;
@@ -278,14 +280,36 @@ vmas_status validate(const vmas_world_params* pr, const vmas_batch_desc* d, Host
 }
 
 // Builds one launch plan on the host and uploads it.
+// Queue capacity per pair class of the pair-queue plans: the most eligible
+// pairs of the class in one group, at most PQ_CAP_MAX (pairs beyond a full
+// queue are evaluated by both lanes).
+constexpr int PQ_CAP_MAX = 256;
+constexpr size_t PQ_LDS_MAX = 64 * 1024;
+
+int pq_pair_class(int sa, int sb) {
+  const int lo = std::min(sa, sb), hi = std::max(sa, sb);
+  if (lo == SPHERE) return hi == BOX ? 0 : 1;
+  if (lo == BOX) return hi == BOX ? 2 : 3;
+  return 4;
+}
+
+bool excludes(int32_t excl, int loc) {
+  if (excl == -1) return false;
+  for (int k = 0; k < 4; ++k)
+    if ((((uint32_t)excl >> (8 * k)) & 0xffu) == (uint32_t)loc) return true;
+  return false;
+}
+
+// pq_ent: entity table of a pair-queue plan (NULL for the other plans).
 vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8_t>& shape,
                        const std::vector<uint8_t>& flags, int block, bool sorted, Plan& p,
-                       bool all_lanes = false) {
+                       bool all_lanes = false, const std::vector<EntParam>* pq_ent = nullptr) {
   p.block = block;
   p.sorted = sorted;
   p.all_lanes = all_lanes;
-  p.name = std::string(all_lanes ? "adjoint-lane/" : "entity-lane/") + std::to_string(block) +
-           (sorted ? "/size-sorted" : "/natural");
+  p.pq = pq_ent != nullptr;
+  p.name = std::string(all_lanes ? "adjoint-lane/" : (p.pq ? "pair-queue/" : "entity-lane/")) +
+           std::to_string(block) + (sorted ? "/size-sorted" : "/natural");
   const int E = b->n_envs;
   auto has_lane = [&](int i) { return all_lanes || (flags[i] & (MOVABLE | ROTATABLE)) != 0; };
   std::vector<int> active(E, 0);
@@ -360,6 +384,42 @@ vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8
   p.max_stage = max_stage;
   p.max_n = 0;
   for (int32_t m : maxn) p.max_n = std::max(p.max_n, (int)m);
+  if (p.pq) {
+    // environments of at most 32 entities; capacities from the eligible
+    // pairs (both collidable, one with a lane, no joint exclusion, not
+    // sphere-sphere) of each group
+    if (p.max_n > 32) {
+      p.valid = false;
+      return VMAS_OK;
+    }
+    const std::vector<EntParam>& ent = *pq_ent;
+    int cap[5] = {0, 0, 0, 0, 0};
+    for (int g = 0; g < G; ++g) {
+      int cnt[5] = {0, 0, 0, 0, 0};
+      for (int e : groups[g]) {
+        for (int i = h.off[e]; i < h.off[e + 1]; ++i)
+          for (int j = i + 1; j < h.off[e + 1]; ++j) {
+            if (!(flags[i] & COLLIDABLE) || !(flags[j] & COLLIDABLE)) continue;
+            if (!(flags[i] & (MOVABLE | ROTATABLE)) && !(flags[j] & (MOVABLE | ROTATABLE))) continue;
+            if (shape[i] == SPHERE && shape[j] == SPHERE) continue;
+            if (excludes(ent[i].excl, j - h.off[e])) continue;
+            ++cnt[pq_pair_class(shape[i], shape[j])];
+          }
+      }
+      for (int c = 0; c < 5; ++c) cap[c] = std::max(cap[c], std::min(cnt[c], PQ_CAP_MAX));
+    }
+    int total = 0;
+    for (int c = 0; c < 5; ++c) {
+      p.pq_cap[c] = cap[c];
+      total += cap[c];
+    }
+    p.pq_cap[5] = total;
+    if (total == 0 ||
+        rollout_lds_bytes(p.max_stage, false, false, total, block, p.max_n) > PQ_LDS_MAX) {
+      p.valid = false;
+      return VMAS_OK;
+    }
+  }
   vmas_status s;
   if ((s = upload(&p.d_lanes, lane.data(), lane.size())) != VMAS_OK) return s;
   if ((s = upload(&p.d_stage_off, stage_off.data(), stage_off.size())) != VMAS_OK) return s;
@@ -427,6 +487,7 @@ StepArgs make_args(vmas_batch* b, const Plan& p) {
   a.quad = p.quad ? p.d_quad : nullptr;
   a.env_off = b->d_env_off;
   a.n_envs = b->n_envs;
+  for (int c = 0; c < 6; ++c) a.pq_cap[c] = p.pq ? p.pq_cap[c] : 0;
   a.w = b->w;
   return a;
 }
@@ -634,9 +695,27 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
   // the largest workgroups (fewest atomics on one counter)
   b->lane_plan = first_valid;
   for (int q = 0; q < (int)b->plans.size(); ++q)
-    if (b->plans[q].valid && !b->plans[q].quad && b->plans[q].block <= 256 &&
+    if (b->plans[q].valid && !b->plans[q].quad && !b->plans[q].pq && b->plans[q].block <= 256 &&
         b->plans[q].block > b->plans[b->lane_plan].block)
       b->lane_plan = q;
+  if (!spheres_only && max_env <= 32) {
+    // pair-queue plans: every pair with a box or a segment evaluated once
+    for (int sorted = 0; sorted < 2; ++sorted) {
+      for (int bi = 0; bi < 3; ++bi) {
+        Plan p;
+        if ((s = build_plan(b, h, shape, flags, blocks[bi], sorted != 0, p, false, &ent)) !=
+            VMAS_OK) {
+          free_plan(p);
+          free_batch(b);
+          return s;
+        }
+        if (p.valid)
+          b->plans.push_back(p);
+        else
+          free_plan(p);
+      }
+    }
+  }
   {
     Plan p;
     if ((s = build_quad_plan(b, h, flags, p)) != VMAS_OK) {
@@ -772,10 +851,11 @@ vmas_status vmas_rollout_graph(vmas_batch* b, float* state, const float* actions
   void* args[1] = {&a};
   hipKernelNodeParams kp{};
   kp.func = const_cast<void*>(
-      rollout_kernel(b->spheres_only, p.quad, p.block, p.max_n, b->w.min_dist, false));
+      rollout_kernel(b->spheres_only, p.quad, p.pq, p.block, p.max_n, b->w.min_dist, false));
   kp.gridDim = dim3(p.groups);
   kp.blockDim = dim3(p.block);
-  kp.sharedMemBytes = (unsigned)rollout_lds_bytes(p.max_stage, b->spheres_only, p.quad, p.block, p.max_n);
+  kp.sharedMemBytes = (unsigned)rollout_lds_bytes(p.max_stage, b->spheres_only, p.quad,
+                                                  p.pq ? p.pq_cap[5] : 0, p.block, p.max_n);
   kp.kernelParams = args;
   kp.extra = nullptr;
   if (!b->gexec || b->graph_T != T || b->graph_plan != b->cur || b->graph_drawn != drawn) {
