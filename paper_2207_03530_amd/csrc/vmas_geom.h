@@ -230,16 +230,19 @@ template <class S> __device__ HitT<S> sphere_line(V2T<S> c, const GeoT<S>& l) {
 // Two segments: orientation-sign crossing test (collinear overlap counts as
 // crossing); apart -> exact segment distance; crossing -> separating-axis
 // depth of the endpoint nearest to the other supporting line.
-template <class S> __device__ HitT<S> line_line(const GeoT<S>& I, const GeoT<S>& J) {
+// cutoff as for poly_poly: apart segments one of which lies wholly on one
+// side of the other's line, farther than cutoff, are returned at +infinity.
+template <class S>
+__device__ HitT<S> line_line(const GeoT<S>& I, const GeoT<S>& J, float cutoff = INFINITY) {
   V2T<S> ai, bi, aj, bj;
   line_ends(I, &ai, &bi);
   line_ends(J, &aj, &bj);
   const V2T<S> ni = {-I.sn, I.cs}, nj = {-J.sn, J.cs};
   const V2T<S> ui = vsub(bi, ai), uj = vsub(bj, aj);
-  const int o1 = fsign(val(vcross(ui, vsub(aj, ai))));
-  const int o2 = fsign(val(vcross(ui, vsub(bj, ai))));
-  const int o3 = fsign(val(vcross(uj, vsub(ai, aj))));
-  const int o4 = fsign(val(vcross(uj, vsub(bi, aj))));
+  // offsets of each segment's ends from the other's line, times its length
+  const float c1 = val(vcross(ui, vsub(aj, ai))), c2 = val(vcross(ui, vsub(bj, ai)));
+  const float c3 = val(vcross(uj, vsub(ai, aj))), c4 = val(vcross(uj, vsub(bi, aj)));
+  const int o1 = fsign(c1), o2 = fsign(c2), o3 = fsign(c3), o4 = fsign(c4);
   bool crossing;
   if ((o1 | o2 | o3 | o4) == 0) {
     const float tu = val(vdot(ui, ui));
@@ -249,6 +252,17 @@ template <class S> __device__ HitT<S> line_line(const GeoT<S>& I, const GeoT<S>&
     crossing = (o1 * o2 <= 0) && (o3 * o4 <= 0);
   }
   if (!crossing) {
+    // The distance is at least the smaller offset of a segment lying on one
+    // side of the other's line (the offsets carry the length |u| ~ d0; the
+    // factor 1.001 covers the difference).
+    if (cutoff >= 0.0f &&
+        ((o1 == o2 && o1 != 0 && fminf(fabsf(c1), fabsf(c2)) > cutoff * I.d0 * 1.001f) ||
+         (o3 == o4 && o3 != 0 && fminf(fabsf(c3), fabsf(c4)) > cutoff * J.d0 * 1.001f))) {
+      HitT<S> far;
+      far.d = S(INFINITY);
+      far.n = far.plo = far.phi = V2T<S>{S(0.0f), S(0.0f)};
+      return far;
+    }
     ClosestT<S> b;
     b.d2v = INFINITY;
     const V2T<S> ti = {I.cs, I.sn}, tj = {J.cs, J.sn};
@@ -283,22 +297,22 @@ template <class S> __device__ HitT<S> line_line(const GeoT<S>& I, const GeoT<S>&
   return h;
 }
 
-// Convex polygon view of a box (4 CCW vertices, 4 edges, 2 axes) or a line
-// (2 vertices, 1 edge, 1 axis).
+// Convex polygon view of a box (NV = 4: 4 CCW vertices, 4 edges, 2 axes) or
+// a line (NV = 2: 2 vertices, 1 edge, 1 axis); the counts are compile-time
+// constants, so every loop below runs exactly over the real features.
 template <class S> struct PolyT {
-  int nv, ne, na;
   V2T<S> v[4];
   V2T<S> ax[2];
   V2T<S> eu[4];  // unit direction of edge k (from v[k] to v[k+1])
   float el[4];   // its length
 };
+template <int NV> struct PolyN {
+  static constexpr int nv = NV, ne = NV == 4 ? 4 : 1, na = NV == 4 ? 2 : 1;
+};
 
-template <class S> __device__ __forceinline__ void make_poly(const GeoT<S>& g, PolyT<S>& p) {
-  if (g.shape == BOX) {
+template <int NV, class S> __device__ __forceinline__ void make_poly(const GeoT<S>& g, PolyT<S>& p) {
+  if constexpr (NV == 4) {
     const S hx = S(0.5f * g.d0), hy = S(0.5f * g.d1);
-    p.nv = 4;
-    p.ne = 4;
-    p.na = 2;
     p.v[0] = vadd(g.c, vrot(g.cs, g.sn, V2T<S>{hx, hy}));
     p.v[1] = vadd(g.c, vrot(g.cs, g.sn, V2T<S>{-hx, hy}));
     p.v[2] = vadd(g.c, vrot(g.cs, g.sn, V2T<S>{-hx, -hy}));
@@ -314,112 +328,101 @@ template <class S> __device__ __forceinline__ void make_poly(const GeoT<S>& g, P
     p.el[2] = g.d0;
     p.el[3] = g.d1;
   } else {
-    p.nv = 2;
-    p.ne = 1;
-    p.na = 1;
     line_ends(g, &p.v[0], &p.v[1]);
-    p.v[2] = p.v[1];
-    p.v[3] = p.v[0];
     p.ax[0] = {-g.sn, g.cs};
-    p.ax[1] = p.ax[0];
     p.eu[0] = {g.cs, g.sn};
     p.el[0] = g.d0;
-    p.eu[1] = p.eu[2] = p.eu[3] = p.eu[0];
-    p.el[1] = p.el[2] = p.el[3] = p.el[0];
   }
 }
 
-template <class S> __device__ __forceinline__ void project(const PolyT<S>& p, V2T<S> s, float* mn, float* mx) {
+template <int NV, class S>
+__device__ __forceinline__ void project(const PolyT<S>& p, V2T<S> s, float* mn, float* mx) {
   float a = val(vdot(p.v[0], s)), b = a;
 #pragma unroll
-  for (int q = 1; q < 4; ++q) {
-    if (q < p.nv) {
-      const float t = val(vdot(p.v[q], s));
-      a = fminf(a, t);
-      b = fmaxf(b, t);
-    }
+  for (int q = 1; q < NV; ++q) {
+    const float t = val(vdot(p.v[q], s));
+    a = fminf(a, t);
+    b = fmaxf(b, t);
   }
   *mn = a;
   *mx = b;
 }
 
 // Projection extremes as S (only the winning axis needs derivatives).
-template <class S> __device__ __forceinline__ S proj_min(const PolyT<S>& p, V2T<S> s) {
+template <int NV, class S> __device__ __forceinline__ S proj_min(const PolyT<S>& p, V2T<S> s) {
   S a = vdot(p.v[0], s);
 #pragma unroll
-  for (int q = 1; q < 4; ++q)
-    if (q < p.nv) a = s_min(a, vdot(p.v[q], s));
+  for (int q = 1; q < NV; ++q) a = s_min(a, vdot(p.v[q], s));
   return a;
 }
-template <class S> __device__ __forceinline__ S proj_max(const PolyT<S>& p, V2T<S> s) {
+template <int NV, class S> __device__ __forceinline__ S proj_max(const PolyT<S>& p, V2T<S> s) {
   S a = vdot(p.v[0], s);
 #pragma unroll
-  for (int q = 1; q < 4; ++q)
-    if (q < p.nv) a = s_max(a, vdot(p.v[q], s));
+  for (int q = 1; q < NV; ++q) a = s_max(a, vdot(p.v[q], s));
   return a;
 }
 
-// Axis k of the pair: lo's axes first, then hi's, chosen by value selects
-// (choosing between array elements by address keeps both polygons in
-// scratch memory instead of registers).
-template <class S>
+// Axis k of the pair: lo's axes first, then hi's.
+template <int NA, int NB, class S>
 __device__ __forceinline__ V2T<S> pair_axis(const PolyT<S>& A, const PolyT<S>& B, int k) {
-  const V2T<S> a0 = A.ax[0], a1 = A.ax[1], b0 = B.ax[0], b1 = B.ax[1];
-  const bool in_a = k < A.na;
-  const bool first = in_a ? (k == 0) : (k - A.na == 0);
-  V2T<S> r;
-  r.x = in_a ? (first ? a0.x : a1.x) : (first ? b0.x : b1.x);
-  r.y = in_a ? (first ? a0.y : a1.y) : (first ? b0.y : b1.y);
-  return r;
+  constexpr int na = PolyN<NA>::na;
+  return k < na ? A.ax[k] : B.ax[k - na];
 }
 
 // Line/box and box/box by the separating-axis test: apart -> exact distance
 // between the convex sets (vertex against edge, lo's vertices first);
 // overlapping -> smallest overlap over the axes (lo's first), contact point
 // at the deepest vertex of the shape that does not own the winning axis.
-template <class S> __device__ HitT<S> poly_poly(const GeoT<S>& I, const GeoT<S>& J) {
+// cutoff: when some axis separates the shapes by more than cutoff, the
+// distance (which is at least that separation) is not worked out and d is
+// returned as +infinity; callers that only test d <= d_min pass d_min plus
+// a margin above the FP32 error of the separation and of the distance.
+template <int NA, int NB, class S>
+__device__ HitT<S> poly_poly(const GeoT<S>& I, const GeoT<S>& J, float cutoff) {
+  using PA = PolyN<NA>;
+  using PB = PolyN<NB>;
+  constexpr int NAX = PA::na + PB::na;
   PolyT<S> A, B;
-  make_poly(I, A);
-  make_poly(J, B);
+  make_poly<NA>(I, A);
+  make_poly<NB>(J, B);
   bool separated = false;
-  float best = INFINITY;
+  float best = INFINITY, gap = -INFINITY;
   int best_k = 0;
   bool best_plus = true;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (k < A.na + B.na) {
-      const V2T<S> s = pair_axis(A, B, k);
-      float mina, maxa, minb, maxb;
-      project(A, s, &mina, &maxa);
-      project(B, s, &minb, &maxb);
-      if (maxa < minb || maxb < mina) separated = true;
-      const float op = maxb - mina, om = maxa - minb;
-      const float ov = op <= om ? op : om;
-      if (ov < best) {
-        best = ov;
-        best_k = k;
-        best_plus = op <= om;
-      }
+  for (int k = 0; k < NAX; ++k) {
+    const V2T<S> s = pair_axis<NA, NB>(A, B, k);
+    float mina, maxa, minb, maxb;
+    project<NA>(A, s, &mina, &maxa);
+    project<NB>(B, s, &minb, &maxb);
+    if (maxa < minb || maxb < mina) separated = true;
+    gap = fmaxf(gap, fmaxf(minb - maxa, mina - maxb));
+    const float op = maxb - mina, om = maxa - minb;
+    const float ov = op <= om ? op : om;
+    if (ov < best) {
+      best = ov;
+      best_k = k;
+      best_plus = op <= om;
     }
   }
   if (separated) {
+    if (gap > cutoff) {
+      HitT<S> far;
+      far.d = S(INFINITY);
+      far.n = far.plo = far.phi = V2T<S>{S(0.0f), S(0.0f)};
+      return far;
+    }
     ClosestT<S> b;
     b.d2v = INFINITY;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (q < A.nv) {
+    for (int q = 0; q < PA::nv; ++q) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (e < B.ne) consider(b, A.v[q], B.v[e], B.eu[e], B.el[e], true);
-      }
+      for (int e = 0; e < PB::ne; ++e) consider(b, A.v[q], B.v[e], B.eu[e], B.el[e], true);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (q < B.nv) {
+    for (int q = 0; q < PB::nv; ++q) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (e < A.ne) consider(b, B.v[q], A.v[e], A.eu[e], A.el[e], false);
-      }
+      for (int e = 0; e < PA::ne; ++e) consider(b, B.v[q], A.v[e], A.eu[e], A.el[e], false);
     }
     const V2T<S> fb = {S(1.0f), S(0.0f)};
     return finish_closest(b, fb, fb);
@@ -427,36 +430,37 @@ template <class S> __device__ HitT<S> poly_poly(const GeoT<S>& I, const GeoT<S>&
   HitT<S> h;
   V2T<S> s = A.ax[0];
 #pragma unroll
-  for (int k = 1; k < 4; ++k)
-    if (k == best_k) s = pair_axis(A, B, k);
+  for (int k = 1; k < NAX; ++k) {
+    const V2T<S> sk = pair_axis<NA, NB>(A, B, k);
+    const bool w = k == best_k;
+    s.x = w ? sk.x : s.x;
+    s.y = w ? sk.y : s.y;
+  }
   // overlap along the winning axis with derivatives
-  h.d = best_plus ? -(proj_max(B, s) - proj_min(A, s)) : -(proj_max(A, s) - proj_min(B, s));
+  h.d = best_plus ? -(proj_max<NB>(B, s) - proj_min<NA>(A, s))
+                  : -(proj_max<NA>(A, s) - proj_min<NB>(B, s));
   h.n = best_plus ? s : vneg(s);
   V2T<S> p;
-  if (best_k >= A.na) {  // axis of hi: deepest vertex of lo
+  if (best_k >= PA::na) {  // axis of hi: deepest vertex of lo
     p = A.v[0];
     float m = val(vdot(h.n, p));
 #pragma unroll
-    for (int q = 1; q < 4; ++q) {
-      if (q < A.nv) {
-        const float t = val(vdot(h.n, A.v[q]));
-        if (t < m) {
-          m = t;
-          p = A.v[q];
-        }
+    for (int q = 1; q < PA::nv; ++q) {
+      const float t = val(vdot(h.n, A.v[q]));
+      if (t < m) {
+        m = t;
+        p = A.v[q];
       }
     }
   } else {               // axis of lo: deepest vertex of hi
     p = B.v[0];
     float m = val(vdot(h.n, p));
 #pragma unroll
-    for (int q = 1; q < 4; ++q) {
-      if (q < B.nv) {
-        const float t = val(vdot(h.n, B.v[q]));
-        if (t > m) {
-          m = t;
-          p = B.v[q];
-        }
+    for (int q = 1; q < PB::nv; ++q) {
+      const float t = val(vdot(h.n, B.v[q]));
+      if (t > m) {
+        m = t;
+        p = B.v[q];
       }
     }
   }
@@ -466,7 +470,8 @@ template <class S> __device__ HitT<S> poly_poly(const GeoT<S>& I, const GeoT<S>&
 }
 
 // Narrow phase of a pair that is not sphere-sphere, canonical (lo, hi) order.
-template <class S> __device__ HitT<S> narrow(const GeoT<S>& lo, const GeoT<S>& hi) {
+template <class S>
+__device__ HitT<S> narrow(const GeoT<S>& lo, const GeoT<S>& hi, float cutoff = INFINITY) {
   if (lo.shape == SPHERE) return hi.shape == LINE ? sphere_line(lo.c, hi) : sphere_box(lo.c, hi);
   if (hi.shape == SPHERE) {
     const HitT<S> r = lo.shape == LINE ? sphere_line(hi.c, lo) : sphere_box(hi.c, lo);
@@ -477,8 +482,21 @@ template <class S> __device__ HitT<S> narrow(const GeoT<S>& lo, const GeoT<S>& h
     o.phi = r.plo;
     return o;
   }
-  if (lo.shape == LINE && hi.shape == LINE) return line_line(lo, hi);
-  return poly_poly(lo, hi);
+  if (lo.shape == LINE && hi.shape == LINE) return line_line(lo, hi, cutoff);
+  if (lo.shape == BOX && hi.shape == BOX) return poly_poly<4, 4>(lo, hi, cutoff);
+  if (lo.shape == BOX) return poly_poly<4, 2>(lo, hi, cutoff);
+  return poly_poly<2, 4>(lo, hi, cutoff);
+}
+
+// Cutoff for narrow() in a contact test against d_min: a separation beyond
+// d_min by more than 1e-4 + 1e-5 (|coordinates| + sizes) cannot end in
+// d <= d_min, the FP32 errors of the separation and of the exact distance
+// being a few ulps of the coordinates.
+__device__ __forceinline__ float contact_cutoff(const GeoT<float>& lo, const GeoT<float>& hi,
+                                                float dmin) {
+  const float scale = (fabsf(lo.c.x) + fabsf(lo.c.y) + lo.d0 + lo.d1) +
+                      (fabsf(hi.c.x) + fabsf(hi.c.y) + hi.d0 + hi.d1);
+  return dmin + (1e-4f + 1e-5f * scale);
 }
 
 // Magnitude of Eq. (2): c k log(1 + e^z), z = (d_min - d)/k, in the stable
@@ -557,7 +575,23 @@ __device__ __forceinline__ bool pair_force(const GeoT<float>& self, float rho_s,
   o.d1 = S.y;
   o.shape = so;
   const bool self_lo = a < b;
-  const HitT<float> h = self_lo ? narrow(self, o) : narrow(o, self);
+  // the pair in canonical order, chosen by value (one narrow-phase call)
+  GeoT<float> lo, hi;
+  lo.c.x = self_lo ? self.c.x : o.c.x;
+  lo.c.y = self_lo ? self.c.y : o.c.y;
+  lo.cs = self_lo ? self.cs : o.cs;
+  lo.sn = self_lo ? self.sn : o.sn;
+  lo.d0 = self_lo ? self.d0 : o.d0;
+  lo.d1 = self_lo ? self.d1 : o.d1;
+  lo.shape = self_lo ? self.shape : o.shape;
+  hi.c.x = self_lo ? o.c.x : self.c.x;
+  hi.c.y = self_lo ? o.c.y : self.c.y;
+  hi.cs = self_lo ? o.cs : self.cs;
+  hi.sn = self_lo ? o.sn : self.sn;
+  hi.d0 = self_lo ? o.d0 : self.d0;
+  hi.d1 = self_lo ? o.d1 : self.d1;
+  hi.shape = self_lo ? o.shape : self.shape;
+  const HitT<float> h = narrow(lo, hi, contact_cutoff(lo, hi, dmin));
   if (!(h.d <= dmin)) return false;
   const float F = contact_mag(dmin, h.d, w);
   const float sg = self_lo ? F : -F;

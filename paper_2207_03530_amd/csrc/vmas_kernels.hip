@@ -74,7 +74,8 @@ __device__ __forceinline__ int pair_class(int sa, int sb) {
 
 // narrow(lo, hi) for a pair of class C: the same routines in the same order,
 // with the shape pair fixed at compile time up to which side is the sphere.
-template <int C> __device__ __forceinline__ Hit narrow_class(const Geo& lo, const Geo& hi) {
+template <int C>
+__device__ __forceinline__ Hit narrow_class(const Geo& lo, const Geo& hi, float cutoff) {
   if constexpr (C == PQ_SB || C == PQ_SL) {
     if (lo.shape == SPHERE) return C == PQ_SL ? sphere_line(lo.c, hi) : sphere_box(lo.c, hi);
     const Hit r = C == PQ_SL ? sphere_line(hi.c, lo) : sphere_box(hi.c, lo);
@@ -85,9 +86,11 @@ template <int C> __device__ __forceinline__ Hit narrow_class(const Geo& lo, cons
     o.phi = r.plo;
     return o;
   } else if constexpr (C == PQ_LL) {
-    return line_line(lo, hi);
+    return line_line(lo, hi, cutoff);
+  } else if constexpr (C == PQ_BB) {
+    return poly_poly<4, 4>(lo, hi, cutoff);
   } else {
-    return poly_poly(lo, hi);
+    return lo.shape == BOX ? poly_poly<4, 2>(lo, hi, cutoff) : poly_poly<2, 4>(lo, hi, cutoff);
   }
 }
 
@@ -111,7 +114,7 @@ __device__ __forceinline__ bool queued_pair(const float4* cur, const float4* sta
   const float4 Sa = stat[qa], Sb = stat[qb];
   const Geo lo = staged_geo(cur[qa], Sa), hi = staged_geo(cur[qb], Sb);
   const float dmin = (Sa.z + Sb.z) + w.min_dist;
-  const Hit h = narrow_class<C>(lo, hi);
+  const Hit h = narrow_class<C>(lo, hi, contact_cutoff(lo, hi, dmin));
   if (!(h.d <= dmin)) return false;
   const float F = contact_mag(dmin, h.d, w);
   const V2 flo = V2{F * h.n.x, F * h.n.y};
