@@ -12,6 +12,11 @@ region; the state carries over from step to step.
 Prints one JSON line (rank 0): throughput in agent-steps/s, the roofline
 of the dominant kernel measured with HIP events on the launch stream, and
 the FP64 CPU oracle timed on the host cores on the same workload.
+
+--workload mixed4096 measures the mixed-shape workload instead: 4,096
+environments of 16 sphere agents (r = 0.03), 4 boxes (0.1 x 0.3) and 8
+segments (length 0.5), all movable and rotatable, two joints each, one
+200-step rollout per bench step; its roofline is the FP32 vector peak.
 """
 import argparse
 import hashlib
@@ -27,7 +32,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
-KERNEL_SRC = os.path.join(ROOT, "paper_2207_03530_amd", "csrc", "vmas_kernels.hip")
+# sources of the rollout kernels (the traffic summaries name their hash)
+KERNEL_SRC = [os.path.join(ROOT, "paper_2207_03530_amd", "csrc", f)
+              for f in ("vmas_kernels.hip", "vmas_geom.h", "vmas_internal.h")]
 PROFILES = os.path.join(ROOT, "profiles")
 
 # Algorithmic bytes of one environment-step / one entity of the spread
@@ -41,8 +48,19 @@ STATE_WRITE_PER_ACTIVE = 24
 STATIC_PER_ENTITY = 12
 
 
+# Model FLOP count of one environment-step of the mixed workload (FMA = 2,
+# transcendental = 1; every pair tested once): sphere-sphere 120 x 5,
+# sphere-segment 128 x 15, sphere-box 64 x 20, segment-segment 28 x 75,
+# segment-box 32 x 150, box-box 6 x 200 (11,900), integration 28 x 16 and
+# box/segment geometry 12 x 20.
+MIXED_FLOP_PER_ENV_STEP = 12600
+
+
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes(n_envs, agents, landmarks, T):
@@ -52,16 +70,19 @@ def algorithmic_bytes(n_envs, agents, landmarks, T):
             + A * STATE_WRITE_PER_ACTIVE + N * STATIC_PER_ENTITY)
 
 
-def kernel_of(schedule: str) -> str:
+def kernel_of(schedule: str, spheres_only: bool = True) -> str:
     """Device function that runs a rollout under the given schedule."""
+    if not spheres_only:
+        return "k_rollout"
     return "k_rollout_quad" if schedule.startswith("quad") else "k_rollout_sph"
 
 
-def traffic_per_launch(kernel: str):
+def traffic_per_launch(kernel: str, tag: str = "spread30k"):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary of `kernel`, if it was taken on the current kernel source; else None."""
+    summary of `kernel` on workload `tag`, if it was taken on the current
+    kernel source; else None."""
     try:
-        d = json.load(open(os.path.join(PROFILES, f"{kernel}_spread30k_traffic.json")))
+        d = json.load(open(os.path.join(PROFILES, f"{kernel}_{tag}_traffic.json")))
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_sha") != kernel_sha():
@@ -94,8 +115,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--envs", type=int, default=30000)
-    ap.add_argument("--T", type=int, default=100)
+    ap.add_argument("--workload", choices=("spread30000", "mixed4096"), default="spread30000")
+    ap.add_argument("--envs", type=int, default=None,
+                    help="environments (default 30000 spread, 4096 mixed)")
+    ap.add_argument("--T", type=int, default=None, help="rollout length (default 100 spread, 200 mixed)")
     ap.add_argument("--graph", action="store_true", help="replay a captured hipGraph")
     ap.add_argument("--schedule", default=None,
                     help="run this launch plan (vmas_schedule_name) instead of autotuning")
@@ -114,8 +137,9 @@ def main():
     import torch
     from paper_2207_03530_amd import binding, workloads as W
 
-    T = args.T
-    w = W.spread(args.envs)
+    mixed = args.workload == "mixed4096"
+    T = args.T or (200 if mixed else 100)
+    w = W.mixed(args.envs or 4096) if mixed else W.spread(args.envs or 30000)
     acts_np = w.actions(T)
     dev = torch.device("cuda", 0)
     batch = binding.vmas_create_batch(w, 0)
@@ -166,14 +190,47 @@ def main():
     agent_steps = w.n_agents_total * T
     value = agent_steps / (ms_per_step * 1e-3)
 
-    nbytes = algorithmic_bytes(w.n_envs, 4, 2, T)
-    if args.drawn_actions:
-        nbytes -= T * w.n_agents_total * ACTION_BYTES_PER_AGENT_STEP
-    achieved = nbytes / (kernel_ms * 1e-3) / 1e9
-    kernel = kernel_of(batch.schedule_name(plan))
-    traffic = traffic_per_launch(kernel) if not (args.drawn_actions or args.graph) else None
+    kernel = kernel_of(batch.schedule_name(plan), not mixed)
+    tag = "mixed4096" if mixed else "spread30k"
+    default_size = w.n_envs == (4096 if mixed else 30000) and T == (200 if mixed else 100)
+    traffic = (traffic_per_launch(kernel, tag)
+               if not (args.drawn_actions or args.graph) and default_size else None)
+    if mixed:
+        flop = MIXED_FLOP_PER_ENV_STEP * w.n_envs * T
+        achieved = flop / (kernel_ms * 1e-3) / 1e12
+        roofline = {
+            "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
+            "kernel": kernel, "kernel_ms": kernel_ms,
+            "algorithmic_flop_per_launch": flop,
+            "algorithmic_flop_per_env_step": MIXED_FLOP_PER_ENV_STEP,
+        }
+        workload = (f"mixed{w.n_envs}: {w.n_envs} envs x (16 sphere agents + 4 boxes + 8 segments, "
+                    f"2 joints), one {T}-step rollout per step, actions "
+                    + ("drawn in-kernel" if args.drawn_actions else "read from HBM"))
+        metric = f"agent-steps/s at {w.n_envs} envs x (16 spheres + 4 boxes + 8 segments)"
+        shape = {"n_envs": w.n_envs, "agents_per_env": 16, "boxes_per_env": 4,
+                 "segments_per_env": 8, "joints_per_env": 2}
+    else:
+        nbytes = algorithmic_bytes(w.n_envs, 4, 2, T)
+        if args.drawn_actions:
+            nbytes -= T * w.n_agents_total * ACTION_BYTES_PER_AGENT_STEP
+        achieved = nbytes / (kernel_ms * 1e-3) / 1e9
+        roofline = {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": kernel, "kernel_ms": kernel_ms,
+            "algorithmic_bytes_per_launch": nbytes,
+            "algorithmic_bytes_per_env_step": nbytes / (w.n_envs * T),
+        }
+        workload = (f"spread{w.n_envs}: {w.n_envs} envs x (4 sphere agents + 2 sphere "
+                    f"landmarks), one {T}-step rollout per step, actions "
+                    + ("drawn in-kernel" if args.drawn_actions else "read from HBM"))
+        metric = "agent-steps/s at 30k envs x 4 agents"
+        shape = {"n_envs": w.n_envs, "agents_per_env": 4, "landmarks_per_env": 2}
     out = {
-        "metric": "agent-steps/s at 30k envs x 4 agents",
+        "metric": metric,
         "value": value,
         "unit": "agent-steps/s",
         "n_gpus": 1,
@@ -186,21 +243,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"spread{w.n_envs}: {w.n_envs} envs x (4 sphere agents + 2 sphere "
-                        f"landmarks), one {T}-step rollout per step, actions "
-                        + ("drawn in-kernel" if args.drawn_actions else "read from HBM"),
-            "n_envs": w.n_envs, "agents_per_env": 4, "landmarks_per_env": 2, "rollout_T": T,
+            "workload": workload, **shape, "rollout_T": T,
             "dt": w.dt, "drag": w.drag, "schedule": batch.schedule_name(plan),
             "graph": bool(args.graph),
         },
-        "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel": kernel, "kernel_ms": kernel_ms,
-            "algorithmic_bytes_per_launch": nbytes,
-            "algorithmic_bytes_per_env_step": nbytes / (w.n_envs * T),
-        },
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, acts_np, T)

@@ -202,9 +202,10 @@ vmas_status vmas_rollout_backward(vmas_batch* batch, const float* state0, const 
  * every plan computes the same results bit for bit. vmas_autotune times each
  * plan on a T-step rollout of a scratch copy of `state` (state itself is not
  * modified) with the given actions (device float32 [T][A][2]; NULL: actions
- * drawn in the kernel, seed 12345), three timed repetitions after a warm-up,
- * and keeps the fastest; a later plan replaces the current choice only when
- * it is at least 3 % faster. Returns the plan id in *chosen (and makes it
+ * drawn in the kernel, seed 12345): about 20 ms of warm-up on the current
+ * plan, then three rounds over all plans with two timed runs each; a plan's
+ * time is its fastest run, and a later plan replaces the current choice
+ * only when it is at least 3 % faster. Returns the plan id in *chosen (and makes it
  * current). It synchronises the stream; it allocates one state-sized scratch
  * buffer for the duration of the call. */
 vmas_status vmas_set_schedule(vmas_batch* batch, int32_t schedule);

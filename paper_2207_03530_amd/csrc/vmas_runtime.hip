@@ -892,33 +892,47 @@ vmas_status vmas_autotune(vmas_batch* b, const float* state, const float* action
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   const int prev = b->cur;
-  int best = -1;
-  float best_ms = 0;
+  const int nplans = (int)b->plans.size();
+  std::vector<float> ms_min(nplans, INFINITY);
   vmas_status st = VMAS_OK;
-  for (int q = 0; q < (int)b->plans.size() && st == VMAS_OK; ++q) {
-    if (!b->plans[q].valid) continue;
+  auto trial = [&](int q, float* ms_out) {
     b->cur = q;
-    float ms_min = 0;
-    for (int rep = 0; rep < 4 && st == VMAS_OK; ++rep) {
-      if (hipMemcpyAsync(scratch, state, n * sizeof(float), hipMemcpyDeviceToDevice, s) !=
-          hipSuccess) {
-        st = fail(VMAS_ERR_DEVICE, "autotune copy failed");
-        break;
+    if (hipMemcpyAsync(scratch, state, n * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return fail(VMAS_ERR_DEVICE, "autotune copy failed");
+    (void)hipEventRecord(e0, s);
+    vmas_status r = vmas_rollout(b, scratch, actions, 12345u, 0, T, nullptr, nullptr, stream);
+    (void)hipEventRecord(e1, s);
+    if (r != VMAS_OK) return r;
+    if (hipEventSynchronize(e1) != hipSuccess) return fail(VMAS_ERR_DEVICE, "autotune sync failed");
+    (void)hipEventElapsedTime(ms_out, e0, e1);
+    return VMAS_OK;
+  };
+  // Warm-up (clocks and code objects settle): about 20 ms of the first plan.
+  {
+    float ms = 0, spent = 0;
+    for (int rep = 0; rep < 200 && spent < 20.0f && st == VMAS_OK; ++rep) {
+      st = trial(prev, &ms);
+      spent += ms;
+    }
+  }
+  // Three rounds over all plans, two timed runs each: the fastest run of a
+  // plan over the rounds is its time.
+  for (int round = 0; round < 3 && st == VMAS_OK; ++round) {
+    for (int q = 0; q < nplans && st == VMAS_OK; ++q) {
+      if (!b->plans[q].valid) continue;
+      for (int rep = 0; rep < 2 && st == VMAS_OK; ++rep) {
+        float ms = 0;
+        st = trial(q, &ms);
+        if (st == VMAS_OK && ms < ms_min[q]) ms_min[q] = ms;
       }
-      (void)hipEventRecord(e0, s);
-      st = vmas_rollout(b, scratch, actions, 12345u, 0, T, nullptr, nullptr, stream);
-      (void)hipEventRecord(e1, s);
-      if (hipEventSynchronize(e1) != hipSuccess) st = fail(VMAS_ERR_DEVICE, "autotune sync failed");
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (rep > 0 && (rep == 1 || ms < ms_min)) ms_min = ms;  // first repetition warms up
     }
-    // a later schedule must be clearly faster (3 %) to replace the current
-    // choice, which keeps the choice stable where schedules are within noise
-    if (st == VMAS_OK && (best < 0 || ms_min < 0.97f * best_ms)) {
-      best = q;
-      best_ms = ms_min;
-    }
+  }
+  // a later schedule must be clearly faster (3 %) to replace the current
+  // choice, which keeps the choice stable where schedules are within noise
+  int best = -1;
+  for (int q = 0; q < nplans && st == VMAS_OK; ++q) {
+    if (!b->plans[q].valid) continue;
+    if (best < 0 || ms_min[q] < 0.97f * ms_min[best]) best = q;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
