@@ -434,9 +434,14 @@ def test_uneven_batch_parity():
     _free_run_check(w, ow, gtraj, gmasks, acts, "uneven96 T=40", min_full=0.5, min_steps=10)
 
 
-def test_trajectory_output():
-    w = W.mixed(8, seed=2)
-    T = 6
+@pytest.mark.parametrize("kind", ["mixed", "spread", "uneven"])
+def test_trajectory_output(kind):
+    """The trajectory of one rollout (kernels with outputs) equals T single
+    steps (kernels without outputs) bit for bit."""
+    w = {"mixed": lambda: W.mixed(8, seed=2),
+         "spread": lambda: W.spread(64, radius=0.2, seed=2),
+         "uneven": lambda: W.uneven(100, lo=2, hi=8, radius=0.2, seed=2)}[kind]()
+    T = 6 if kind == "mixed" else 25
     acts = _dev(w.actions(T))
     b = _batch(w)
     tr = torch.zeros((T + 1) * 6 * w.n_entities, device="cuda:0")
