@@ -93,6 +93,16 @@ template <class S> __device__ __forceinline__ V2T<S> vrot_t(S cs, S sn, V2T<S> v
   return {s_fma(cs, v.x, sn * v.y), s_fma(-sn, v.x, cs * v.y)};
 }
 
+// Value selects (component by component): a conditional between two
+// aggregates would otherwise choose an address and keep both in scratch.
+__device__ __forceinline__ float ssel(bool c, float a, float b) { return c ? a : b; }
+__device__ __forceinline__ D3 ssel(bool c, D3 a, D3 b) {
+  return D3(c ? a.v : b.v, c ? a.a : b.a, c ? a.b : b.b, c ? a.c : b.c);
+}
+template <class S> __device__ __forceinline__ V2T<S> vsel(bool c, V2T<S> a, V2T<S> b) {
+  return {ssel(c, a.x, b.x), ssel(c, a.y, b.y)};
+}
+
 // Geometry of one entity for the narrow phase: pose and (constant) size.
 template <class S> struct GeoT {
   V2T<S> c;
@@ -175,18 +185,18 @@ __device__ __forceinline__ void consider(ClosestT<S>& b, V2T<S> e, V2T<S> p0, V2
   const V2T<S> qi = {s_fma(u.x, st, p0.x), s_fma(u.y, st, p0.y)};
   // foot at an end of the edge
   const V2T<S> p1 = {s_fma(u.x, S(len), p0.x), s_fma(u.y, S(len), p0.y)};
-  const V2T<S> qe = val(st) <= 0.0f ? V2T<S>{p0.x, p0.y} : p1;
+  const V2T<S> qe = vsel(val(st) <= 0.0f, p0, p1);
   const V2T<S> we = vsub(e, qe);
-  const S d2 = inner ? sn * sn : vdot(we, we);
+  const S d2 = ssel(inner, sn * sn, vdot(we, we));
   // one update of every field (values, no field chosen by address), so the
   // running minimum stays in registers
   if (val(d2) < b.d2v) {
     b.d2v = val(d2);
     b.d2 = d2;
-    b.d = inner ? s_abs(sn) : S(-1.0f);
+    b.d = ssel(inner, s_abs(sn), S(-1.0f));
     b.e = e;
-    b.q = inner ? qi : qe;
-    b.dir = val(sn) >= 0.0f ? V2T<S>{-u.y, u.x} : V2T<S>{u.y, -u.x};
+    b.q = vsel(inner, qi, qe);
+    b.dir = vsel(val(sn) >= 0.0f, V2T<S>{-u.y, u.x}, V2T<S>{u.y, -u.x});
     b.exact = inner;
     b.of_lo = of_lo;
   }
@@ -203,17 +213,16 @@ __device__ __forceinline__ HitT<S> finish_closest(const ClosestT<S>& b, V2T<S> f
     dir = b.dir;
   } else {
     h.d = s_sqrt(b.d2);
-    dir = val(h.d) == 0.0f ? (b.of_lo ? fb_lo : vneg(fb_hi)) : vscl(vsub(b.e, b.q), S(1.0f) / h.d);
+    if (val(h.d) == 0.0f)
+      dir = vsel(b.of_lo, fb_lo, vneg(fb_hi));
+    else
+      dir = vscl(vsub(b.e, b.q), S(1.0f) / h.d);
   }
-  if (b.of_lo) {  // vertex of lo, foot on hi: lo pushed from the foot to the vertex
-    h.n = dir;
-    h.plo = b.e;
-    h.phi = b.q;
-  } else {        // vertex of hi, foot on lo: lo pushed the other way
-    h.n = vneg(dir);
-    h.plo = b.q;
-    h.phi = b.e;
-  }
+  // vertex of lo, foot on hi: lo pushed from the foot to the vertex;
+  // vertex of hi, foot on lo: lo pushed the other way
+  h.n = vsel(b.of_lo, dir, vneg(dir));
+  h.plo = vsel(b.of_lo, b.e, b.q);
+  h.phi = vsel(b.of_lo, b.q, b.e);
   return h;
 }
 
@@ -431,39 +440,30 @@ __device__ HitT<S> poly_poly(const GeoT<S>& I, const GeoT<S>& J, float cutoff) {
   V2T<S> s = A.ax[0];
 #pragma unroll
   for (int k = 1; k < NAX; ++k) {
-    const V2T<S> sk = pair_axis<NA, NB>(A, B, k);
-    const bool w = k == best_k;
-    s.x = w ? sk.x : s.x;
-    s.y = w ? sk.y : s.y;
+    s = vsel(k == best_k, pair_axis<NA, NB>(A, B, k), s);
   }
   // overlap along the winning axis with derivatives
   h.d = best_plus ? -(proj_max<NB>(B, s) - proj_min<NA>(A, s))
                   : -(proj_max<NA>(A, s) - proj_min<NB>(B, s));
-  h.n = best_plus ? s : vneg(s);
-  V2T<S> p;
-  if (best_k >= PA::na) {  // axis of hi: deepest vertex of lo
-    p = A.v[0];
-    float m = val(vdot(h.n, p));
+  h.n = vsel(best_plus, s, vneg(s));
+  // axis of hi: deepest vertex of lo; axis of lo: deepest vertex of hi
+  V2T<S> pa = A.v[0], pb = B.v[0];
+  float ma = val(vdot(h.n, pa)), mb = val(vdot(h.n, pb));
 #pragma unroll
-    for (int q = 1; q < PA::nv; ++q) {
-      const float t = val(vdot(h.n, A.v[q]));
-      if (t < m) {
-        m = t;
-        p = A.v[q];
-      }
-    }
-  } else {               // axis of lo: deepest vertex of hi
-    p = B.v[0];
-    float m = val(vdot(h.n, p));
-#pragma unroll
-    for (int q = 1; q < PB::nv; ++q) {
-      const float t = val(vdot(h.n, B.v[q]));
-      if (t > m) {
-        m = t;
-        p = B.v[q];
-      }
-    }
+  for (int q = 1; q < PA::nv; ++q) {
+    const float t = val(vdot(h.n, A.v[q]));
+    const bool lt = t < ma;
+    ma = lt ? t : ma;
+    pa = vsel(lt, A.v[q], pa);
   }
+#pragma unroll
+  for (int q = 1; q < PB::nv; ++q) {
+    const float t = val(vdot(h.n, B.v[q]));
+    const bool gt = t > mb;
+    mb = gt ? t : mb;
+    pb = vsel(gt, B.v[q], pb);
+  }
+  const V2T<S> p = vsel(best_k >= PA::na, pa, pb);
   h.plo = p;
   h.phi = p;
   return h;
@@ -619,9 +619,9 @@ template <class S>
 __device__ __forceinline__ bool joint_eval(V2T<S> xs, S cs, S sn, V2T<S> xo, S co, S so, bool is_a,
                                            const JointK& J, float k, V2T<S>* f_self, S* tq_self,
                                            S* tq_other) {
-  const V2T<S> xa = is_a ? xs : xo, xb = is_a ? xo : xs;
-  const S ca = is_a ? cs : co, sa = is_a ? sn : so;
-  const S cb = is_a ? co : cs, sb = is_a ? so : sn;
+  const V2T<S> xa = vsel(is_a, xs, xo), xb = vsel(is_a, xo, xs);
+  const S ca = ssel(is_a, cs, co), sa = ssel(is_a, sn, so);
+  const S cb = ssel(is_a, co, cs), sb = ssel(is_a, so, sn);
   const V2T<S> Pa = vadd(xa, vrot(ca, sa, V2T<S>{S(J.ax), S(J.ay)}));
   const V2T<S> Pb = vadd(xb, vrot(cb, sb, V2T<S>{S(J.bx), S(J.by)}));
   const V2T<S> dl = vsub(Pa, Pb);
@@ -629,9 +629,9 @@ __device__ __forceinline__ bool joint_eval(V2T<S> xs, S cs, S sn, V2T<S> xo, S c
   if (val(len) == 0.0f) return false;
   const S mag = S(-k) * (len - S(J.rest)) / len;
   const V2T<S> fa = vscl(dl, mag);
-  const V2T<S> fs = is_a ? fa : vneg(fa);
-  const V2T<S> arm_s = is_a ? vsub(Pa, xa) : vsub(Pb, xb);
-  const V2T<S> arm_o = is_a ? vsub(Pb, xb) : vsub(Pa, xa);
+  const V2T<S> fs = vsel(is_a, fa, vneg(fa));
+  const V2T<S> arm_s = vsel(is_a, vsub(Pa, xa), vsub(Pb, xb));
+  const V2T<S> arm_o = vsel(is_a, vsub(Pb, xb), vsub(Pa, xa));
   *f_self = fs;
   *tq_self = vcross(arm_s, fs);
   *tq_other = vcross(arm_o, vneg(fs));
@@ -658,13 +658,27 @@ __device__ __forceinline__ void pair_grad(const GeoT<D3>& self, float rho_s, boo
     *tq_other = D3(0.0f);
     return;
   }
-  const HitT<D3> h = self_lo ? narrow(self, other) : narrow(other, self);
+  // the pair in canonical order, chosen by value (one narrow-phase call)
+  GeoT<D3> lo, hi;
+  lo.c = vsel(self_lo, self.c, other.c);
+  lo.cs = ssel(self_lo, self.cs, other.cs);
+  lo.sn = ssel(self_lo, self.sn, other.sn);
+  lo.d0 = self_lo ? self.d0 : other.d0;
+  lo.d1 = self_lo ? self.d1 : other.d1;
+  lo.shape = self_lo ? self.shape : other.shape;
+  hi.c = vsel(self_lo, other.c, self.c);
+  hi.cs = ssel(self_lo, other.cs, self.cs);
+  hi.sn = ssel(self_lo, other.sn, self.sn);
+  hi.d0 = self_lo ? other.d0 : self.d0;
+  hi.d1 = self_lo ? other.d1 : self.d1;
+  hi.shape = self_lo ? other.shape : self.shape;
+  const HitT<D3> h = narrow(lo, hi);
   const D3 F = contact_mag(D3(dmin), h.d, w);
   const V2T<D3> flo = vscl(h.n, F);
-  const V2T<D3> fs = self_lo ? flo : vneg(flo);
+  const V2T<D3> fs = vsel(self_lo, flo, vneg(flo));
   *f_self = fs;
-  *tq_self = vcross(vsub(self_lo ? h.plo : h.phi, self.c), fs);
-  *tq_other = vcross(vsub(self_lo ? h.phi : h.plo, other.c), vneg(fs));
+  *tq_self = vcross(vsub(vsel(self_lo, h.plo, h.phi), self.c), fs);
+  *tq_other = vcross(vsub(vsel(self_lo, h.phi, h.plo), other.c), vneg(fs));
 }
 
 }  // namespace vmas
