@@ -188,7 +188,9 @@ vmas_status vmas_step_backward(vmas_batch* batch, const float* state_t, const fl
 /* Reverse-mode derivative of a T-step rollout with checkpointing: the
  * forward pass is replayed from checkpoints stored every `ckpt_every` steps
  * (workspace owned by the handle, ceil(T / ckpt_every) + ckpt_every + 1 states),
- * so memory is O(T / k + k) states instead of O(T).
+ * so memory is O(T / k + k) states instead of O(T); the reverse steps of a
+ * segment run in one launch, each computing what vmas_step_backward computes
+ * (the same bits).
  *   state0        device float32 [6][N]: initial state
  *   actions       device float32 [T][A][2]
  *   grad_state_T  device float32 [6][N]: dL/d state_T

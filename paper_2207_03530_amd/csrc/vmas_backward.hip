@@ -16,6 +16,11 @@
 // Contact decisions and closest-feature branches are those of the forward
 // step (same FP32 values), i.e. the derivative of the piecewise-smooth map
 // on the piece the forward pass is on.
+//
+// One launch runs T reverse steps (t = T-1 .. 0) of a segment whose states
+// and actions are stored one step after the other: every entity has a lane,
+// which carries its entity's gradient from step to step in registers; T = 1
+// is the single-step adjoint.
 
 #include "vmas_geom.h"
 #include "vmas_internal.h"
@@ -23,7 +28,8 @@
 namespace vmas {
 namespace {
 
-template <int MAXB>
+// SPH: sphere-only batch (only the sphere pair code is compiled in).
+template <int MAXB, bool SPH>
 __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
   extern __shared__ float4 lds[];
   const int E = a.max_stage;
@@ -34,27 +40,16 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
   const int N = a.w.N;
   const int s0 = a.stage_off[g], ns = a.stage_off[g + 1] - s0;
   for (int s = l; s < ns; s += B) {
-    const int e = a.stage[s0 + s];
-    float cs, sn;
-    sincosf(a.state[4 * N + e], &sn, &cs);
-    pose[s] = make_float4(a.state[e], a.state[N + e], cs, sn);
-    const EntParam p = a.ent[e];
+    const EntParam p = a.ent[a.stage[s0 + s]];
     stat[s] = make_float4(p.d0, p.d1, p.rho, __int_as_float(p.sf));
   }
   const LaneRec r = a.lanes[(size_t)g * B + l];
   const bool act = r.ent >= 0;
   const WorldK w = a.w;
-  // omega itself is not needed: its step is linear (damping and torque)
-  float x = 0, y = 0, vx = 0, vy = 0, th = 0;
   EntParam p{};
   float gx = 0, gy = 0, gvx = 0, gvy = 0, gth = 0, gom = 0;
   if (act) {
     const int e = r.ent;
-    x = a.state[e];
-    y = a.state[N + e];
-    vx = a.state[2 * N + e];
-    vy = a.state[3 * N + e];
-    th = a.state[4 * N + e];
     p = a.ent[e];
     gx = a.gnext[e];
     gy = a.gnext[N + e];
@@ -68,156 +63,194 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
   const bool collide = act && (fl & COLLIDABLE);
   const bool agent = act && r.agent >= 0;
   const int myloc = r.slot - r.lo;
-  float cs = 1.0f, sn = 0.0f;
-  if (act) sincosf(th, &sn, &cs);
-  __syncthreads();
+  for (int t = a.T - 1; t >= 0; --t) {
+    const float* state = a.state + (size_t)t * 6 * N;
+    const float* actions = a.actions ? a.actions + (size_t)t * 2 * w.A : nullptr;
+    float* gact = a.gact ? a.gact + (size_t)t * 2 * w.A : nullptr;
+    __syncthreads();  // the previous step's readers of pose and adj are done
+    for (int s = l; s < ns; s += B) {
+      const int e = a.stage[s0 + s];
+      float cs, sn;
+      sincosf(state[4 * N + e], &sn, &cs);
+      pose[s] = make_float4(state[e], state[N + e], cs, sn);
+    }
+    // omega itself is not needed: its step is linear (damping and torque)
+    float x = 0, y = 0, vx = 0, vy = 0, th = 0;
+    if (act) {
+      const int e = r.ent;
+      x = state[e];
+      y = state[N + e];
+      vx = state[2 * N + e];
+      vy = state[3 * N + e];
+      th = state[4 * N + e];
+    }
+    float cs = 1.0f, sn = 0.0f;
+    if (act) sincosf(th, &sn, &cs);
+    __syncthreads();
 
-  // 1. Reverse of the integration.
-  float Fbx = 0.0f, Fby = 0.0f, Tb = 0.0f;
-  float ox = gx, oy = gy, ovx = gvx, ovy = gvy, oth = gth, oom = gom;
-  if (movable) {
-    // v' = clamp(v^), x' = x + v' dt
-    const float vtx = fmaf(gx, w.dt, gvx), vty = fmaf(gy, w.dt, gvy);
-    float hx = vtx, hy = vty;  // adjoint of v^
-    if (p.vmax > 0.0f) {
-      // forward force, exactly as the step computed it (for the clamp)
-      const float2 an = agent ? *reinterpret_cast<const float2*>(a.actions + 2 * (size_t)r.agent)
-                              : make_float2(0.0f, 0.0f);
-      float fx = an.x + p.mgx, fy = an.y + p.mgy, tq = 0.0f;
+    // 1. Reverse of the integration.
+    float Fbx = 0.0f, Fby = 0.0f, Tb = 0.0f;
+    float ox = gx, oy = gy, ovx = gvx, ovy = gvy, oth = gth, oom = gom;
+    if (movable) {
+      // v' = clamp(v^), x' = x + v' dt
+      const float vtx = fmaf(gx, w.dt, gvx), vty = fmaf(gy, w.dt, gvy);
+      float hx = vtx, hy = vty;  // adjoint of v^
+      if (p.vmax > 0.0f) {
+        // forward force, exactly as the step computed it (for the clamp)
+        const float2 an = agent ? *reinterpret_cast<const float2*>(actions + 2 * (size_t)r.agent)
+                                : make_float2(0.0f, 0.0f);
+        float fx = an.x + p.mgx, fy = an.y + p.mgy, tq = 0.0f;
+        if (collide) {
+          GeoT<float> self;
+          self.c = V2T<float>{x, y};
+          self.cs = cs;
+          self.sn = sn;
+          self.d0 = p.d0;
+          self.d1 = p.d1;
+          self.shape = shape;
+          for (int q = r.lo; q < r.hi; ++q) {
+            if (q == r.slot) continue;
+            const float4 S = stat[q];
+            const int of = (__float_as_int(S.w) >> 8) & 0xff;
+            if (!(of & COLLIDABLE)) continue;
+            if (p.excl != -1 && excluded(p.excl, q - r.lo)) continue;
+            pair_force<SPH>(self, p.rho, myloc, pose[q], S, q - r.lo, w, fx, fy, tq);
+          }
+        }
+        for (int jj = a.joff[r.ent]; jj < a.joff[r.ent + 1]; ++jj) {
+          const JointK J = a.joints[a.jlist[jj]];
+          const bool is_a = J.a == r.ent;
+          const float4 P = pose[r.lo + ((is_a ? J.b : J.a) - r.first)];
+          V2T<float> f;
+          float ts, to;
+          if (joint_eval<float>(V2T<float>{x, y}, cs, sn, V2T<float>{P.x, P.y}, P.z, P.w, is_a, J,
+                                w.joint_k, &f, &ts, &to)) {
+            fx += f.x;
+            fy += f.y;
+          }
+        }
+        const float ux = fmaf(fx * p.inv_m, w.dt, w.damp * vx);
+        const float uy = fmaf(fy * p.inv_m, w.dt, w.damp * vy);
+        const float sp = sqrtf(fmaf(ux, ux, uy * uy));
+        if (sp > p.vmax) {
+          // v' = v^ vmax / |v^|: Jacobian (vmax/|v^|) (I - n n^T), symmetric
+          const float k = p.vmax / sp, nx = ux / sp, ny = uy / sp;
+          const float dot = nx * vtx + ny * vty;
+          hx = k * (vtx - nx * dot);
+          hy = k * (vty - ny * dot);
+        }
+      }
+      ovx = w.damp * hx;
+      ovy = w.damp * hy;
+      Fbx = hx * p.inv_m * w.dt;
+      Fby = hy * p.inv_m * w.dt;
+    }
+    if (rotatable) {
+      const float wt = fmaf(gth, w.dt, gom);
+      oom = w.damp * wt;
+      Tb = wt * p.inv_I * w.dt;
+    }
+    if (act) adj[r.slot] = make_float4(Fbx, Fby, Tb, 0.0f);
+    __syncthreads();
+
+    // 2. Pose adjoint through the contacts and joints of the entity.
+    if (act) {
+      GeoT<D3> self;
+      self.c = V2T<D3>{D3(x, 1.0f, 0.0f, 0.0f), D3(y, 0.0f, 1.0f, 0.0f)};
+      self.cs = D3(cs, 0.0f, 0.0f, -sn);
+      self.sn = D3(sn, 0.0f, 0.0f, cs);
+      self.d0 = p.d0;
+      self.d1 = p.d1;
+      self.shape = shape;
+      const bool self_dof = (fl & (MOVABLE | ROTATABLE)) != 0;
+      auto contract = [&](const V2T<D3>& f, D3 ts, D3 to, float4 A_self, float4 A_other) {
+        const float ax = A_self.x - A_other.x, ay = A_self.y - A_other.y;
+        ox += f.x.a * ax + f.y.a * ay + ts.a * A_self.z + to.a * A_other.z;
+        oy += f.x.b * ax + f.y.b * ay + ts.b * A_self.z + to.b * A_other.z;
+        oth += f.x.c * ax + f.y.c * ay + ts.c * A_self.z + to.c * A_other.z;
+      };
+      const float4 A_self = adj[r.slot];
       if (collide) {
-        GeoT<float> self;
-        self.c = V2T<float>{x, y};
-        self.cs = cs;
-        self.sn = sn;
-        self.d0 = p.d0;
-        self.d1 = p.d1;
-        self.shape = shape;
+        GeoT<float> selff;
+        selff.c = V2T<float>{x, y};
+        selff.cs = cs;
+        selff.sn = sn;
+        selff.d0 = p.d0;
+        selff.d1 = p.d1;
+        selff.shape = shape;
         for (int q = r.lo; q < r.hi; ++q) {
           if (q == r.slot) continue;
           const float4 S = stat[q];
           const int of = (__float_as_int(S.w) >> 8) & 0xff;
           if (!(of & COLLIDABLE)) continue;
+          if (!self_dof && !(of & (MOVABLE | ROTATABLE))) continue;
           if (p.excl != -1 && excluded(p.excl, q - r.lo)) continue;
-          pair_force<false>(self, p.rho, myloc, pose[q], S, q - r.lo, w, fx, fy, tq);
+          const float4 P = pose[q];
+          float fx = 0.0f, fy = 0.0f, tq = 0.0f;
+          if (!pair_force<SPH>(selff, p.rho, myloc, P, S, q - r.lo, w, fx, fy, tq)) continue;
+          GeoT<D3> other;
+          other.c = V2T<D3>{D3(P.x), D3(P.y)};
+          other.cs = D3(P.z);
+          other.sn = D3(P.w);
+          other.d0 = S.x;
+          other.d1 = S.y;
+          other.shape = __float_as_int(S.w) & 0xff;
+          V2T<D3> f;
+          D3 ts, to;
+          pair_grad<SPH>(self, p.rho, myloc < q - r.lo, other, S.z, w, &f, &ts, &to);
+          contract(f, ts, to, A_self, adj[q]);
         }
       }
       for (int jj = a.joff[r.ent]; jj < a.joff[r.ent + 1]; ++jj) {
         const JointK J = a.joints[a.jlist[jj]];
         const bool is_a = J.a == r.ent;
-        const float4 P = pose[r.lo + ((is_a ? J.b : J.a) - r.first)];
-        V2T<float> f;
-        float ts, to;
-        if (joint_eval<float>(V2T<float>{x, y}, cs, sn, V2T<float>{P.x, P.y}, P.z, P.w, is_a, J,
-                              w.joint_k, &f, &ts, &to)) {
-          fx += f.x;
-          fy += f.y;
-        }
-      }
-      const float ux = fmaf(fx * p.inv_m, w.dt, w.damp * vx);
-      const float uy = fmaf(fy * p.inv_m, w.dt, w.damp * vy);
-      const float sp = sqrtf(fmaf(ux, ux, uy * uy));
-      if (sp > p.vmax) {
-        // v' = v^ vmax / |v^|: Jacobian (vmax/|v^|) (I - n n^T), symmetric
-        const float k = p.vmax / sp, nx = ux / sp, ny = uy / sp;
-        const float dot = nx * vtx + ny * vty;
-        hx = k * (vtx - nx * dot);
-        hy = k * (vty - ny * dot);
-      }
-    }
-    ovx = w.damp * hx;
-    ovy = w.damp * hy;
-    Fbx = hx * p.inv_m * w.dt;
-    Fby = hy * p.inv_m * w.dt;
-  }
-  if (rotatable) {
-    const float wt = fmaf(gth, w.dt, gom);
-    oom = w.damp * wt;
-    Tb = wt * p.inv_I * w.dt;
-  }
-  if (act) adj[r.slot] = make_float4(Fbx, Fby, Tb, 0.0f);
-  __syncthreads();
-
-  // 2. Pose adjoint through the contacts and joints of the entity.
-  if (act) {
-    GeoT<D3> self;
-    self.c = V2T<D3>{D3(x, 1.0f, 0.0f, 0.0f), D3(y, 0.0f, 1.0f, 0.0f)};
-    self.cs = D3(cs, 0.0f, 0.0f, -sn);
-    self.sn = D3(sn, 0.0f, 0.0f, cs);
-    self.d0 = p.d0;
-    self.d1 = p.d1;
-    self.shape = shape;
-    const bool self_dof = (fl & (MOVABLE | ROTATABLE)) != 0;
-    auto contract = [&](const V2T<D3>& f, D3 ts, D3 to, float4 A_self, float4 A_other) {
-      const float ax = A_self.x - A_other.x, ay = A_self.y - A_other.y;
-      ox += f.x.a * ax + f.y.a * ay + ts.a * A_self.z + to.a * A_other.z;
-      oy += f.x.b * ax + f.y.b * ay + ts.b * A_self.z + to.b * A_other.z;
-      oth += f.x.c * ax + f.y.c * ay + ts.c * A_self.z + to.c * A_other.z;
-    };
-    const float4 A_self = adj[r.slot];
-    if (collide) {
-      GeoT<float> selff;
-      selff.c = V2T<float>{x, y};
-      selff.cs = cs;
-      selff.sn = sn;
-      selff.d0 = p.d0;
-      selff.d1 = p.d1;
-      selff.shape = shape;
-      for (int q = r.lo; q < r.hi; ++q) {
-        if (q == r.slot) continue;
-        const float4 S = stat[q];
-        const int of = (__float_as_int(S.w) >> 8) & 0xff;
-        if (!(of & COLLIDABLE)) continue;
-        if (!self_dof && !(of & (MOVABLE | ROTATABLE))) continue;
-        if (p.excl != -1 && excluded(p.excl, q - r.lo)) continue;
+        const int q = r.lo + ((is_a ? J.b : J.a) - r.first);
         const float4 P = pose[q];
-        float fx = 0.0f, fy = 0.0f, tq = 0.0f;
-        if (!pair_force<false>(selff, p.rho, myloc, P, S, q - r.lo, w, fx, fy, tq)) continue;
-        GeoT<D3> other;
-        other.c = V2T<D3>{D3(P.x), D3(P.y)};
-        other.cs = D3(P.z);
-        other.sn = D3(P.w);
-        other.d0 = S.x;
-        other.d1 = S.y;
-        other.shape = __float_as_int(S.w) & 0xff;
         V2T<D3> f;
         D3 ts, to;
-        pair_grad(self, p.rho, myloc < q - r.lo, other, S.z, w, &f, &ts, &to);
-        contract(f, ts, to, A_self, adj[q]);
+        if (joint_eval<D3>(self.c, self.cs, self.sn, V2T<D3>{D3(P.x), D3(P.y)}, D3(P.z), D3(P.w),
+                           is_a, J, w.joint_k, &f, &ts, &to))
+          contract(f, ts, to, A_self, adj[q]);
+      }
+      if (agent && gact) {
+        gact[2 * (size_t)r.agent] = Fbx;
+        gact[2 * (size_t)r.agent + 1] = Fby;
       }
     }
-    for (int jj = a.joff[r.ent]; jj < a.joff[r.ent + 1]; ++jj) {
-      const JointK J = a.joints[a.jlist[jj]];
-      const bool is_a = J.a == r.ent;
-      const int q = r.lo + ((is_a ? J.b : J.a) - r.first);
-      const float4 P = pose[q];
-      V2T<D3> f;
-      D3 ts, to;
-      if (joint_eval<D3>(self.c, self.cs, self.sn, V2T<D3>{D3(P.x), D3(P.y)}, D3(P.z), D3(P.w),
-                         is_a, J, w.joint_k, &f, &ts, &to))
-        contract(f, ts, to, A_self, adj[q]);
-    }
+    gx = ox;
+    gy = oy;
+    gvx = ovx;
+    gvy = ovy;
+    gth = oth;
+    gom = oom;
+  }
+  if (act) {
     const int e = r.ent;
-    a.gstate[e] = ox;
-    a.gstate[N + e] = oy;
-    a.gstate[2 * N + e] = ovx;
-    a.gstate[3 * N + e] = ovy;
-    a.gstate[4 * N + e] = oth;
-    a.gstate[5 * N + e] = oom;
-    if (agent && a.gact) {
-      a.gact[2 * (size_t)r.agent] = Fbx;
-      a.gact[2 * (size_t)r.agent + 1] = Fby;
-    }
+    a.gstate[e] = gx;
+    a.gstate[N + e] = gy;
+    a.gstate[2 * N + e] = gvx;
+    a.gstate[3 * N + e] = gvy;
+    a.gstate[4 * N + e] = gth;
+    a.gstate[5 * N + e] = gom;
   }
 }
 
 }  // namespace
 
-hipError_t launch_backward(const BackArgs& a, int groups, int block, hipStream_t s) {
+hipError_t launch_backward(const BackArgs& a, int groups, int block, bool spheres_only,
+                           hipStream_t s) {
   const size_t shm = (size_t)a.max_stage * 3 * sizeof(float4);
-  if (block <= 256)
-    hipLaunchKernelGGL((k_step_backward<256>), dim3(groups), dim3(block), shm, s, a);
-  else
-    hipLaunchKernelGGL((k_step_backward<1024>), dim3(groups), dim3(block), shm, s, a);
+  if (block <= 256) {
+    if (spheres_only)
+      hipLaunchKernelGGL((k_step_backward<256, true>), dim3(groups), dim3(block), shm, s, a);
+    else
+      hipLaunchKernelGGL((k_step_backward<256, false>), dim3(groups), dim3(block), shm, s, a);
+  } else {
+    if (spheres_only)
+      hipLaunchKernelGGL((k_step_backward<1024, true>), dim3(groups), dim3(block), shm, s, a);
+    else
+      hipLaunchKernelGGL((k_step_backward<1024, false>), dim3(groups), dim3(block), shm, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -642,11 +642,13 @@ __device__ __forceinline__ bool joint_eval(V2T<S> xs, S cs, S sn, V2T<S> xo, S c
 // known to be in contact (decided by pair_force's FP32 rule); self carries
 // the dual seeds. Outputs the force on self and both torques, with their
 // derivatives with respect to self's (x, y, theta).
+// SPH: both entities are spheres (sphere-only batches).
+template <bool SPH = false>
 __device__ __forceinline__ void pair_grad(const GeoT<D3>& self, float rho_s, bool self_lo,
                                           const GeoT<D3>& other, float rho_o, const WorldK& w,
                                           V2T<D3>* f_self, D3* tq_self, D3* tq_other) {
   const float dmin = (rho_s + rho_o) + w.min_dist;
-  if (self.shape == SPHERE && other.shape == SPHERE) {
+  if (SPH || (self.shape == SPHERE && other.shape == SPHERE)) {
     const D3 dx = self.c.x - other.c.x, dy = self.c.y - other.c.y;
     const D3 sq = s_fma(dx, dx, dy * dy);
     V2T<D3> n;

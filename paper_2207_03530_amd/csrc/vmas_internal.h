@@ -117,11 +117,11 @@ __device__ __forceinline__ void lds_barrier() {
 
 // Arguments of the adjoint kernel (one step backwards).
 struct BackArgs {
-  const float* state;      // [6][N] state at t
-  const float* actions;    // [A][2] actions at t
-  const float* gnext;      // [6][N] dL/ds_{t+1}
-  float* gstate;           // [6][N] dL/ds_t
-  float* gact;             // [A][2] or NULL
+  const float* state;      // [T][6][N] states t0 .. t0 + T - 1
+  const float* actions;    // [T][A][2] actions of the same steps
+  const float* gnext;      // [6][N] dL/ds_{t0+T}
+  float* gstate;           // [6][N] dL/ds_t0
+  float* gact;             // [T][A][2] or NULL
   const EntParam* ent;
   const LaneRec* lanes;
   const int32_t* stage_off;
@@ -130,14 +130,15 @@ struct BackArgs {
   const int32_t* jlist;
   const JointK* joints;
   int32_t max_stage;
-  int32_t pad;
+  int32_t T;               // reverse steps of the launch (>= 1)
   WorldK w;
 };
 
 // Host-side launchers (vmas_kernels.hip).
 hipError_t launch_rollout(const StepArgs& a, int groups, int block, bool spheres_only,
                           hipStream_t s);
-hipError_t launch_backward(const BackArgs& a, int groups, int block, hipStream_t s);
+hipError_t launch_backward(const BackArgs& a, int groups, int block, bool spheres_only,
+                           hipStream_t s);
 // Device function of the rollout kernel launched by launch_rollout (for
 // explicit graph construction) and its dynamic LDS size.
 const void* rollout_kernel(bool spheres_only, bool quad, bool pq, int block, int max_n,

@@ -946,6 +946,33 @@ vmas_status vmas_autotune(vmas_batch* b, const float* state, const float* action
   return VMAS_OK;
 }
 
+// T reverse steps in one launch: states [T][6][N] (t0 .. t0 + T - 1), their
+// actions [T][A][2], dL/ds_{t0+T} -> dL/ds_t0 and dL/da of every step.
+static vmas_status adjoint_segment(vmas_batch* b, const float* states, const float* actions, int T,
+                                   const float* gnext, float* gstate, float* gact, hipStream_t s) {
+  // Entities without a lane in no group (environments of size 0) keep a zero gradient.
+  BackArgs a{};
+  a.state = states;
+  a.actions = actions;
+  a.gnext = gnext;
+  a.gstate = gstate;
+  a.gact = gact;
+  a.ent = b->d_ent;
+  a.lanes = b->back.d_lanes;
+  a.stage_off = b->back.d_stage_off;
+  a.stage = b->back.d_stage;
+  a.joff = b->d_joff;
+  a.jlist = b->d_jlist;
+  a.joints = b->d_joints;
+  a.max_stage = b->back.max_stage;
+  a.T = T;
+  a.w = b->w;
+  if (b->back.groups == 0) return VMAS_OK;
+  hipError_t e = launch_backward(a, b->back.groups, b->back.block, b->spheres_only, s);
+  if (e != hipSuccess) return fail(VMAS_ERR_DEVICE, "adjoint launch failed: %s", hipGetErrorString(e));
+  return VMAS_OK;
+}
+
 vmas_status vmas_step_backward(vmas_batch* b, const float* state_t, const float* actions_t,
                                const float* grad_state_next, float* grad_state_t,
                                float* grad_actions_t, void* stream) {
@@ -959,27 +986,8 @@ vmas_status vmas_step_backward(vmas_batch* b, const float* state_t, const float*
   if (!b->back.valid)
     return fail(VMAS_ERR_UNSUPPORTED, "an environment is too large for the adjoint plan");
   DeviceGuard guard(b->device);
-  hipStream_t s = (hipStream_t)stream;
-  // Entities without a lane in no group (environments of size 0) keep a zero gradient.
-  BackArgs a{};
-  a.state = state_t;
-  a.actions = actions_t;
-  a.gnext = grad_state_next;
-  a.gstate = grad_state_t;
-  a.gact = grad_actions_t;
-  a.ent = b->d_ent;
-  a.lanes = b->back.d_lanes;
-  a.stage_off = b->back.d_stage_off;
-  a.stage = b->back.d_stage;
-  a.joff = b->d_joff;
-  a.jlist = b->d_jlist;
-  a.joints = b->d_joints;
-  a.max_stage = b->back.max_stage;
-  a.w = b->w;
-  if (b->back.groups == 0) return VMAS_OK;
-  hipError_t e = launch_backward(a, b->back.groups, b->back.block, s);
-  if (e != hipSuccess) return fail(VMAS_ERR_DEVICE, "adjoint launch failed: %s", hipGetErrorString(e));
-  return VMAS_OK;
+  return adjoint_segment(b, state_t, actions_t, 1, grad_state_next, grad_state_t, grad_actions_t,
+                         (hipStream_t)stream);
 }
 
 vmas_status vmas_rollout_backward(vmas_batch* b, const float* state0, const float* actions,
@@ -991,6 +999,8 @@ vmas_status vmas_rollout_backward(vmas_batch* b, const float* state0, const floa
   if (T < 1) return fail(VMAS_ERR_INVALID_ARGUMENT, "T must be >= 1");
   if (ckpt_every < 1) return fail(VMAS_ERR_INVALID_ARGUMENT, "ckpt_every must be >= 1");
   if (!actions && b->A > 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "actions must not be NULL");
+  if (!b->back.valid)
+    return fail(VMAS_ERR_UNSUPPORTED, "an environment is too large for the adjoint plan");
   DeviceGuard guard(b->device);
   hipStream_t s = (hipStream_t)stream;
   const int k = std::min(ckpt_every, T);
@@ -1034,13 +1044,11 @@ vmas_status vmas_rollout_backward(vmas_batch* b, const float* state0, const floa
     vmas_status st = vmas_rollout(b, st_tmp, actions ? actions + A2 * (size_t)t0 : nullptr, 0, 0, len,
                                   seg, nullptr, stream);
     if (st != VMAS_OK) return st;
-    for (int t = len - 1; t >= 0; --t) {
-      const float* at = actions ? actions + A2 * (size_t)(t0 + t) : nullptr;
-      float* ga = grad_actions ? grad_actions + A2 * (size_t)(t0 + t) : nullptr;
-      st = vmas_step_backward(b, seg + S6 * t, at, g0, g1, ga, stream);
-      if (st != VMAS_OK) return st;
-      std::swap(g0, g1);
-    }
+    // the reverse steps of the segment in one launch
+    st = adjoint_segment(b, seg, actions ? actions + A2 * (size_t)t0 : nullptr, len, g0, g1,
+                         grad_actions ? grad_actions + A2 * (size_t)t0 : nullptr, s);
+    if (st != VMAS_OK) return st;
+    std::swap(g0, g1);
   }
   if (grad_state0)
     HIPCHK(hipMemcpyAsync(grad_state0, g0, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));

@@ -9,6 +9,8 @@ anywhere along the rollout (Eq. 2 jumps by c k ln 2 there), and
 environments past their FP64 predictability horizon, are excluded and
 counted.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -215,9 +217,20 @@ def test_checkpoint_stride_does_not_change_gradients():
         assert torch.equal(gs, outs[0][0]) and torch.equal(ga, outs[0][1])
 
 
-def test_rollout_backward_equals_step_chain():
-    """The checkpointed driver equals T explicit vmas_step_backward calls."""
-    w = W.spread(40, seed=3)
+def _chain_world(kind):
+    if kind == "spread":
+        return W.spread(40, seed=3)
+    w = W.mixed(12, n_spheres=8, n_boxes=2, n_lines=4, seed=5)
+    if kind == "mixed-capped":  # the speed clamp of the integration
+        w = dataclasses.replace(w, max_speed=np.full(w.n_entities, 0.6, np.float32))
+    return w
+
+
+@pytest.mark.parametrize("kind", ["spread", "mixed", "mixed-capped"])
+def test_rollout_backward_equals_step_chain(kind):
+    """The checkpointed driver (the reverse steps of a segment in one launch)
+    equals T explicit vmas_step_backward calls, bit for bit."""
+    w = _chain_world(kind)
     T = 12
     acts = w.actions(T)
     b = _batch(w)
