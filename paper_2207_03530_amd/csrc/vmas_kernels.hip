@@ -626,9 +626,11 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
           if (MD) dmin += w.min_dist;
           const float dx = x - P.x, dy = y - P.y;
           const float sq = fmaf(dx, dx, __fmul_rn(dy, dy));
-          V2 n;
-          float d;
-          sphere_normal(dx, dy, sq, r.slot < q, &d, &n);
+          // sphere_normal without a branch: the same values, selected
+          const float rs = __frsqrt_rn(sq);
+          const bool coincide = sq == 0.0f;
+          const float d = coincide ? 0.0f : sq * rs;
+          const V2 n = {coincide ? (r.slot < q ? 1.0f : -1.0f) : dx * rs, coincide ? 0.0f : dy * rs};
           const float F = contact_mag(dmin, d, w);
           fx = fmaf(F, n.x, fx);
           fy = fmaf(F, n.y, fy);
@@ -680,10 +682,15 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
 #pragma unroll
             for (int blk = 0; blk < NP; blk += 8) {
               if (blk < gmaxn - 1) {  // uniform over the block
+                // all reads of the block in flight before the tests (the
+                // scheduler otherwise holds one back behind the others)
+                float2 P[8];
+#pragma unroll
+                for (int v = 0; v < 8 && blk + v < NP; ++v) P[v] = pb[sl[blk + v]];
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int v = 0; v < 8 && blk + v < NP; ++v) {
-                  const float2 P = pb[sl[blk + v]];
-                  const float dx = x - P.x, dy = y - P.y;
+                  const float dx = x - P[v].x, dy = y - P[v].y;
                   const bool hit = fmaf(dx, dx, __fmul_rn(dy, dy)) <= dm2[blk + v];
                   hits |= (hit ? 1u : 0u) << (blk + v);
                 }
