@@ -592,15 +592,17 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
   constexpr bool HOIST = NB > 0 && NB <= 32;
   constexpr int NP = HOIST ? NB - 1 : 1;
   int sl[NP];
-  float dm2[NP];
+  float dm2[NP], pdm[NP];  // squared contact distance, contact distance
 #pragma unroll
   for (int u = 0; u < NP; ++u) {
     sl[u] = u + (u >= myloc ? 1 : 0);
     dm2[u] = -1.0f;
+    pdm[u] = 0.0f;
     if (HOIST && collide && sl[u] < nloc) {
       float dmin = p.rho + stat[r.lo + sl[u]].x;
       if (MD) dmin += w.min_dist;
       dm2[u] = __fmul_rn(dmin, dmin);
+      pdm[u] = dmin;
     }
   }
   // NB == 64: slots u < nloc other than the lane's own
@@ -678,6 +680,56 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
             // partner first, so a wavefront runs the force code as often as
             // its busiest lane has contacts.
             const float2* pb = ((k & 1) ? pos1 : pos0) + r.lo;  // KCH is even
+            if constexpr (NP <= 8) {
+              // one block: the offsets stay in registers, and a contact
+              // picks its partner's values by selects instead of reading
+              // the partner from LDS again
+              if (0 < gmaxn - 1) {  // uniform over the block
+                float2 P[NP];
+#pragma unroll
+                for (int v = 0; v < NP; ++v) P[v] = pb[sl[v]];
+                __builtin_amdgcn_sched_barrier(0);
+                float pdx[NP], pdy[NP], psq[NP];
+                uint32_t hits = 0;
+#pragma unroll
+                for (int v = 0; v < NP; ++v) {
+                  pdx[v] = x - P[v].x;
+                  pdy[v] = y - P[v].y;
+                  psq[v] = fmaf(pdx[v], pdx[v], __fmul_rn(pdy[v], pdy[v]));
+                  hits |= (psq[v] <= dm2[v] ? 1u : 0u) << v;
+                }
+                while (hits) {
+                  const int u = __builtin_ctz(hits);
+                  hits &= hits - 1;
+                  float dx = pdx[0], dy = pdy[0], sq = psq[0], dmin = pdm[0];
+                  int b = sl[0];
+#pragma unroll
+                  for (int v = 1; v < NP; ++v) {
+                    const bool m = u == v;
+                    dx = m ? pdx[v] : dx;
+                    dy = m ? pdy[v] : dy;
+                    sq = m ? psq[v] : sq;
+                    dmin = m ? pdm[v] : dmin;
+                    b = m ? sl[v] : b;
+                  }
+                  const float rs = __frsqrt_rn(sq);
+                  const bool coincide = sq == 0.0f;
+                  const float d = coincide ? 0.0f : sq * rs;
+                  const V2 n = {coincide ? (myloc < b ? 1.0f : -1.0f) : dx * rs, coincide ? 0.0f : dy * rs};
+                  const float F = contact_mag(dmin, d, w);
+                  fx = fmaf(F, n.x, fx);
+                  fy = fmaf(F, n.y, fy);
+                  if (mk) {
+                    const int of = __float_as_int(stat[r.lo + b].y) >> 8;
+                    if (myloc < b || (of & (MOVABLE | ROTATABLE)) == 0) {
+                      const int ia = min(myloc, b), ib = max(myloc, b);
+                      const int64_t idx = (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
+                      mk[a.pair_off[r.env] + idx] = 1;
+                    }
+                  }
+                }
+              }
+            } else {
             uint32_t hits = 0;
 #pragma unroll
             for (int blk = 0; blk < NP; blk += 8) {
@@ -700,6 +752,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
               const int u = __builtin_ctz(hits);
               hits &= hits - 1;
               contact(r.lo + u + (u >= myloc ? 1 : 0));
+            }
             }
           } else {
             // any size: 32 partners per pass, tested into a bit mask, then the
