@@ -97,7 +97,13 @@ struct StepArgs {
   // sphere-segment, box-box, box-segment, segment-segment) and their sum;
   // all 0 for the other plans
   int32_t pq_cap[6];
-  int32_t pad2[2];
+  // eligible pairs of each group (collidable, one side with a lane, not
+  // switched off by a joint), packed slot_lo | slot_hi << 11 | lo << 22 |
+  // hi << 27, groups back to back
+  const uint32_t* pq_pairs;
+  const int32_t* pq_pair_off;  // [groups + 1]
+  int32_t pq_max_pairs;        // most pairs of one group (at most 32 x block)
+  int32_t pad2;
   WorldK w;
 };
 
@@ -143,8 +149,8 @@ hipError_t launch_backward(const BackArgs& a, int groups, int block, bool sphere
 // explicit graph construction) and its dynamic LDS size.
 const void* rollout_kernel(bool spheres_only, bool quad, bool pq, int block, int max_n,
                            float min_dist, bool out);
-size_t rollout_lds_bytes(int max_stage, bool spheres_only, bool quad, int pq_total, int block,
-                         int max_n);
+size_t rollout_lds_bytes(int max_stage, bool spheres_only, bool quad, int pq_total, int pq_pairs,
+                         int block, int max_n);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);

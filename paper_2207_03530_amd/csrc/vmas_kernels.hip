@@ -149,7 +149,9 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
   int* qcap = qcnt + 8;                                      // [8] capacity per class
   int* qbase = qcnt + 16;                                    // [8] first entry of each class
   uint32_t* qent = reinterpret_cast<uint32_t*>(qcnt + 24);   // [QT] slot_lo | slot_hi << 11 | lo << 22 | hi << 27
-  uint16_t* qmap = reinterpret_cast<uint16_t*>(qent + QT);   // [E][32] queue entry of (entity, partner)
+  uint32_t* sphw = qent + QT;                                // [E] sphere partners to evaluate
+  uint32_t* pairs = sphw + E;                                // [pq_max_pairs] the group's pairs
+  uint16_t* qmap = reinterpret_cast<uint16_t*>(pairs + (PQ ? a.pq_max_pairs : 0));  // [E][32] queue entry of (entity, partner)
   const int g = blockIdx.x, l = threadIdx.x, B = blockDim.x;
   const int N = a.w.N;
   const int s0 = a.stage_off[g], ns = a.stage_off[g + 1] - s0;
@@ -165,6 +167,8 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
     brad[s] = ((p.sf >> 8) & COLLIDABLE) ? bounding_radius(p.sf & 0xff, p.d0, p.d1)
                                          : __int_as_float(0x7fc00000);
   }
+  const int np0 = PQ ? a.pq_pair_off[g] : 0, npairs = PQ ? a.pq_pair_off[g + 1] - np0 : 0;
+  for (int k = l; k < npairs; k += B) pairs[k] = a.pq_pairs[np0 + k];
   if (PQ && l == 0) {
     int acc = 0;
 #pragma unroll
@@ -206,16 +210,11 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
   }
   __syncthreads();
   // shape classes of the first 32 partners (static for the whole rollout)
-  uint32_t cls_sph0 = 0, cls_box0 = 0, own0 = 0;
+  uint32_t cls_sph0 = 0, cls_box0 = 0;
   for (int u = 0; u < min(32, nloc); ++u) {
-    const int sfo = __float_as_int(stat[r.lo + u].w);
-    const int so = sfo & 0xff;
+    const int so = __float_as_int(stat[r.lo + u].w) & 0xff;
     cls_sph0 |= (so == SPHERE ? 1u : 0u) << u;
     cls_box0 |= (so == BOX ? 1u : 0u) << u;
-    // PQ: pairs this lane owns (queues): higher partners, and partners without a lane
-    const bool other_lane = ((sfo >> 8) & (MOVABLE | ROTATABLE)) != 0;
-    if (PQ && (u > myloc || !other_lane) && !(p.excl != -1 && excluded(p.excl, u)))
-      own0 |= 1u << u;
   }
   for (int t = 0; t < a.T; ++t) {
     float4* cur = (t & 1) ? buf1 : buf0;
@@ -229,6 +228,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
         if (t > 0) cur[r.slot] = make_float4(x, y, cs, sn);
         hitw[r.slot] = 0u;
         selfw[r.slot] = 0u;
+        sphw[r.slot] = 0u;
       }
       if (l < 8) qcnt[l] = 0;
       __syncthreads();
@@ -249,39 +249,43 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
     const bool last = t == a.T - 1;
     uint8_t* mk = (last && a.mask) ? a.mask : nullptr;
     if (PQ) {
-      // Broad phase of the lane's partners; the owned candidates of a pair
-      // class are queued (sphere pairs of a sphere lane stay on the lane).
-      uint32_t cand = 0;
-      if (collide) {
-        const float rs = bounding_radius(shape, p.d0, p.d1);
-        const float reach = w.min_dist + 1e-4f + 1e-5f * (fabsf(x) + fabsf(y));
-        for (int u = 0; u < nloc; ++u) {
-          const int q = r.lo + u;
-          const float4 P = cur[q];
-          const float dx = x - P.x, dy = y - P.y;
-          const float lim = (rs + brad[q]) + reach;
-          cand |= (dx * dx + dy * dy <= lim * lim ? 1u : 0u) << u;
+      // Broad phase over the group's pairs, spread evenly over its lanes
+      // (margin from the larger coordinates of the two): sphere pairs are
+      // marked for both of their lanes, the others go to their class queue.
+      // Tests first (no LDS atomic waits in between), then the candidates.
+      uint32_t pc = 0;  // bit i: pair l + i B passed
+      for (int k = l, i = 0; k < npairs; k += B, ++i) {
+        const uint32_t pe = pairs[k];
+        const int qa = pe & 0x7ff, qb = (pe >> 11) & 0x7ff;
+        const float4 Pa = cur[qa], Pb = cur[qb];
+        const float dx = Pa.x - Pb.x, dy = Pa.y - Pb.y;
+        const float reach =
+            w.min_dist + 1e-4f + 1e-5f * fmaxf(fabsf(Pa.x) + fabsf(Pa.y), fabsf(Pb.x) + fabsf(Pb.y));
+        const float lim = (brad[qa] + brad[qb]) + reach;
+        pc |= (dx * dx + dy * dy <= lim * lim ? 1u : 0u) << i;
+      }
+      while (pc) {
+        const int i = __builtin_ctz(pc);
+        pc &= pc - 1;
+        const uint32_t pe = pairs[l + i * B];
+        const int qa = pe & 0x7ff, qb = (pe >> 11) & 0x7ff;
+        const int la = (pe >> 22) & 31, lb = pe >> 27;
+        const int sa = __float_as_int(stat[qa].w) & 0xff, sb = __float_as_int(stat[qb].w) & 0xff;
+        if (sa == SPHERE && sb == SPHERE) {
+          atomicOr(&sphw[qa], 1u << lb);
+          atomicOr(&sphw[qb], 1u << la);
+          continue;
         }
-        cand &= ~(1u << myloc);
-        uint32_t own = cand & own0 & (shape == SPHERE ? ~cls_sph0 : ~0u);
-        while (own) {
-          const int u = __builtin_ctz(own);
-          own &= own - 1;
-          const int so = (cls_sph0 >> u) & 1 ? SPHERE : ((cls_box0 >> u) & 1 ? BOX : LINE);
-          const int c = pair_class(shape, so);
-          const int k = atomicAdd(&qcnt[c], 1);
-          const int qo = r.lo + u;
-          if (k < qcap[c]) {
-            const int e = qbase[c] + k;
-            const int sa = min(r.slot, qo), sb = max(r.slot, qo);
-            const int la = min(myloc, u), lb = max(myloc, u);
-            qent[e] = (uint32_t)sa | ((uint32_t)sb << 11) | ((uint32_t)la << 22) | ((uint32_t)lb << 27);
-            qmap[r.slot * 32 + u] = (uint16_t)e;
-            qmap[qo * 32 + myloc] = (uint16_t)e;
-          } else {
-            atomicOr(&selfw[r.slot], 1u << u);
-            atomicOr(&selfw[qo], 1u << myloc);
-          }
+        const int c = pair_class(sa, sb);
+        const int kq = atomicAdd(&qcnt[c], 1);
+        if (kq < qcap[c]) {
+          const int e = qbase[c] + kq;
+          qent[e] = pe;
+          qmap[qa * 32 + lb] = (uint16_t)e;
+          qmap[qb * 32 + la] = (uint16_t)e;
+        } else {
+          atomicOr(&selfw[qa], 1u << lb);
+          atomicOr(&selfw[qb], 1u << la);
         }
       }
       lds_barrier();
@@ -363,7 +367,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
         };
         const uint32_t mline = ~(cls_sph0 | cls_box0);
         if (shape == SPHERE)
-          run(std::integral_constant<int, SPHERE>{}, cand & cls_sph0, true);
+          run(std::integral_constant<int, SPHERE>{}, sphw[r.slot] & cls_sph0, true);
         else
           run(std::integral_constant<int, SPHERE>{}, (hits | mine) & cls_sph0, false);
         run(std::integral_constant<int, BOX>{}, (hits | mine) & cls_box0, false);
@@ -1133,13 +1137,13 @@ const void* rollout_kernel(bool spheres_only, bool quad, bool pq, int block, int
   return block <= 256 ? (const void*)k_rollout<256, false> : (const void*)k_rollout<1024, false>;
 }
 
-size_t rollout_lds_bytes(int max_stage, bool spheres_only, bool quad, int pq_total, int block,
-                         int max_n) {
+size_t rollout_lds_bytes(int max_stage, bool spheres_only, bool quad, int pq_total, int pq_pairs,
+                         int block, int max_n) {
   if (quad) return 0;
   if (!spheres_only && pq_total > 0)
     return (size_t)(3 * max_stage + pq_total) * sizeof(float4) +
-           (size_t)max_stage * (3 * sizeof(uint32_t) + 32 * sizeof(uint16_t)) + 24 * sizeof(int) +
-           (size_t)pq_total * sizeof(uint32_t);
+           (size_t)max_stage * (4 * sizeof(uint32_t) + 32 * sizeof(uint16_t)) + 24 * sizeof(int) +
+           (size_t)(pq_total + pq_pairs) * sizeof(uint32_t);
   if (!spheres_only) return (size_t)max_stage * (3 * sizeof(float4) + sizeof(float));
   return (size_t)(max_stage + sph_pad(block, max_n)) * 3 * sizeof(float2);
 }
@@ -1150,7 +1154,8 @@ hipError_t launch_rollout(const StepArgs& a, int groups, int block, bool spheres
   const bool out = a.traj || a.mask || a.forces;
   const int pq_total = a.pq_cap[PQ_CLASSES];
   const void* f = rollout_kernel(spheres_only, quad, pq_total > 0, block, a.max_n, a.w.min_dist, out);
-  const size_t shm = rollout_lds_bytes(a.max_stage, spheres_only, quad, pq_total, block, a.max_n);
+  const size_t shm =
+      rollout_lds_bytes(a.max_stage, spheres_only, quad, pq_total, a.pq_max_pairs, block, a.max_n);
   StepArgs args = a;
   void* kargs[1] = {&args};
   return hipLaunchKernel(f, dim3(groups), dim3(block), kargs, shm, s);

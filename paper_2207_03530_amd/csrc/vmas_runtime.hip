@@ -60,6 +60,9 @@ struct Plan {
   bool quad = false;          // quad schedule (d_quad), no lane records
   bool pq = false;            // pair-queue variant of the entity-lane kernel
   int32_t pq_cap[6] = {0, 0, 0, 0, 0, 0};  // queue capacity per pair class, then the sum
+  uint32_t* d_pq_pairs = nullptr;   // eligible pairs of each group
+  int32_t* d_pq_pair_off = nullptr;
+  int pq_max_pairs = 0;
   QuadEnv* d_quad = nullptr;
   LaneRec* d_lanes = nullptr;
   int32_t* d_stage_off = nullptr;
@@ -133,6 +136,10 @@ void free_plan(Plan& p) {
   if (p.d_stage) (void)hipFree(p.d_stage);
   if (p.d_maxn) (void)hipFree(p.d_maxn);
   if (p.d_quad) (void)hipFree(p.d_quad);
+  if (p.d_pq_pairs) (void)hipFree(p.d_pq_pairs);
+  if (p.d_pq_pair_off) (void)hipFree(p.d_pq_pair_off);
+  p.d_pq_pairs = nullptr;
+  p.d_pq_pair_off = nullptr;
   p.d_quad = nullptr;
   p.d_maxn = nullptr;
   p.d_lanes = nullptr;
@@ -281,8 +288,11 @@ vmas_status validate(const vmas_world_params* pr, const vmas_batch_desc* d, Host
 
 // Builds one launch plan on the host and uploads it.
 // Queue capacity per pair class of the pair-queue plans: the most eligible
-// pairs of the class in one group, at most PQ_CAP_MAX (pairs beyond a full
-// queue are evaluated by both lanes).
+// pairs of the class in one group, at most PQ_CAP_PER_ENV per environment of
+// the group and PQ_CAP_MAX in all (pairs beyond a full queue are evaluated by
+// both of their lanes, so the capacity trades LDS, hence resident
+// workgroups, against that slower path).
+constexpr int PQ_CAP_PER_ENV = 32;
 constexpr int PQ_CAP_MAX = 256;
 constexpr size_t PQ_LDS_MAX = 64 * 1024;
 
@@ -394,19 +404,30 @@ vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8
     }
     const std::vector<EntParam>& ent = *pq_ent;
     int cap[5] = {0, 0, 0, 0, 0};
+    std::vector<uint32_t> pairs;
+    std::vector<int32_t> pair_off(G + 1, 0);
     for (int g = 0; g < G; ++g) {
       int cnt[5] = {0, 0, 0, 0, 0};
+      int slot = 0;  // LDS slot of the environment's first entity
       for (int e : groups[g]) {
+        const int n = h.off[e + 1] - h.off[e];
         for (int i = h.off[e]; i < h.off[e + 1]; ++i)
           for (int j = i + 1; j < h.off[e + 1]; ++j) {
             if (!(flags[i] & COLLIDABLE) || !(flags[j] & COLLIDABLE)) continue;
             if (!(flags[i] & (MOVABLE | ROTATABLE)) && !(flags[j] & (MOVABLE | ROTATABLE))) continue;
+            const int li = i - h.off[e], lj = j - h.off[e];
+            if (excludes(ent[i].excl, lj)) continue;
+            pairs.push_back((uint32_t)(slot + li) | ((uint32_t)(slot + lj) << 11) |
+                            ((uint32_t)li << 22) | ((uint32_t)lj << 27));
             if (shape[i] == SPHERE && shape[j] == SPHERE) continue;
-            if (excludes(ent[i].excl, j - h.off[e])) continue;
             ++cnt[pq_pair_class(shape[i], shape[j])];
           }
+        slot += n;
       }
-      for (int c = 0; c < 5; ++c) cap[c] = std::max(cap[c], std::min(cnt[c], PQ_CAP_MAX));
+      pair_off[g + 1] = (int32_t)pairs.size();
+      p.pq_max_pairs = std::max(p.pq_max_pairs, pair_off[g + 1] - pair_off[g]);
+      const int lim = std::min(PQ_CAP_MAX, PQ_CAP_PER_ENV * (int)groups[g].size());
+      for (int c = 0; c < 5; ++c) cap[c] = std::max(cap[c], std::min(cnt[c], lim));
     }
     int total = 0;
     for (int c = 0; c < 5; ++c) {
@@ -414,11 +435,17 @@ vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8
       total += cap[c];
     }
     p.pq_cap[5] = total;
-    if (total == 0 ||
-        rollout_lds_bytes(p.max_stage, false, false, total, block, p.max_n) > PQ_LDS_MAX) {
+    // a lane tests at most 32 pairs per step (one bit each)
+    if (total == 0 || p.pq_max_pairs > 32 * block ||
+        rollout_lds_bytes(p.max_stage, false, false, total, p.pq_max_pairs, block, p.max_n) >
+            PQ_LDS_MAX) {
       p.valid = false;
       return VMAS_OK;
     }
+    vmas_status s;
+    if ((s = upload(&p.d_pq_pairs, pairs.data(), std::max<size_t>(pairs.size(), 1))) != VMAS_OK)
+      return s;
+    if ((s = upload(&p.d_pq_pair_off, pair_off.data(), pair_off.size())) != VMAS_OK) return s;
   }
   vmas_status s;
   if ((s = upload(&p.d_lanes, lane.data(), lane.size())) != VMAS_OK) return s;
@@ -488,6 +515,9 @@ StepArgs make_args(vmas_batch* b, const Plan& p) {
   a.env_off = b->d_env_off;
   a.n_envs = b->n_envs;
   for (int c = 0; c < 6; ++c) a.pq_cap[c] = p.pq ? p.pq_cap[c] : 0;
+  a.pq_pairs = p.pq ? p.d_pq_pairs : nullptr;
+  a.pq_pair_off = p.pq ? p.d_pq_pair_off : nullptr;
+  a.pq_max_pairs = p.pq ? p.pq_max_pairs : 0;
   a.w = b->w;
   return a;
 }
@@ -855,7 +885,8 @@ vmas_status vmas_rollout_graph(vmas_batch* b, float* state, const float* actions
   kp.gridDim = dim3(p.groups);
   kp.blockDim = dim3(p.block);
   kp.sharedMemBytes = (unsigned)rollout_lds_bytes(p.max_stage, b->spheres_only, p.quad,
-                                                  p.pq ? p.pq_cap[5] : 0, p.block, p.max_n);
+                                                  p.pq ? p.pq_cap[5] : 0, p.pq_max_pairs, p.block,
+                                                  p.max_n);
   kp.kernelParams = args;
   kp.extra = nullptr;
   if (!b->gexec || b->graph_T != T || b->graph_plan != b->cur || b->graph_drawn != drawn) {
