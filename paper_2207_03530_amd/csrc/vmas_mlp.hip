@@ -32,12 +32,24 @@ constexpr int LDH = NH + 8;     // padded row stride (bf16) of 128-wide operands
 constexpr int LDI = NIP + 8;    // padded row stride of 16-wide operands
 constexpr int LDR = ROWS + 8;   // padded row stride of transposed (K = rows) operands
 
-// BF16 from FP32, round to nearest even (NaN kept quiet).
+// BF16 from FP32, round to nearest even (the hardware conversion).
 __device__ __forceinline__ unsigned short to_bf16(float f) {
-  unsigned u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+  return __builtin_bit_cast(unsigned short, (__bf16)f);
+}
+
+// tanh x = (e^{2x} - 1) / (e^{2x} + 1) with the hardware exp2 and reciprocal
+// (each about 1 ulp): absolute error of a few 1e-7, far below the BF16
+// rounding the activations go through; |x| is clamped to 9, where tanh is 1
+// in FP32. Inference uses it; training (activations kept for the backward
+// pass) uses tanhf, so a training run does not depend on this shortcut.
+__device__ __forceinline__ float tanh_fast(float x) {
+  const float c = fminf(fmaxf(x, -9.0f), 9.0f);
+  const float e = __builtin_amdgcn_exp2f(c * 2.8853900817779268f);  // 2 / ln 2
+  return (e - 1.0f) * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+template <bool TRAIN> __device__ __forceinline__ float act(float x) {
+  if constexpr (TRAIN) return tanhf(x);
+  else return tanh_fast(x);
 }
 __device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
@@ -92,9 +104,10 @@ __device__ void stage_weights(const MlpArgs& m, unsigned short* w1, unsigned sho
   }
 }
 
-// Forward pass over 64-row tiles. X [n][12] -> Y [n][2]; optionally the FP32
+// Forward pass over 64-row tiles. X [n][12] -> Y [n][2]; TRAIN: also the FP32
 // activations H1, H2 [n][128] for the backward pass. With n_dev set, the row
 // count is min(n, *n_dev), read on the device.
+template <bool TRAIN>
 __global__ void __launch_bounds__(256) k_mlp_forward(MlpArgs m, const float* __restrict__ X,
                                                      int64_t n, const int32_t* __restrict__ n_dev,
                                                      float* __restrict__ Y,
@@ -129,7 +142,7 @@ __global__ void __launch_bounds__(256) k_mlp_forward(MlpArgs m, const float* __r
       acc = mma(acc, xs, LDI, r0, w1, LDI, j * 16, NIP, lane);
       const int c = j * 16 + col;
       for (int i = 0; i < 4; ++i) {
-        const float h = tanhf(acc[i] + bias[c]);
+        const float h = act<TRAIN>(acc[i] + bias[c]);
         const int r = r0 + rq + i;
         h1s[r * LDH + c] = to_bf16(h);
         if (H1 && row0 + r < n) H1[(row0 + r) * NH + c] = h;
@@ -138,15 +151,25 @@ __global__ void __launch_bounds__(256) k_mlp_forward(MlpArgs m, const float* __r
     __syncthreads();
     // layer 2: h2 = tanh(h1 W2^T + b2); all 8 column tiles are accumulated in
     // registers first, then h2 overwrites this wavefront's own rows of h1
+    // (the wavefront's 16 rows of h1 are read from LDS once, as 8 fragments)
     f4 acc2[NH / 16];
-    for (int j = 0; j < NH / 16; ++j) {
-      acc2[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-      acc2[j] = mma(acc2[j], h1s, LDH, r0, w2, LDH, j * 16, NH, lane);
+    {
+      s4 a[NH / 16];
+#pragma unroll
+      for (int kk = 0; kk < NH / 16; ++kk) a[kk] = frag(h1s, LDH, r0 + col, kk * 16 + rq);
+#pragma unroll
+      for (int j = 0; j < NH / 16; ++j) {
+        acc2[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kk = 0; kk < NH / 16; ++kk)
+          acc2[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+              a[kk], frag(w2, LDH, j * 16 + col, kk * 16 + rq), acc2[j], 0, 0, 0);
+      }
     }
     for (int j = 0; j < NH / 16; ++j) {
       const int c = j * 16 + col;
       for (int i = 0; i < 4; ++i) {
-        const float h = tanhf(acc2[j][i] + bias[NH + c]);
+        const float h = act<TRAIN>(acc2[j][i] + bias[NH + c]);
         const int r = r0 + rq + i;
         h1s[r * LDH + c] = to_bf16(h);
         if (H2 && row0 + r < n) H2[(row0 + r) * NH + c] = h;
@@ -441,8 +464,12 @@ hipError_t mlp_launch_forward(const unsigned short* W1, const unsigned short* W2
   MlpArgs m{W1, W2, W3, b1, b2, b3};
   const int64_t tiles = (n + ROWS - 1) / ROWS;
   const int64_t blocks = tiles < 2048 ? tiles : 2048;  // 8 workgroups per CU walk the tiles
-  hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)blocks), dim3(256), 0, s, m, X, n, n_dev, Y, H1,
-                     H2);
+  if (H1 || H2)
+    hipLaunchKernelGGL(k_mlp_forward<true>, dim3((unsigned)blocks), dim3(256), 0, s, m, X, n, n_dev,
+                       Y, H1, H2);
+  else
+    hipLaunchKernelGGL(k_mlp_forward<false>, dim3((unsigned)blocks), dim3(256), 0, s, m, X, n, n_dev,
+                       Y, H1, H2);
   return hipGetLastError();
 }
 
