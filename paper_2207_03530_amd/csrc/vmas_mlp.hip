@@ -188,6 +188,83 @@ __global__ void __launch_bounds__(256) k_mlp_forward(MlpArgs m, const float* __r
   }
 }
 
+// Inference forward pass with the layers transposed: a wavefront computes
+// H1^T = tanh(W1 X^T + b1), H2^T = tanh(W2 H1^T + b2), Y^T = W3 H2^T + b3 for
+// 16 rows. The 16 x 16 result of one matrix-core product gives lane l the
+// hidden units 4 (l / 16) .. +3 of row l % 16, which is exactly the B
+// fragment (k = those hidden units, column = that row) of the next layer's
+// product, so activations stay in registers: no LDS round trip and no
+// barrier between layers. The weights are staged in LDS once per workgroup.
+constexpr int INFER_WAVES = 8;                  // wavefronts per workgroup (one weight copy)
+constexpr int INFER_ROWS = 16 * INFER_WAVES;     // rows per workgroup tile
+__global__ void __launch_bounds__(64 * INFER_WAVES)
+k_mlp_infer(MlpArgs m, const float* __restrict__ X, int64_t n, const int32_t* __restrict__ n_dev,
+            float* __restrict__ Y) {
+  if (n_dev) n = min(n, (int64_t)max(*n_dev, 0));
+  const int64_t tiles = (n + INFER_ROWS - 1) / INFER_ROWS;
+  if ((int64_t)blockIdx.x >= tiles) return;  // uniform per workgroup, before any barrier
+  __shared__ __attribute__((aligned(16))) unsigned short w1[NH * LDI], w2[NH * LDH], w3[NOP * LDH];
+  __shared__ __attribute__((aligned(16))) float bias[NH + NH + NOP];
+  stage_weights(m, w1, w2, w3);
+  for (int i = threadIdx.x; i < NH; i += blockDim.x) {
+    bias[i] = m.b1[i];
+    bias[NH + i] = m.b2[i];
+  }
+  if (threadIdx.x < NOP) bias[2 * NH + threadIdx.x] = threadIdx.x < NO ? m.b3[threadIdx.x] : 0.0f;
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, kq = (lane >> 4) * 4;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t row = tile * INFER_ROWS + wv * 16 + col;  // this lane's row (column of the products)
+    // B fragment of X^T: features kq .. kq + 3 of the row (zero past 12 and past n)
+    s4 bx;
+    {
+      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (row < n && kq < NI) v = *reinterpret_cast<const float4*>(X + row * NI + kq);
+      bx = s4{(short)to_bf16(v.x), (short)to_bf16(v.y), (short)to_bf16(v.z), (short)to_bf16(v.w)};
+    }
+    auto activate = [&](f4 acc, int boff) {
+      const float4 b = *reinterpret_cast<const float4*>(bias + boff + kq);
+      return s4{(short)to_bf16(tanh_fast(acc[0] + b.x)), (short)to_bf16(tanh_fast(acc[1] + b.y)),
+                (short)to_bf16(tanh_fast(acc[2] + b.z)), (short)to_bf16(tanh_fast(acc[3] + b.w))};
+    };
+    // layer 1: 8 blocks of 16 hidden units
+    s4 h1[NH / 16];
+#pragma unroll
+    for (int t = 0; t < NH / 16; ++t) {
+      f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag(w1, LDI, t * 16 + col, kq), bx, acc, 0, 0, 0);
+      h1[t] = activate(acc, t * 16);
+    }
+    // layer 2: the 8 output blocks advance together (independent
+    // accumulators keep the matrix cores busy), input block by input block
+    f4 acc2[NH / 16];
+#pragma unroll
+    for (int u = 0; u < NH / 16; ++u) acc2[u] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < NH / 16; ++t) {
+#pragma unroll
+      for (int u = 0; u < NH / 16; ++u)
+        acc2[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag(w2, LDH, u * 16 + col, t * 16 + kq),
+                                                            h1[t], acc2[u], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);  // 8 weight fragments live at a time
+    }
+    s4 h2[NH / 16];
+#pragma unroll
+    for (int u = 0; u < NH / 16; ++u) h2[u] = activate(acc2[u], NH + u * 16);
+    // layer 3: outputs 0 and 1 land in lanes 0 .. 15, elements 0 and 1
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int u = 0; u < NH / 16; ++u)
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag(w3, LDH, col, u * 16 + kq), h2[u], acc, 0,
+                                                      0, 0);
+    if (kq == 0 && row < n) {
+      Y[row * NO] = acc[0] + bias[2 * NH];
+      Y[row * NO + 1] = acc[1] + bias[2 * NH + 1];
+    }
+  }
+}
+
 // Backward pass of 64 rows given dY [n][2] and the forward activations.
 // Writes dX [n][12] (optional) and this workgroup's partial gradient of all
 // parameters, in the canonical order W1 (128x12), b1, W2 (128x128), b2,
@@ -467,9 +544,12 @@ hipError_t mlp_launch_forward(const unsigned short* W1, const unsigned short* W2
   if (H1 || H2)
     hipLaunchKernelGGL(k_mlp_forward<true>, dim3((unsigned)blocks), dim3(256), 0, s, m, X, n, n_dev,
                        Y, H1, H2);
-  else
-    hipLaunchKernelGGL(k_mlp_forward<false>, dim3((unsigned)blocks), dim3(256), 0, s, m, X, n, n_dev,
-                       Y, H1, H2);
+  else {
+    const int64_t itiles = (n + INFER_ROWS - 1) / INFER_ROWS;
+    const int64_t iblocks = itiles < 768 ? itiles : 768;  // 3 workgroups per CU walk the tiles
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)iblocks), dim3(64 * INFER_WAVES), 0, s, m, X, n,
+                       n_dev, Y);
+  }
   return hipGetLastError();
 }
 
