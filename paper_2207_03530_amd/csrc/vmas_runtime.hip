@@ -117,6 +117,8 @@ struct vmas_batch {
   int cur = 0;
   int lane_plan = 0;  // entity-lane plan of the surrogate kernels: the largest block up to 256
   Plan back;  // adjoint plan: every entity has a lane
+  Plan cand;  // 1024-lane plan of the surrogate's candidate kernel (fewer workgroups
+              // take rows from the one shared counter)
   // checkpoint workspace of the adjoint driver and the autotuner scratch
   float* d_ws = nullptr;
   size_t ws_floats = 0;
@@ -153,6 +155,7 @@ void free_batch(vmas_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (auto& p : b->plans) free_plan(p);
   free_plan(b->back);
+  free_plan(b->cand);
   if (b->d_ent) (void)hipFree(b->d_ent);
   if (b->d_joff) (void)hipFree(b->d_joff);
   if (b->d_jlist) (void)hipFree(b->d_jlist);
@@ -755,6 +758,10 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
     }
     b->plans.push_back(p);
   }
+  if (P > 0 && (s = build_plan(b, h, shape, flags, 1024, false, b->cand)) != VMAS_OK) {
+    free_batch(b);
+    return s;
+  }
   {
     int need = 64;
     for (int e = 0; e < E; ++e)
@@ -1137,7 +1144,14 @@ vmas_status vmas_step_surrogate(vmas_batch* b, vmas_mlp* mlp, float* state, cons
     // candidates' features into consecutive rows, the network on those rows only
     int32_t* count = b->d_rows + b->P;
     HIPCHK(launch_fill_i32(count, 1, 0, s));
-    HIPCHK(launch_candidate_features(a, p.groups, p.block, band, b->d_feat, b->d_rows, count, s));
+    if (b->cand.valid) {
+      StepArgs ac = make_args(b, b->cand);
+      ac.state = state;
+      HIPCHK(launch_candidate_features(ac, b->cand.groups, b->cand.block, band, b->d_feat, b->d_rows,
+                                       count, s));
+    } else {
+      HIPCHK(launch_candidate_features(a, p.groups, p.block, band, b->d_feat, b->d_rows, count, s));
+    }
     vmas_status st = mlp_forward_counted(mlp, b->d_feat, b->P, count, b->d_yhat, s);
     if (st != VMAS_OK) return st;
   }

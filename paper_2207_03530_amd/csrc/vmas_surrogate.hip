@@ -183,10 +183,11 @@ struct CandArgs {
 // one has no lane. Rows: each lane counts its candidates, the workgroup
 // scans the counts in LDS and takes its block of rows with one atomic, then
 // every lane writes its candidates in partner order.
-__global__ void __launch_bounds__(256) k_cand_features(CandArgs ca) {
+template <int MAXB>
+__global__ void __launch_bounds__(MAXB) k_cand_features(CandArgs ca) {
   const StepArgs& a = ca.s;
   extern __shared__ float4 lds[];
-  __shared__ int scan[256];
+  __shared__ int scan[MAXB / 64];  // wavefront totals
   __shared__ int gbase;
   const int E = a.max_stage;
   float4* pose = lds;
@@ -227,25 +228,45 @@ __global__ void __launch_bounds__(256) k_cand_features(CandArgs ca) {
     return myloc < b ? net_candidate(me.x, me.y, rme, shape, P.x, P.y, ro, so, ca.band)
                      : net_candidate(P.x, P.y, ro, so, me.x, me.y, rme, shape, ca.band);
   };
+  // environments of at most 32 entities: one pass into a bit mask (bit b:
+  // local partner b); larger ones test every partner again below
+  const bool small = nloc <= 32;
+  uint32_t cm = 0;
   int cnt = 0;
-  if (live)
-    for (int q = r.lo; q < r.hi; ++q) cnt += mine(q) ? 1 : 0;
-  // inclusive scan of the lane counts over the workgroup
-  scan[l] = cnt;
-  __syncthreads();
-  for (int off = 1; off < B; off <<= 1) {
-    const int v = l >= off ? scan[l - off] : 0;
-    __syncthreads();
-    scan[l] += v;
-    __syncthreads();
+  if (live) {
+    if (small) {
+      for (int q = r.lo; q < r.hi; ++q) cm |= (mine(q) ? 1u : 0u) << (q - r.lo);
+      cnt = __popc(cm);
+    } else {
+      for (int q = r.lo; q < r.hi; ++q) cnt += mine(q) ? 1 : 0;
+    }
   }
-  if (l == B - 1) gbase = scan[B - 1] > 0 ? atomicAdd(ca.count, scan[B - 1]) : 0;
+  // exclusive prefix of the lane counts over the workgroup: within each
+  // wavefront by shuffles, then the wavefront totals
+  const int wl = l & 63, wv = l >> 6;
+  int inc = cnt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(inc, off, 64);
+    if (wl >= off) inc += v;
+  }
+  if (wl == 63) scan[wv] = inc;  // wavefront totals
+  __syncthreads();
+  if (l == 0) {
+    int total = 0;
+    for (int k = 0; k < (B + 63) / 64; ++k) {
+      const int t = scan[k];
+      scan[k] = total;  // exclusive prefix of the wavefront totals
+      total += t;
+    }
+    gbase = total > 0 ? atomicAdd(ca.count, total) : 0;
+  }
   __syncthreads();
   if (!live || cnt == 0) return;
-  int row = gbase + scan[l] - cnt;
+  int row = gbase + scan[wv] + inc - cnt;
   const int64_t poff = a.pair_off[r.env];
   for (int q = r.lo; q < r.hi; ++q) {
-    if (!mine(q)) continue;
+    if (small ? !((cm >> (q - r.lo)) & 1u) : !mine(q)) continue;
     const int b = q - r.lo;
     const float4 P = pose[q];
     const float4 S = stat[q];
@@ -450,7 +471,10 @@ hipError_t launch_candidate_features(const StepArgs& a, int groups, int block, f
   if (groups <= 0) return hipSuccess;
   CandArgs ca{a, band, feat, row_of, count};
   const size_t shm = (size_t)a.max_stage * (2 * sizeof(float4) + sizeof(float));
-  hipLaunchKernelGGL(k_cand_features, dim3(groups), dim3(block), shm, s, ca);
+  if (block > 256)
+    hipLaunchKernelGGL(k_cand_features<1024>, dim3(groups), dim3(block), shm, s, ca);
+  else
+    hipLaunchKernelGGL(k_cand_features<256>, dim3(groups), dim3(block), shm, s, ca);
   return hipGetLastError();
 }
 
