@@ -161,11 +161,12 @@ hipError_t launch_pair_features(const float* state, const EntParam* ent, const i
                                 const int64_t* pair_off, const int64_t* slots, int64_t m,
                                 float band, float* feat, float* target, uint8_t* flags,
                                 int n_envs, const WorldK& w, hipStream_t s);
+// out_idx: row r of the output goes to Y[out_idx[r]] (NULL: to Y[r])
 vmas_status mlp_forward_counted(vmas_mlp* m, const float* X, int64_t max_n, const int32_t* d_n,
-                                float* Y, hipStream_t s);
+                                const int32_t* out_idx, float* Y, hipStream_t s);
 hipError_t launch_candidate_features(const StepArgs& a, int groups, int block, float band,
-                                     float* feat, int32_t* row_of, int32_t* count, hipStream_t s);
-hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat, const int32_t* row_of,
+                                     float* feat, int32_t* slot_of, int32_t* count, hipStream_t s);
+hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat_slot,
                                  float band, float frac, int32_t* n_fallback, int groups,
                                  int block, hipStream_t s);
 

@@ -199,7 +199,7 @@ constexpr int INFER_WAVES = 8;                  // wavefronts per workgroup (one
 constexpr int INFER_ROWS = 16 * INFER_WAVES;     // rows per workgroup tile
 __global__ void __launch_bounds__(64 * INFER_WAVES)
 k_mlp_infer(MlpArgs m, const float* __restrict__ X, int64_t n, const int32_t* __restrict__ n_dev,
-            float* __restrict__ Y) {
+            const int32_t* __restrict__ out_idx, float* __restrict__ Y) {
   if (n_dev) n = min(n, (int64_t)max(*n_dev, 0));
   const int64_t tiles = (n + INFER_ROWS - 1) / INFER_ROWS;
   if ((int64_t)blockIdx.x >= tiles) return;  // uniform per workgroup, before any barrier
@@ -259,8 +259,9 @@ k_mlp_infer(MlpArgs m, const float* __restrict__ X, int64_t n, const int32_t* __
       acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag(w3, LDH, col, u * 16 + kq), h2[u], acc, 0,
                                                       0, 0);
     if (kq == 0 && row < n) {
-      Y[row * NO] = acc[0] + bias[2 * NH];
-      Y[row * NO + 1] = acc[1] + bias[2 * NH + 1];
+      const int64_t o = out_idx ? (int64_t)out_idx[row] : row;
+      Y[o * NO] = acc[0] + bias[2 * NH];
+      Y[o * NO + 1] = acc[1] + bias[2 * NH + 1];
     }
   }
 }
@@ -536,8 +537,10 @@ int mlp_nparam() { return NPARAM; }
 hipError_t mlp_launch_forward(const unsigned short* W1, const unsigned short* W2,
                               const unsigned short* W3, const float* b1, const float* b2,
                               const float* b3, const float* X, int64_t n, const int32_t* n_dev,
-                              float* Y, float* H1, float* H2, hipStream_t s) {
+                              const int32_t* out_idx, float* Y, float* H1, float* H2,
+                              hipStream_t s) {
   if (n <= 0) return hipSuccess;
+  if (out_idx && (H1 || H2)) return hipErrorInvalidValue;  // scattered outputs: inference only
   MlpArgs m{W1, W2, W3, b1, b2, b3};
   const int64_t tiles = (n + ROWS - 1) / ROWS;
   const int64_t blocks = tiles < 2048 ? tiles : 2048;  // 8 workgroups per CU walk the tiles
@@ -548,7 +551,7 @@ hipError_t mlp_launch_forward(const unsigned short* W1, const unsigned short* W2
     const int64_t itiles = (n + INFER_ROWS - 1) / INFER_ROWS;
     const int64_t iblocks = itiles < 768 ? itiles : 768;  // 3 workgroups per CU walk the tiles
     hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)iblocks), dim3(64 * INFER_WAVES), 0, s, m, X, n,
-                       n_dev, Y);
+                       n_dev, out_idx, Y);
   }
   return hipGetLastError();
 }

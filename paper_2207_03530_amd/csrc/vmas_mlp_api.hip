@@ -20,7 +20,8 @@ int64_t mlp_parts_for(int64_t n);
 hipError_t mlp_launch_forward(const unsigned short* W1, const unsigned short* W2,
                               const unsigned short* W3, const float* b1, const float* b2,
                               const float* b3, const float* X, int64_t n, const int32_t* n_dev,
-                              float* Y, float* H1, float* H2, hipStream_t s);
+                              const int32_t* out_idx, float* Y, float* H1, float* H2,
+                              hipStream_t s);
 hipError_t mlp_launch_backward(const unsigned short* W1, const unsigned short* W2,
                                const unsigned short* W3, const float* b1, const float* b2,
                                const float* b3, const float* X, const float* H1, const float* H2,
@@ -195,7 +196,7 @@ vmas_status vmas_mlp_forward(vmas_mlp* m, const float* X, int64_t n, float* Y, v
   if (!m || (n > 0 && (!X || !Y))) return set_error(VMAS_ERR_INVALID_ARGUMENT, "mlp, X and Y are required");
   if (n < 0) return set_error(VMAS_ERR_INVALID_ARGUMENT, "n must be >= 0");
   Dev g(m->device);
-  MCHK(mlp_launch_forward(m->W1, m->W2, m->W3, m->b1, m->b2, m->b3, X, n, nullptr, Y, nullptr, nullptr,
+  MCHK(mlp_launch_forward(m->W1, m->W2, m->W3, m->b1, m->b2, m->b3, X, n, nullptr, nullptr, Y, nullptr, nullptr,
                           (hipStream_t)stream));
   return VMAS_OK;
 }
@@ -209,7 +210,7 @@ vmas_status vmas_mlp_backward(vmas_mlp* m, const float* X, int64_t n, const floa
   vmas_status st = ensure_ws(m, n);
   if (st != VMAS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  MCHK(mlp_launch_forward(m->W1, m->W2, m->W3, m->b1, m->b2, m->b3, X, n, nullptr, m->Y, m->H1, m->H2, s));
+  MCHK(mlp_launch_forward(m->W1, m->W2, m->W3, m->b1, m->b2, m->b3, X, n, nullptr, nullptr, m->Y, m->H1, m->H2, s));
   MCHK(mlp_launch_backward(m->W1, m->W2, m->W3, m->b1, m->b2, m->b3, X, m->H1, m->H2, dY, n, dX,
                            m->part, grad ? grad : m->grad, s));
   return VMAS_OK;
@@ -224,7 +225,7 @@ vmas_status vmas_mlp_train_step(vmas_mlp* m, const float* X, const float* target
   vmas_status st = ensure_ws(m, n);
   if (st != VMAS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  MCHK(mlp_launch_forward(m->W1, m->W2, m->W3, m->b1, m->b2, m->b3, X, n, nullptr, m->Y, m->H1, m->H2, s));
+  MCHK(mlp_launch_forward(m->W1, m->W2, m->W3, m->b1, m->b2, m->b3, X, n, nullptr, nullptr, m->Y, m->H1, m->H2, s));
   MCHK(mlp_launch_mse(m->Y, target, n, m->dY, m->rl, s));
   if (loss) MCHK(mlp_launch_sum(m->rl, n, loss, s));
   MCHK(mlp_launch_backward(m->W1, m->W2, m->W3, m->b1, m->b2, m->b3, X, m->H1, m->H2, m->dY, n,
@@ -239,12 +240,13 @@ vmas_status vmas_mlp_train_step(vmas_mlp* m, const float* X, const float* target
 
 namespace vmas {
 // Forward over min(max_n, *d_n) rows, the count read on the device (rows
-// compacted by a preceding kernel on the same stream).
+// compacted by a preceding kernel on the same stream); row r's output goes
+// to Y[out_idx[r]] when out_idx is given.
 vmas_status mlp_forward_counted(vmas_mlp* m, const float* X, int64_t max_n, const int32_t* d_n,
-                                float* Y, hipStream_t s) {
+                                const int32_t* out_idx, float* Y, hipStream_t s) {
   Dev g(m->device);
-  MCHK(mlp_launch_forward(m->W1, m->W2, m->W3, m->b1, m->b2, m->b3, X, max_n, d_n, Y, nullptr,
-                          nullptr, s));
+  MCHK(mlp_launch_forward(m->W1, m->W2, m->W3, m->b1, m->b2, m->b3, X, max_n, d_n, out_idx, Y,
+                          nullptr, nullptr, s));
   return VMAS_OK;
 }
 }  // namespace vmas

@@ -112,7 +112,7 @@ struct vmas_batch {
   // surrogate workspace: features [P][12], MLP outputs [P][2], flags [P]
   float* d_feat = nullptr;
   float* d_yhat = nullptr;
-  int32_t* d_rows = nullptr;   // [P] candidate row of each pair slot, then [1] the count
+  int32_t* d_rows = nullptr;   // [P] pair slot of each candidate row, then [1] the count
   std::vector<Plan> plans;
   int cur = 0;
   int lane_plan = 0;  // entity-lane plan of the surrogate kernels: the largest block up to 256
@@ -1152,11 +1152,12 @@ vmas_status vmas_step_surrogate(vmas_batch* b, vmas_mlp* mlp, float* state, cons
     } else {
       HIPCHK(launch_candidate_features(a, p.groups, p.block, band, b->d_feat, b->d_rows, count, s));
     }
-    vmas_status st = mlp_forward_counted(mlp, b->d_feat, b->P, count, b->d_yhat, s);
+    // outputs scattered to the candidates' pair slots
+    vmas_status st = mlp_forward_counted(mlp, b->d_feat, b->P, count, b->d_rows, b->d_yhat, s);
     if (st != VMAS_OK) return st;
   }
-  HIPCHK(launch_step_surrogate(a, b->d_yhat, b->d_rows, band, fallback_frac, n_fallback, p.groups,
-                               p.block, s));
+  HIPCHK(launch_step_surrogate(a, b->d_yhat, band, fallback_frac, n_fallback, p.groups, p.block,
+                               s));
   return VMAS_OK;
 }
 

@@ -173,7 +173,7 @@ struct CandArgs {
   StepArgs s;          // plan and state
   float band;
   float* feat;         // [P][12] candidate rows
-  int32_t* row_of;     // [P] row of each candidate slot (other slots untouched)
+  int32_t* slot_of;    // [rows] pair slot of each candidate row
   int32_t* count;      // number of candidate rows (starts at 0)
 };
 
@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(MAXB) k_cand_features(CandArgs ca) {
     const int so = __float_as_int(S.w) & 0xff;
     const int ia = min(myloc, b), ib = max(myloc, b);
     const int64_t slot = poff + (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
-    ca.row_of[slot] = row;
+    ca.slot_of[row] = (int32_t)slot;
     float* f = ca.feat + (int64_t)row * 12;
     if (myloc < b)
       write_features(f, me.x, me.y, me.z, me.w, p.d0, p.d1, shape, P.x, P.y, P.z, P.w, S.x, S.y, so);
@@ -285,8 +285,9 @@ __global__ void __launch_bounds__(MAXB) k_cand_features(CandArgs ca) {
 
 struct SurArgs {
   StepArgs s;             // plan, state, actions (T = 1), forces
-  const float* yhat;      // [rows][2] MLP outputs (force on lo in the pair frame / (c Lf))
-  const int32_t* row_of;  // [P] row of each candidate slot in yhat (read for candidates only)
+  // [P][2] the network's output of each candidate pair at its pair slot
+  // (force on lo in the pair frame / (c Lf)); read for candidates only
+  const float* yhat;
   float band;             // candidate reach, as given to the feature kernel
   float fallback_frac;    // exact fallback when predicted penetration > frac * r
   int32_t* n_fallback;    // device counter, or NULL
@@ -375,9 +376,8 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
         if (!cand) continue;
         const int ia = min(myloc, b), ib = max(myloc, b);
         const int64_t slot = a.pair_off[r.env] + (int64_t)ia * nloc - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
-        const int row = sa.row_of[slot];
         // surrogate force on lo, in the pair frame -> world
-        const float hx = sa.yhat[2 * (int64_t)row] * FS, hy = sa.yhat[2 * (int64_t)row + 1] * FS;
+        const float hx = sa.yhat[2 * slot] * FS, hy = sa.yhat[2 * slot + 1] * FS;
         const float sgn = myloc < b ? 1.0f : -1.0f;  // e points from hi to lo
         const float ddx = sgn * (x - P.x), ddy = sgn * (y - P.y);
         const float dd = sqrtf(fmaf(ddx, ddx, ddy * ddy));
@@ -467,9 +467,9 @@ hipError_t launch_pair_features(const float* state, const EntParam* ent, const i
 }
 
 hipError_t launch_candidate_features(const StepArgs& a, int groups, int block, float band,
-                                     float* feat, int32_t* row_of, int32_t* count, hipStream_t s) {
+                                     float* feat, int32_t* slot_of, int32_t* count, hipStream_t s) {
   if (groups <= 0) return hipSuccess;
-  CandArgs ca{a, band, feat, row_of, count};
+  CandArgs ca{a, band, feat, slot_of, count};
   const size_t shm = (size_t)a.max_stage * (2 * sizeof(float4) + sizeof(float));
   if (block > 256)
     hipLaunchKernelGGL(k_cand_features<1024>, dim3(groups), dim3(block), shm, s, ca);
@@ -478,10 +478,10 @@ hipError_t launch_candidate_features(const StepArgs& a, int groups, int block, f
   return hipGetLastError();
 }
 
-hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat, const int32_t* row_of,
+hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat,
                                  float band, float frac, int32_t* n_fallback, int groups,
                                  int block, hipStream_t s) {
-  SurArgs sa{a, yhat, row_of, band, frac, n_fallback};
+  SurArgs sa{a, yhat, band, frac, n_fallback};
   const size_t shm = (size_t)a.max_stage * (2 * sizeof(float4) + sizeof(float));
   hipLaunchKernelGGL(k_step_surrogate, dim3(groups), dim3(block), shm, s, sa);
   return hipGetLastError();
