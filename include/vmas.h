@@ -201,7 +201,14 @@ vmas_status vmas_rollout_backward(vmas_batch* batch, const float* state0, const 
                                   float* grad_state0, float* grad_actions, void* stream);
 
 /* Launch plans. Plan ids are 0 .. n_schedules-1 (see vmas_schedule_name);
- * every plan computes the same results bit for bit. vmas_autotune times each
+ * every plan computes the same results bit for bit. Names:
+ * "entity-lane/<block>/<natural|size-sorted>" (a lane per entity that moves
+ * or rotates, whole environments per workgroup of <block> lanes, in natural
+ * or size order), "pair-queue/<block>/<order>" (batches with boxes or
+ * segments, environments of at most 32 entities: every pair tested and
+ * evaluated once from LDS queues), "quad/256" (sphere batches with at most 4
+ * movers and 4 static collidable entities per environment); "" for an id
+ * whose plan does not fit the batch. vmas_autotune times each
  * plan on a T-step rollout of a scratch copy of `state` (state itself is not
  * modified) with the given actions (device float32 [T][A][2]; NULL: actions
  * drawn in the kernel, seed 12345): about 20 ms of warm-up on the current

@@ -8,9 +8,14 @@
 // environments are packed in their natural order or sorted by size (which
 // keeps the lanes of one wavefront on environments of similar size when
 // sizes are uneven); sphere batches whose environments have at most 4 movers
-// also get the quad plan (one lane quad per environment). The per-lane
-// arithmetic does not depend on the packing, so every plan returns the same
-// bits; the autotuner picks the fastest on the caller's workload.
+// also get the quad plan (one lane quad per environment), and batches with
+// boxes or segments (environments of at most 32 entities) the pair-queue
+// plans (a static list of each workgroup's pairs; every pair tested and
+// evaluated once). The per-lane arithmetic does not depend on the packing, so
+// every plan returns the same bits; the autotuner picks the fastest on the
+// caller's workload. Two more plans are not schedules: the adjoint plan (every
+// entity has a lane) and the 1024-lane plan of the surrogate's candidate
+// kernel.
 
 #include <hip/hip_runtime.h>
 
