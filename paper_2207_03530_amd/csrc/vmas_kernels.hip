@@ -661,12 +661,19 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
 #pragma unroll
             for (int blk = 0; blk < 64; blk += 8) {
               if (blk < gmaxn) {
+                // the block's reads in flight before its tests
+                float2 P[8], S[8];
 #pragma unroll
                 for (int v = 0; v < 8; ++v) {
-                  const float2 P = pb[blk + v];
-                  float dmin = p.rho + sb[blk + v].x;
+                  P[v] = pb[blk + v];
+                  S[v] = sb[blk + v];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                  float dmin = p.rho + S[v].x;
                   if (MD) dmin += w.min_dist;
-                  const float dx = x - P.x, dy = y - P.y;
+                  const float dx = x - P[v].x, dy = y - P[v].y;
                   const bool hit = fmaf(dx, dx, __fmul_rn(dy, dy)) <= __fmul_rn(dmin, dmin);
                   hits |= (hit ? 1ull : 0ull) << (blk + v);
                 }
