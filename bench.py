@@ -161,7 +161,15 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(f"calibration copy: {src.numel() * 4} bytes read and written per launch",
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(10):
+            dst.copy_(src)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        sec = c0.elapsed_time(c1) * 1e-3 / 10
+        print(f"calibration copy: {src.numel() * 4} bytes read and written per launch, "
+              f"{2 * src.numel() * 4 / sec / 1e9:.0f} GB/s (read + write)",
               file=sys.stderr, flush=True)
 
     # one step = one T-step rollout of the whole batch; arguments marshalled once
