@@ -103,11 +103,22 @@ def cpu_baseline(w, acts, T):
         O.rollout_threaded(ow, w.state0, acts, threads)
         times.append(time.perf_counter() - t)
     sec = float(np.median(times))
+    # the same oracle on one core (at least one full run, then until about 10 s)
+    times1 = []
+    t_start = time.perf_counter()
+    while not times1 or time.perf_counter() - t_start < 10.0:
+        t = time.perf_counter()
+        O.rollout_threaded(ow, w.state0, acts, 1)
+        times1.append(time.perf_counter() - t)
+    sec1 = float(np.median(times1))
     return {"value": w.n_agents_total * T / sec, "unit": "agent-steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"the full workload ({w.n_envs} envs x {T} steps, FP64) repeated {len(times)} "
                       f"times (about 10 s), median {sec:.3f} s per run, {threads} threads on "
-                      f"disjoint environment ranges"}
+                      f"disjoint environment ranges",
+            "single_core": {"value": w.n_agents_total * T / sec1, "cores": 1,
+                            "sample": f"the same workload on one thread, {len(times1)} run(s), "
+                                      f"median {sec1:.3f} s"}}
 
 
 def main():
