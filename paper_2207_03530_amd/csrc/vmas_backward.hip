@@ -28,6 +28,13 @@
 namespace vmas {
 namespace {
 
+// Radius of the circle about an entity's centre that holds its shape.
+__device__ __forceinline__ float circle_radius(int shape, float d0, float d1) {
+  if (shape == SPHERE) return d0;
+  if (shape == BOX) return 0.5f * sqrtf(d0 * d0 + d1 * d1);
+  return 0.5f * d0;
+}
+
 // SPH: sphere-only batch (only the sphere pair code is compiled in).
 template <int MAXB, bool SPH>
 __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
@@ -36,12 +43,14 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
   float4* pose = lds;          // x, y, cos, sin
   float4* stat = lds + E;      // d0, d1, rho, shape | flags << 8
   float4* adj = lds + 2 * E;   // adjoint of force x, y and torque
+  float* brad = reinterpret_cast<float*>(lds + 3 * E);  // bounding radius of each slot
   const int g = blockIdx.x, l = threadIdx.x, B = blockDim.x;
   const int N = a.w.N;
   const int s0 = a.stage_off[g], ns = a.stage_off[g + 1] - s0;
   for (int s = l; s < ns; s += B) {
     const EntParam p = a.ent[a.stage[s0 + s]];
     stat[s] = make_float4(p.d0, p.d1, p.rho, __int_as_float(p.sf));
+    brad[s] = circle_radius(p.sf & 0xff, p.d0, p.d1);
   }
   const LaneRec r = a.lanes[(size_t)g * B + l];
   const bool act = r.ent >= 0;
@@ -63,6 +72,18 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
   const bool collide = act && (fl & COLLIDABLE);
   const bool agent = act && r.agent >= 0;
   const int myloc = r.slot - r.lo;
+  const float rs = circle_radius(shape, p.d0, p.d1);
+  // Bounding circles farther apart than d_min plus a margin far above the
+  // FP32 error of the narrow-phase distance cannot be in contact: such
+  // partners skip pair_force, which would find no contact (sphere batches
+  // test every partner, their test being as cheap as this one).
+  auto apart = [&](float x, float y, int q, const float4 P) {
+    if (SPH) return false;
+    const float reach = w.min_dist + 1e-4f + 1e-5f * (fabsf(x) + fabsf(y));
+    const float lim = (rs + brad[q]) + reach;
+    const float dx = x - P.x, dy = y - P.y;
+    return !(dx * dx + dy * dy <= lim * lim);
+  };
   for (int t = a.T - 1; t >= 0; --t) {
     const float* state = a.state + (size_t)t * 6 * N;
     const float* actions = a.actions ? a.actions + (size_t)t * 2 * w.A : nullptr;
@@ -114,6 +135,7 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
             const int of = (__float_as_int(S.w) >> 8) & 0xff;
             if (!(of & COLLIDABLE)) continue;
             if (p.excl != -1 && excluded(p.excl, q - r.lo)) continue;
+            if (apart(x, y, q, pose[q])) continue;
             pair_force<SPH>(self, p.rho, myloc, pose[q], S, q - r.lo, w, fx, fy, tq);
           }
         }
@@ -186,6 +208,7 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
           if (!self_dof && !(of & (MOVABLE | ROTATABLE))) continue;
           if (p.excl != -1 && excluded(p.excl, q - r.lo)) continue;
           const float4 P = pose[q];
+          if (apart(x, y, q, P)) continue;
           float fx = 0.0f, fy = 0.0f, tq = 0.0f;
           if (!pair_force<SPH>(selff, p.rho, myloc, P, S, q - r.lo, w, fx, fy, tq)) continue;
           GeoT<D3> other;
@@ -239,7 +262,7 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
 
 hipError_t launch_backward(const BackArgs& a, int groups, int block, bool spheres_only,
                            hipStream_t s) {
-  const size_t shm = (size_t)a.max_stage * 3 * sizeof(float4);
+  const size_t shm = (size_t)a.max_stage * (3 * sizeof(float4) + sizeof(float));
   if (block <= 256) {
     if (spheres_only)
       hipLaunchKernelGGL((k_step_backward<256, true>), dim3(groups), dim3(block), shm, s, a);
