@@ -1,8 +1,8 @@
 """Build the FP64 CPU oracle (test infrastructure) into oracle/liboracle.so.
 
-The oracle is plain C++17 compiled by the host compiler with floating-point
-contraction switched off, so that its FP32 contact decisions are the IEEE
-single-precision operations written in the source.
+The oracle is plain C++17 (FP64) compiled by the host compiler with
+floating-point contraction and fast-math switched off, so every operation is
+the IEEE double-precision operation written in the source.
 """
 import os
 import subprocess

@@ -23,18 +23,15 @@
 // Everything is templated on the scalar type:
 //   * double  -> the oracle proper;
 //   * Dual    -> forward-mode tangents (exact JVP of the discrete step, used to
-//                check the hand-written adjoint);
-//   * float   -> only to take the contact decision |x_ij| <= d_min in FP32,
-//                the precision of the GPU path, so that the integer contact
-//                mask is comparable bit for bit.
+//                check the hand-written adjoint).
 // Branches on the geometry are taken on values; a Dual carries the derivative
 // of the branch that is taken.
 //
-// Parity notes: the contact predicate between two spheres is decided in FP32
-// as fl(dx*dx + fl(dy*dy)) <= fl(d_min * d_min) (one fused multiply-add) with
-// dx, dy, d_min rounded exactly as written; for the other pair types the FP32 decision uses this
-// file's own FP32 geometry and is comparable to the GPU's only outside a band
-// around d_min (see the tests). Parity unpinned: the values of c and k, the
+// The contact decision of Eq. (2), |x_ij| <= d_min, is taken on the FP64
+// signed distance of this file's own narrow phase against the FP64 sum
+// d_min = rho_i + rho_j + min_dist. A GPU that decides in FP32 can disagree
+// only for pairs whose distance lies within FP32 rounding of d_min; the tests
+// count those as band cases. Parity unpinned: the values of c and k, the
 // joint model and the tie-breaking order between equally close features are
 // this implementation's reading, not fixed by the paper.
 
@@ -67,29 +64,23 @@ inline bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
 inline bool operator==(Dual a, Dual b) { return a.v == b.v; }
 
 inline double val(double x) { return x; }
-inline float val(float x) { return x; }
 inline double val(Dual x) { return x.v; }
 
 inline double m_sqrt(double x) { return std::sqrt(x); }
-inline float m_sqrt(float x) { return std::sqrt(x); }
 inline Dual m_sqrt(Dual x) {
   double s = std::sqrt(x.v);
   return {s, s > 0 ? x.d / (2 * s) : 0.0};
 }
 inline double m_sin(double x) { return std::sin(x); }
-inline float m_sin(float x) { return std::sin(x); }
 inline Dual m_sin(Dual x) { return {std::sin(x.v), std::cos(x.v) * x.d}; }
 inline double m_cos(double x) { return std::cos(x); }
-inline float m_cos(float x) { return std::cos(x); }
 inline Dual m_cos(Dual x) { return {std::cos(x.v), -std::sin(x.v) * x.d}; }
 inline double m_exp(double x) { return std::exp(x); }
-inline float m_exp(float x) { return std::exp(x); }
 inline Dual m_exp(Dual x) {
   double e = std::exp(x.v);
   return {e, e * x.d};
 }
 inline double m_log1p(double x) { return std::log1p(x); }
-inline float m_log1p(float x) { return std::log1p(x); }
 inline Dual m_log1p(Dual x) { return {std::log1p(x.v), x.d / (1 + x.v)}; }
 template <class T> inline T m_abs(T x) { return x < T(0) ? -x : x; }
 
@@ -559,31 +550,6 @@ template <class T> Pose<T> pose_of(const T* x, const T* y, const T* th, int i) {
   return p;
 }
 
-// Contact decision in FP32 from the FP32-rounded poses (see file header).
-bool contact_fp32(const oracle_world* w, int a, int b, double xa, double ya, double ta, double xb,
-                  double yb, double tb) {
-  int sa = w->shape[a], sb = w->shape[b];
-  float ra = sa == SPHERE ? (float)w->dims[2 * a] : 0.0f;
-  float rb = sb == SPHERE ? (float)w->dims[2 * b] : 0.0f;
-  float dmin = (ra + rb) + (float)w->min_dist;
-  if (sa == SPHERE && sb == SPHERE) {
-    float dx = (float)xa - (float)xb;
-    float dy = (float)ya - (float)yb;
-    float s = std::fma(dx, dx, dy * dy);
-    return s <= dmin * dmin;
-  }
-  Pose<float> pa, pb;
-  pa.c = {(float)xa, (float)ya};
-  pa.cs = std::cos((float)ta);
-  pa.sn = std::sin((float)ta);
-  pb.c = {(float)xb, (float)yb};
-  pb.cs = std::cos((float)tb);
-  pb.sn = std::sin((float)tb);
-  Contact<float> r = narrow<float>(sa, (float)w->dims[2 * a], (float)w->dims[2 * a + 1], pa, sb,
-                                   (float)w->dims[2 * b], (float)w->dims[2 * b + 1], pb);
-  return r.d <= dmin;
-}
-
 // One step of environments [e0, e1) in place. State is field-major [6][N]:
 // x, y, vx, vy, theta, omega. mask (optional) gets one byte per pair slot,
 // environments in order, pairs (a < b) in lexicographic order of the local
@@ -640,16 +606,17 @@ void step_envs(const oracle_world* w, int e0, int e1, T* st, const T* act, uint8
         int i = o + a, j = o + c;
         if (mask) mask[slot] = 0;
         if (!pair_eligible(w, js, nj, i, j)) continue;
-        bool hit = contact_fp32(w, i, j, val(X[i]), val(Y[i]), val(TH[i]), val(X[j]), val(Y[j]),
-                                val(TH[j]));
-        if (mask) mask[slot] = hit ? 1 : 0;
-        if (!hit) continue;
         Pose<T> pi = pose_of(X, Y, TH, i), pj = pose_of(X, Y, TH, j);
         Contact<T> r = narrow<T>(w->shape[i], T(w->dims[2 * i]), T(w->dims[2 * i + 1]), pi,
                                  w->shape[j], T(w->dims[2 * j]), T(w->dims[2 * j + 1]), pj);
         double ri = w->shape[i] == SPHERE ? w->dims[2 * i] : 0.0;
         double rj = w->shape[j] == SPHERE ? w->dims[2 * j] : 0.0;
         T dmin = T(ri + rj + w->min_dist);
+        // Eq. (2): the force acts iff |x_ij| <= d_min (inclusive), decided on
+        // the signed distance just computed.
+        bool hit = val(r.d) <= val(dmin);
+        if (mask) mask[slot] = hit ? 1 : 0;
+        if (!hit) continue;
         T F = T(w->c * w->k) * softplus((dmin - r.d) / T(w->k));
         V2<T> f = mul(r.n, F);
         FX[a] = FX[a] + f.x;

@@ -178,32 +178,70 @@ def test_coincident_spheres_fallback_normal():
     assert forces[1, 0] == 0 and forces[1, 1] == 0
 
 
-def test_sphere_mask_matches_exact_predicate():
-    """Contact mask between spheres against the exact predicate
-    dx^2 + dy^2 <= (ri + rj)^2 in rational arithmetic (inputs are FP32-exact),
-    away from a 1e-6 relative band where the FP32 decision may round either way."""
+def _exact_sphere_mask(w):
+    """Eq. (2)'s condition |x_ij| <= r_i + r_j for every eligible sphere pair,
+    in rational arithmetic on the FP32-exact inputs (squared, both sides >= 0)."""
     from fractions import Fraction
-    w = W.spread(64, seed=3)
-    ow = O.OracleWorld(w)
-    _, mask, _ = ow.step(w.state0, w.actions(1)[0])
-    slot, checked = 0, 0
+    out = []
     for b in range(w.n_envs):
         o = w.env_offset[b]
         n = w.env_offset[b + 1] - o
         for a in range(n):
             for c in range(a + 1, n):
                 i, j = o + a, o + c
-                fi, fj = w.flags[i], w.flags[j]
-                eligible = bool((fi | fj) & (W.MOVABLE | W.ROTATABLE))
+                eligible = bool((w.flags[i] | w.flags[j]) & (W.MOVABLE | W.ROTATABLE))
                 dx = Fraction(float(w.state0[0, i])) - Fraction(float(w.state0[0, j]))
                 dy = Fraction(float(w.state0[1, i])) - Fraction(float(w.state0[1, j]))
                 rr = (Fraction(float(w.dims[i, 0])) + Fraction(float(w.dims[j, 0]))) ** 2
-                s = dx * dx + dy * dy
-                if abs(float(s - rr)) > 1e-6 * float(rr):
-                    assert mask[slot] == (1 if (eligible and s <= rr) else 0)
-                    checked += 1
-                slot += 1
-    assert checked > 0.99 * slot
+                out.append(1 if (eligible and dx * dx + dy * dy <= rr) else 0)
+    return np.array(out, np.uint8)
+
+
+def _touching_pairs(n, seed):
+    """n two-sphere environments whose centres sit at r_i + r_j apart up to
+    the FP32 rounding of the second centre: the exact distance falls within
+    about 1e-8 of d_min, on either side, plus exactly touching 3-4-5 pairs."""
+    rng = np.random.default_rng(seed)
+    N = 2 * n
+    st = np.zeros((6, N), np.float32)
+    dims = np.zeros((N, 2), np.float32)
+    dims[0::2, 0] = rng.uniform(0.01, 0.1, n).astype(np.float32)
+    dims[1::2, 0] = rng.uniform(0.01, 0.1, n).astype(np.float32)
+    ci = rng.uniform(-1, 1, (n, 2)).astype(np.float32)
+    phi = rng.uniform(-np.pi, np.pi, n)
+    R = dims[0::2, 0].astype(np.float64) + dims[1::2, 0]
+    cj = (ci + np.stack([R * np.cos(phi), R * np.sin(phi)], 1)).astype(np.float32)
+    st[0, 0::2], st[1, 0::2] = ci[:, 0], ci[:, 1]
+    st[0, 1::2], st[1, 1::2] = cj[:, 0], cj[:, 1]
+    # exactly touching: offsets (3, 4) / 64, radii 2/64 and 3/64, |x_ij| = 5/64
+    # (centres on a 2^-10 grid, so every coordinate and offset is exact)
+    for k in range(0, n, 7):
+        dims[2 * k, 0], dims[2 * k + 1, 0] = 2 / 64, 3 / 64
+        st[0:2, 2 * k] = np.round(st[0:2, 2 * k] * 1024) / 1024
+        st[0, 2 * k + 1] = st[0, 2 * k] + np.float32(3 / 64)
+        st[1, 2 * k + 1] = st[1, 2 * k] + np.float32(4 / 64)
+    flags = np.full(N, ALL, np.uint8)
+    return W.World(env_offset=(np.arange(n + 1) * 2).astype(np.int32),
+                   n_agents=np.zeros(n, np.int32), shape=np.zeros(N, np.uint8), dims=dims,
+                   mass=np.ones(N, np.float32), flags=flags, state0=st)
+
+
+def test_sphere_mask_matches_exact_predicate():
+    """Eq. (2) applies the force iff |x_ij| <= d_min (inclusive). The oracle's
+    contact mask between spheres equals that predicate evaluated exactly (in
+    rational arithmetic on the FP32-exact inputs) for every pair, with no
+    exclusion band: random spread positions, and pairs built to sit within one
+    FP32 rounding of touching, on both sides of it and exactly on it."""
+    w = W.spread(64, seed=3)
+    _, mask, _ = O.OracleWorld(w).step(w.state0, w.actions(1)[0])
+    assert np.array_equal(mask, _exact_sphere_mask(w))
+    t = _touching_pairs(1500, seed=4)
+    _, tm, _ = O.OracleWorld(t).step(t.state0, np.zeros((0, 2), np.float32))
+    exact = _exact_sphere_mask(t)
+    assert np.array_equal(tm, exact)
+    # both outcomes occur near the boundary, and the 3-4-5 pairs touch exactly
+    assert 0.2 < exact.mean() < 0.8
+    assert np.all(tm[0::7] == 1)
 
 
 # ---------------------------------------------------------- invariants -----
@@ -426,6 +464,68 @@ def test_narrow_phase_overlap_penetration_depth():
         if b[0] == SPH:
             assert _inside(a[0], a[1], a[2], pa, np.array(pb[:2]))
     assert len(seen) >= 6
+
+
+# Overlapping pairs whose contact point is fixed by the geometry: one vertex
+# (or endpoint) of the shape that does not own the separating axis of least
+# overlap is strictly deepest, so p, the torques of Eq. (3) and the angular
+# velocities after one step from rest have closed forms.
+_S2 = math.sqrt(2.0)
+OVERLAP_POINT_CASES = [
+    # box 0.4 x 0.2 at the origin; a 0.2 x 0.2 box turned 45 degrees (a
+    # diamond) whose lowest corner (0.05, 0.08) sits 0.02 below the top face
+    ("box-box", (BOX, 0.4, 0.2), (0.0, 0.0, 0.0), (BOX, 0.2, 0.2),
+     (0.05, 0.08 + 0.1 * _S2, math.pi / 4), -0.02, (0.0, -1.0), (0.05, 0.08)),
+    # the same box; a vertical segment of length 0.3 whose lower end
+    # (0.1, 0.07) sits 0.03 below the top face
+    ("box-segment", (BOX, 0.4, 0.2), (0.0, 0.0, 0.0), (LIN, 0.3, 0.0),
+     (0.1, 0.22, math.pi / 2), -0.03, (0.0, -1.0), (0.1, 0.07)),
+    # a horizontal segment of length 0.4 crossed by a vertical one of length
+    # 0.3 whose lower end (0.05, -0.03) is the endpoint nearest the other line
+    ("segment-segment", (LIN, 0.4, 0.0), (0.0, 0.0, 0.0), (LIN, 0.3, 0.0),
+     (0.05, 0.12, math.pi / 2), -0.03, (0.0, -1.0), (0.05, -0.03)),
+]
+
+
+@pytest.mark.parametrize("name,a,pa,b,pb,d,n,p", OVERLAP_POINT_CASES,
+                         ids=[c[0] for c in OVERLAP_POINT_CASES])
+def test_overlap_contact_point_closed_form(name, a, pa, b, pb, d, n, p):
+    """Overlapping cores (Eq. 2 with the signed distance of the separating-axis
+    reading): d is minus the least overlap, n the axis, and both torque arms
+    of Eq. (3) end at the deepest vertex of the shape that does not own that
+    axis. One step from rest (zeta = 0): F = c p + c k log1p(e^{-p/k}) along
+    n on i, tau_i = (p - c_i) x f, tau_j = (p - c_j) x (-f) (0 here: the
+    point lies on the line of action through c_j), omega = tau dt / I."""
+    dd, nn, pi, pj = O.pair(a[0], a[1:], pa, b[0], b[1:], pb)
+    np.testing.assert_allclose(dd, d, atol=1e-12)
+    np.testing.assert_allclose(nn, n, atol=1e-12)
+    np.testing.assert_allclose(pi, p, atol=1e-12)
+    np.testing.assert_allclose(pj, p, atol=1e-12)
+    c, k, dt = 100.0, 1e-3, 0.1
+    w = make([dict(shape=a[0], d0=a[1], d1=a[2], x=pa[0], y=pa[1], th=pa[2]),
+              dict(shape=b[0], d0=b[1], d1=b[2], x=pb[0], y=pb[1], th=pb[2])],
+             dt=dt, drag=0.0, contact_force=c, contact_margin=k)
+    # the world holds FP32 poses and sizes: take the geometry from them
+    st0 = w.state0.astype(np.float64)
+    dims = w.dims.astype(np.float64)
+    dd, nn, pp, _ = O.pair(a[0], dims[0], st0[[0, 1, 4], 0], b[0], dims[1], st0[[0, 1, 4], 1])
+    pen = -dd
+    F = c * pen + c * k * math.log1p(math.exp(-pen / k))
+    f = F * nn
+    tau_i = (pp[0] - st0[0, 0]) * f[1] - (pp[1] - st0[1, 0]) * f[0]
+    tau_j = -((pp[0] - st0[0, 1]) * f[1] - (pp[1] - st0[1, 1]) * f[0])
+    assert abs(tau_i) > 0.01 * F and abs(tau_j) < 1e-6 * F
+    st, mask, forces = O.OracleWorld(w).step(w.state0, np.zeros((0, 2)), want_forces=True)
+    assert mask[0] == 1
+    np.testing.assert_allclose(forces[2], [tau_i, tau_j], rtol=1e-12, atol=1e-12 * F)
+    I = [O.default_inertia(int(w.shape[q]), 1.0, float(w.dims[q, 0]), float(w.dims[q, 1]))
+         for q in range(2)]
+    np.testing.assert_allclose(st[5], [tau_i * dt / I[0], tau_j * dt / I[1]], rtol=1e-12,
+                               atol=1e-12)
+    # the expected arm in closed form: a wrong vertex (i's own corner, a
+    # face midpoint) changes tau_i by a large factor
+    np.testing.assert_allclose(tau_i, (p[0] - pa[0]) * (n[1] * F) - (p[1] - pa[1]) * (n[0] * F),
+                               rtol=1e-5)
 
 
 def test_narrow_phase_swap_symmetry():
