@@ -29,9 +29,12 @@
  *   - a joint is a linear spring of stiffness joint_stiffness between two
  *     body-frame anchor points (rest length: given, or the anchor distance in
  *     the initial state); by default the two jointed entities do not collide.
- *   - the contact decision |x_ij| <= d_min is taken in FP32; between two
- *     spheres it is fl(dx*dx) + fl(dy*dy) <= fl(d_min*d_min) with
- *     dx = fl(x_i - x_j), dy = fl(y_i - y_j), d_min = fl(fl(r_i + r_j) + min_dist).
+ *   - the contact decision |x_ij| <= d_min (inclusive) is taken in FP32;
+ *     between two spheres it is fma(dx, dx, fl(dy*dy)) <= fl(d_min*d_min)
+ *     (one fused multiply-add) with dx = fl(x_i - x_j), dy = fl(y_i - y_j),
+ *     d_min = fl(fl(r_i + r_j) + min_dist); other pairs compare the FP32
+ *     signed distance with the FP32 d_min. An exact evaluation can decide
+ *     differently only for pairs within FP32 rounding of d_min.
  *
  * Memory. Every state, action, mask, force and gradient buffer passed to the
  * step calls is DEVICE memory owned by the caller; the library never frees

@@ -95,6 +95,65 @@ def pair_shapes(shape: np.ndarray, env_offset: np.ndarray):
     return shape[i], shape[j]
 
 
+def ulp32(x) -> np.ndarray:
+    """Spacing of FP32 numbers at |x| (in FP64)."""
+    return np.spacing(np.abs(np.asarray(x, np.float64)).astype(np.float32)).astype(np.float64)
+
+
+def in_band(ow, state, ulps=8):
+    """Per pair slot: whether the exact distance lies within `ulps` FP32 ulps
+    of d_min (see mask_compare); also returns (d64, d_min)."""
+    from oracle import oracle as O
+    w = ow.w
+    st = np.asarray(state, np.float64)
+    d, dm = O.pair_distances(ow, st)
+    i, j = pair_members(w.env_offset)
+    sph = (w.shape[i] == 0) & (w.shape[j] == 0)
+    s = np.maximum(np.abs(d), dm)
+    coord = np.max(np.abs(np.stack([st[0, i], st[1, i], st[0, j], st[1, j],
+                                    w.dims[i, 0], w.dims[i, 1], w.dims[j, 0], w.dims[j, 1]])), 0)
+    s = np.where(sph, s, np.maximum(s, coord))
+    with np.errstate(invalid="ignore"):
+        band = np.abs(d - dm) <= ulps * ulp32(s)
+    return band, d, dm
+
+
+def mask_compare(ow, state, gmask, omask, ulps=8):
+    """Contact masks of one step from the same input state, compared the way
+    Eq. (2)'s threshold allows.
+
+    The oracle decides |x_ij| <= d_min in FP64 on its own signed distance;
+    the GPU decides in FP32. A disagreement is admissible only for a pair
+    whose exact distance lies within `ulps` FP32 ulps of the threshold:
+    |d64 - d_min| <= ulps * ulp32(s). For two spheres s = max(|d|, d_min)
+    (the decision is a difference of centres, squared and summed, whose
+    rounding is relative to d). For a pair with a box or a segment the FP32
+    distance is built from vertex coordinates, so s also covers the largest
+    coordinate and size of the two entities. Any other disagreement raises.
+    Returns the slots of the admissible ("band") disagreements."""
+    gmask = np.asarray(gmask)
+    omask = np.asarray(omask)
+    diff = gmask != omask
+    if not np.any(diff):
+        return np.zeros(0, np.int64)
+    band, d, dm = in_band(ow, state, ulps)
+    bad = diff & ~band
+    assert not np.any(bad), (
+        f"contact mask differs outside the FP32 band at slots {np.nonzero(bad)[0][:10]}: "
+        f"d - d_min = {(d - dm)[bad][:10]}, gpu {gmask[bad][:10]}, oracle {omask[bad][:10]}")
+    return np.nonzero(diff)[0]
+
+
+def nearest_to_threshold(ow, state):
+    """Smallest |d64 - d_min| over the eligible pairs (how close the input
+    comes to the band), for reporting."""
+    from oracle import oracle as O
+    d, dm = O.pair_distances(ow, np.asarray(state, np.float64))
+    g = np.abs(d - dm)
+    g = g[np.isfinite(g)]
+    return float(g.min()) if g.size else float("inf")
+
+
 def _perturb(state, rel, seed, shape=None):
     """Poses moved by +-rel (positions, in world units, and the angles of
     boxes and lines, in radians): the size of FP32 rounding of O(1)

@@ -55,8 +55,7 @@ def test_pair_features_and_targets():
     ow = O.OracleWorld(w)
     _, om, _ = ow.step(w.state0, np.zeros((w.n_agents_total, 2)))
     contact = (flags & 2) != 0
-    d, dm = O.pair_distances(ow, w.state0)
-    band = np.abs(d - dm) <= 1e-5
+    band, d, dm = PU.in_band(ow, w.state0)
     seg = (w.shape[I] == 2) | (w.shape[J] == 2)
     assert not np.any((flags[seg] & 1) != 0)           # segments never go to the network
     assert np.all((contact == (om == 1)) | band | seg)
