@@ -60,7 +60,9 @@
  * (a hipStream_t passed as void*, NULL = the default stream) and the calls
  * return after enqueue; only vmas_create_batch blocks. Arguments are checked
  * on the host before any device work: a bad argument returns
- * VMAS_ERR_INVALID_ARGUMENT, a HIP failure VMAS_ERR_DEVICE; the reason is in
+ * VMAS_ERR_INVALID_ARGUMENT, a HIP failure VMAS_ERR_DEVICE, a state that went
+ * non-finite under VMAS_DEBUG_NONFINITE VMAS_ERR_NONFINITE (on the next call);
+ * the reason is in
  * vmas_last_error() (thread-local, valid until the next call on that thread).
  * A handle must not be used from two threads at once; calls on different
  * handles are independent. Calls that overlap on one stream are ordered by it.
@@ -97,8 +99,23 @@ typedef struct {
   float contact_margin;   /* k > 0 */
   float min_dist;         /* added to every pair's d_min (>= 0) */
   float joint_stiffness;  /* spring constant of every joint (>= 0) */
-  uint32_t flags;         /* reserved, must be 0 */
+  uint32_t flags;         /* 0 or VMAS_DEBUG_NONFINITE; other bits are rejected */
 } vmas_world_params;
+
+/* World flag bits.
+ * VMAS_DEBUG_NONFINITE: after the work of every call that advances the state
+ *   (vmas_step, vmas_rollout, vmas_rollout_graph, vmas_step_surrogate) the
+ *   library enqueues a check of the output state on the same stream: an
+ *   environment one of whose entities holds a NaN or an infinity (a blown-up
+ *   simulation, e.g. beyond the stability bound of the penalty spring) is
+ *   marked on the device and counted the first time it is seen. The next call
+ *   on the handle (any step, rollout or adjoint call) first synchronises its
+ *   stream, reads the count and, when environments were marked since the last
+ *   report, returns VMAS_ERR_NONFINITE with the counts in vmas_last_error()
+ *   and enqueues no work; the call after it proceeds. vmas_nonfinite_envs
+ *   lists the marked environments. Costs one pass over the state per call and
+ *   one stream synchronisation per call; off by default. */
+enum { VMAS_DEBUG_NONFINITE = 1 };
 
 /* Static description of a batch. All pointers are HOST memory, read during
  * vmas_create_batch only. N = total entities, A = total agents, J = joints. */
@@ -118,7 +135,9 @@ typedef struct {
   const int32_t* joint_b;         /* [J] */
   const float* joint_anchor_a;    /* [J][2] body-frame anchor on a */
   const float* joint_anchor_b;    /* [J][2] body-frame anchor on b */
-  const float* joint_rest;        /* [J] rest length; < 0: anchor distance in init_state */
+  const float* joint_rest;        /* [J] rest length; < 0: the anchor distance in init_state,
+                                     evaluated with the step's own FP32 arithmetic (so the
+                                     joint exerts exactly no force in that state) */
   const uint8_t* joint_collide;   /* [J] or NULL: 0 = the jointed pair does not collide */
   const float* init_state;        /* [6][N] host state, needed only when a rest length is < 0 */
 } vmas_batch_desc;
@@ -225,10 +244,12 @@ vmas_status vmas_autotune(vmas_batch* batch, const float* state, const float* ac
                           void* stream, int32_t* chosen);
 const char* vmas_schedule_name(const vmas_batch* batch, int32_t schedule);
 
-/* Rollout through a cached hipGraph: the first call captures the launch on
- * `stream`, later calls with the same (T, traj == NULL, mask == NULL,
- * actions == NULL) shape rebind the kernel arguments and replay the graph.
- * Same arguments and results as vmas_rollout. */
+/* Rollout through a cached hipGraph: the first call builds a graph that
+ * holds the rollout kernel as its one node (built explicitly, not captured,
+ * so any stream works); later calls with the same T, the same plan and
+ * actions given or drawn alike rebind the kernel arguments and launch the
+ * graph on `stream`. Calls with traj or final_mask, or T <= 0, run
+ * vmas_rollout. Same arguments and results as vmas_rollout. */
 vmas_status vmas_rollout_graph(vmas_batch* batch, float* state, const float* actions,
                                uint64_t action_seed, int32_t t0, int32_t T, float* traj,
                                uint8_t* final_mask, void* stream);
@@ -305,6 +326,14 @@ vmas_status vmas_pair_features(vmas_batch* batch, const float* state, float band
 vmas_status vmas_step_surrogate(vmas_batch* batch, vmas_mlp* mlp, float* state,
                                 const float* actions, float band, float fallback_frac,
                                 float* forces, int32_t* n_fallback, void* stream);
+
+/* VMAS_DEBUG_NONFINITE batches only: synchronises `stream`, then writes
+ * marks (host uint8 [n_envs], or NULL): 1 for every environment that has held
+ * a non-finite state since creation or the last clear, and count (host, or
+ * NULL): their number. clear != 0 then unmarks all environments.
+ * VMAS_ERR_INVALID_ARGUMENT for a batch created without the flag. */
+vmas_status vmas_nonfinite_envs(vmas_batch* batch, uint8_t* marks, int32_t* count, int32_t clear,
+                                void* stream);
 
 /* Reason for the last failure on this thread ("" if none). */
 const char* vmas_last_error(void);

@@ -26,7 +26,9 @@ EXPORTS = ("vmas_create_batch", "vmas_destroy_batch", "vmas_batch_get_info", "vm
            "vmas_autotune", "vmas_schedule_name", "vmas_rollout_graph", "vmas_last_error",
            "vmas_mlp_num_params", "vmas_mlp_create", "vmas_mlp_destroy", "vmas_mlp_get_params",
            "vmas_mlp_forward", "vmas_mlp_backward", "vmas_mlp_train_step", "vmas_pair_features",
-           "vmas_step_surrogate")
+           "vmas_step_surrogate", "vmas_nonfinite_envs")
+
+VMAS_DEBUG_NONFINITE = 1
 
 
 class VmasError(RuntimeError):
@@ -101,6 +103,7 @@ def lib():
     L.vmas_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_float, vp, vp]
     L.vmas_pair_features.argtypes = [vp, vp, ctypes.c_float, vp, ctypes.c_int64, vp, vp, vp, vp]
     L.vmas_step_surrogate.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, vp, vp, vp]
+    L.vmas_nonfinite_envs.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
     for name in EXPORTS:
         if name not in ("vmas_schedule_name", "vmas_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -138,7 +141,7 @@ def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def make_params(w) -> WorldParams:
+def make_params(w, flags: int = 0) -> WorldParams:
     p = WorldParams()
     p.dt = w.dt
     p.drag = w.drag
@@ -147,14 +150,15 @@ def make_params(w) -> WorldParams:
     p.contact_margin = w.contact_margin
     p.min_dist = w.min_dist
     p.joint_stiffness = w.joint_stiffness
-    p.flags = 0
+    p.flags = flags
     return p
 
 
 class Batch:
-    """A batch of environments on one device (handle of vmas_create_batch)."""
+    """A batch of environments on one device (handle of vmas_create_batch).
+    debug_nonfinite sets VMAS_DEBUG_NONFINITE in the world flags."""
 
-    def __init__(self, world, device: int = 0):
+    def __init__(self, world, device: int = 0, debug_nonfinite: bool = False):
         import torch
         self.world = world
         self.device = torch.device("cuda", device)
@@ -194,7 +198,7 @@ class Batch:
         st0 = arr(world.state0, np.float32)
         self._keep.append(st0)
         d.init_state = _np_ptr(st0, _f32p)
-        self.params = make_params(world)
+        self.params = make_params(world, VMAS_DEBUG_NONFINITE if debug_nonfinite else 0)
         h = ctypes.c_void_p()
         _check(lib().vmas_create_batch(ctypes.byref(self.params), ctypes.byref(d), device,
                                        ctypes.byref(h)))
@@ -323,6 +327,15 @@ class Batch:
             ctypes.c_float(fallback_frac), _dptr(forces, 3 * self.N, torch.float32, "forces"),
             _dptr(n_fallback, 1, torch.int32, "n_fallback"), _stream(self.device)))
 
+    def nonfinite_envs(self, clear: bool = False):
+        """(marks uint8 [n_envs], count) of the environments that have held a
+        non-finite state (VMAS_DEBUG_NONFINITE batches)."""
+        marks = np.zeros(self.world.n_envs, np.uint8)
+        cnt = ctypes.c_int32(0)
+        _check(lib().vmas_nonfinite_envs(self.handle, marks.ctypes.data_as(ctypes.c_void_p),
+                                         ctypes.byref(cnt), int(clear), _stream(self.device)))
+        return marks, cnt.value
+
     def close(self) -> None:
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib().vmas_destroy_batch(self.handle)
@@ -431,3 +444,7 @@ def vmas_autotune(batch: Batch, state, T: int = 10, actions=None) -> int:
 
 def vmas_set_schedule(batch: Batch, schedule: int) -> None:
     batch.set_schedule(schedule)
+
+
+def vmas_nonfinite_envs(batch: Batch, clear: bool = False):
+    return batch.nonfinite_envs(clear)

@@ -603,10 +603,14 @@ __device__ __forceinline__ bool pair_force(const GeoT<float>& self, float rho_s,
   return true;
 }
 
+// Whether a joint switches off the contact with local index b: excl holds up
+// to 4 local indices below 255, one per byte, 0xff marking an unused byte (so
+// local index 255 and above is never excluded).
 __device__ __forceinline__ bool excluded(int excl, int b) {
   const unsigned u = (unsigned)excl;
-  return ((u & 0xffu) == (unsigned)b) | (((u >> 8) & 0xffu) == (unsigned)b) |
-         (((u >> 16) & 0xffu) == (unsigned)b) | ((u >> 24) == (unsigned)b);
+  return ((unsigned)b < 255u) &
+         (((u & 0xffu) == (unsigned)b) | (((u >> 8) & 0xffu) == (unsigned)b) |
+          (((u >> 16) & 0xffu) == (unsigned)b) | ((u >> 24) == (unsigned)b));
 }
 
 

@@ -12,6 +12,12 @@ namespace vmas {
 
 enum : int { SPHERE = 0, BOX = 1, LINE = 2 };
 enum : int { MOVABLE = 1, ROTATABLE = 2, COLLIDABLE = 4 };
+// EntParam.sf bit: the entity's orientation enters the geometry of a step
+// (boxes and segments always; a sphere only when a joint anchors it off its
+// centre). Entities without it use the identity rotation, which no routine
+// that reads them can tell from their own.
+enum : int { SF_ROTATES = 1 << 16 };
+__host__ __device__ inline bool uses_rotation(int sf) { return (sf & SF_ROTATES) != 0; }
 
 // Static per-entity parameters, one 48-byte record per entity.
 struct EntParam {
@@ -20,7 +26,7 @@ struct EntParam {
   float vmax;          // <= 0: no speed cap
   float rho;           // radius added to d_min: r for spheres, 0 otherwise
   float mgx, mgy;      // gravity force m g (0 unless movable)
-  int32_t sf;          // shape | flags << 8
+  int32_t sf;          // shape | flags << 8 | SF_ROTATES
   int32_t excl;        // up to 4 environment-local partner indices (one byte
                        // each, 0xff = none) whose contact a joint switches off
   int32_t pad[2];
@@ -151,6 +157,13 @@ const void* rollout_kernel(bool spheres_only, bool quad, bool pq, int block, int
                            float min_dist, bool out);
 size_t rollout_lds_bytes(int max_stage, bool spheres_only, bool quad, int pq_total, int pq_pairs,
                          int block, int max_n);
+// Rest lengths of the joints marked in from_state ([J], 1 = take the anchor
+// distance in state0), evaluated with the step's own FP32 arithmetic, so
+// such a joint exerts exactly no force in state0. Writes joints[q].rest.
+hipError_t launch_joint_rest(const float* state0, int N, const EntParam* ent, JointK* joints,
+                             const uint8_t* from_state, int J, hipStream_t s);
+hipError_t launch_check_nonfinite(const float* state, int N, const int32_t* env_off, int n_envs,
+                                  uint32_t* env_bad, uint32_t* cnt, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);

@@ -157,12 +157,12 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
   const int s0 = a.stage_off[g], ns = a.stage_off[g + 1] - s0;
   for (int s = l; s < ns; s += B) {
     const int e = a.stage[s0 + s];
+    const EntParam p = a.ent[e];
     float cs = 1.0f, sn = 0.0f;
-    sincosf(a.state[4 * N + e], &sn, &cs);
+    if (uses_rotation(p.sf)) sincosf(a.state[4 * N + e], &sn, &cs);
     const float4 P = make_float4(a.state[e], a.state[N + e], cs, sn);
     buf0[s] = P;
     buf1[s] = P;
-    const EntParam p = a.ent[e];
     stat[s] = make_float4(p.d0, p.d1, p.rho, __int_as_float(p.sf));
     brad[s] = ((p.sf >> 8) & COLLIDABLE) ? bounding_radius(p.sf & 0xff, p.d0, p.d1)
                                          : __int_as_float(0x7fc00000);
@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
   for (int t = 0; t < a.T; ++t) {
     float4* cur = (t & 1) ? buf1 : buf0;
     float cs = 1.0f, sn = 0.0f;
-    if (act && shape != SPHERE) sincosf(th, &sn, &cs);
+    if (act && uses_rotation(p.sf)) sincosf(th, &sn, &cs);
     if (PQ) {
       // A lane clears only its own words (another wavefront may still be
       // reading its own ones from the previous step); the words of slots
@@ -1121,6 +1121,48 @@ __global__ void k_replicate(const float* __restrict__ src, float* __restrict__ d
     dst[i] = src[i % n];
 }
 
+// Debug check of a state [6][N]: an entity holding a NaN or an infinity marks
+// its environment (env_off: [n_envs + 1] CSR, found by bisection); the first
+// mark of an environment adds one to both counters (cnt[0]: newly marked
+// since the last report, cnt[1]: all marked).
+__global__ void k_check_nonfinite(const float* __restrict__ state, int N,
+                                  const int32_t* __restrict__ env_off, int n_envs,
+                                  uint32_t* env_bad, uint32_t* cnt) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    bool ok = true;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) ok &= isfinite(state[(size_t)f * N + i]);
+    if (ok) continue;
+    int lo = 0, hi = n_envs - 1;  // the environment b with env_off[b] <= i < env_off[b + 1]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (env_off[mid] <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    if (atomicExch(&env_bad[lo], 1u) == 0u) {
+      atomicAdd(&cnt[0], 1u);
+      atomicAdd(&cnt[1], 1u);
+    }
+  }
+}
+
+// Rest length of joint q from the anchors in state0, with joint_eval's
+// arithmetic (the rotation of an entity as the step kernels stage it).
+__global__ void k_joint_rest(const float* __restrict__ st, int N, const EntParam* __restrict__ ent,
+                             JointK* joints, const uint8_t* __restrict__ from_state, int J) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= J || !from_state[q]) return;
+  JointK jk = joints[q];
+  float ca = 1.0f, sa = 0.0f, cb = 1.0f, sb = 0.0f;
+  if (uses_rotation(ent[jk.a].sf)) sincosf(st[4 * N + jk.a], &sa, &ca);
+  if (uses_rotation(ent[jk.b].sf)) sincosf(st[4 * N + jk.b], &sb, &cb);
+  const V2 xa = {st[jk.a], st[N + jk.a]}, xb = {st[jk.b], st[N + jk.b]};
+  const V2 Pa = vadd(xa, vrot(ca, sa, V2{jk.ax, jk.ay}));
+  const V2 Pb = vadd(xb, vrot(cb, sb, V2{jk.bx, jk.by}));
+  const V2 dl = vsub(Pa, Pb);
+  joints[q].rest = s_sqrt(vdot(dl, dl));
+}
+
 int grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 4096) g = 4096;
@@ -1166,6 +1208,22 @@ hipError_t launch_rollout(const StepArgs& a, int groups, int block, bool spheres
   StepArgs args = a;
   void* kargs[1] = {&args};
   return hipLaunchKernel(f, dim3(groups), dim3(block), kargs, shm, s);
+}
+
+hipError_t launch_joint_rest(const float* state0, int N, const EntParam* ent, JointK* joints,
+                             const uint8_t* from_state, int J, hipStream_t s) {
+  if (J <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_joint_rest, dim3((J + 255) / 256), dim3(256), 0, s, state0, N, ent, joints,
+                     from_state, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_nonfinite(const float* state, int N, const int32_t* env_off, int n_envs,
+                                  uint32_t* env_bad, uint32_t* cnt, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_nonfinite, dim3(grid_for(N)), dim3(256), 0, s, state, N, env_off,
+                     n_envs, env_bad, cnt);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, hipStream_t s) {

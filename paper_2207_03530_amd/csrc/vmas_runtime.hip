@@ -133,6 +133,10 @@ struct vmas_batch {
   hipGraphNode_t gnode = nullptr;
   int graph_T = -1, graph_plan = -1;
   bool graph_drawn = false;
+  // debug check of the state after every step call (VMAS_DEBUG_NONFINITE)
+  bool debug_nonfinite = false;
+  uint32_t* d_bad = nullptr;      // [n_envs] 1: the environment reached a non-finite state
+  uint32_t* d_bad_cnt = nullptr;  // [2] marked since the last report, marked in all
 };
 
 namespace {
@@ -171,6 +175,8 @@ void free_batch(vmas_batch* b) {
   if (b->d_yhat) (void)hipFree(b->d_yhat);
   if (b->d_rows) (void)hipFree(b->d_rows);
   if (b->d_ws) (void)hipFree(b->d_ws);
+  if (b->d_bad) (void)hipFree(b->d_bad);
+  if (b->d_bad_cnt) (void)hipFree(b->d_bad_cnt);
   delete b;
 }
 
@@ -219,7 +225,8 @@ vmas_status validate(const vmas_world_params* pr, const vmas_batch_desc* d, Host
     return fail(VMAS_ERR_INVALID_ARGUMENT, "min_dist must be finite and >= 0");
   if (!(finite(pr->joint_stiffness) && pr->joint_stiffness >= 0))
     return fail(VMAS_ERR_INVALID_ARGUMENT, "joint_stiffness must be finite and >= 0");
-  if (pr->flags != 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "params.flags must be 0");
+  if (pr->flags & ~(uint32_t)VMAS_DEBUG_NONFINITE)
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "params.flags has unknown bits (0x%x)", pr->flags);
   if (d->n_envs < 1) return fail(VMAS_ERR_INVALID_ARGUMENT, "n_envs must be >= 1");
   const int E = d->n_envs;
   h.off.assign(E + 1, 0);
@@ -311,8 +318,10 @@ int pq_pair_class(int sa, int sb) {
   return 4;
 }
 
+// Host twin of the kernels' excluded(): local indices are stored below 255,
+// a 0xff byte is unused.
 bool excludes(int32_t excl, int loc) {
-  if (excl == -1) return false;
+  if (excl == -1 || loc < 0 || loc >= 255) return false;
   for (int k = 0; k < 4; ++k)
     if ((((uint32_t)excl >> (8 * k)) & 0xffu) == (uint32_t)loc) return true;
   return false;
@@ -535,6 +544,29 @@ vmas_status check_batch(const vmas_batch* b) {
   return VMAS_OK;
 }
 
+// VMAS_DEBUG_NONFINITE: environments marked by the check after an earlier
+// call are reported (once) by the next call on the handle. Synchronises s.
+vmas_status report_nonfinite(vmas_batch* b, hipStream_t s) {
+  if (!b->debug_nonfinite) return VMAS_OK;
+  uint32_t c[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(c, b->d_bad_cnt, sizeof(c), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (c[0] == 0) return VMAS_OK;
+  HIPCHK(launch_fill_i32((int32_t*)b->d_bad_cnt, 1, 0, s));
+  return fail(VMAS_ERR_NONFINITE,
+              "%u environment(s) reached a non-finite state since the last report (%u in all; "
+              "vmas_nonfinite_envs lists them); no work was enqueued by this call",
+              c[0], c[1]);
+}
+
+// VMAS_DEBUG_NONFINITE: marks the environments of `state` that hold a NaN or
+// an infinity (enqueued on s after the step work).
+vmas_status check_nonfinite(vmas_batch* b, const float* state, hipStream_t s) {
+  if (!b->debug_nonfinite) return VMAS_OK;
+  HIPCHK(launch_check_nonfinite(state, b->N, b->d_env_off, b->n_envs, b->d_bad, b->d_bad_cnt, s));
+  return VMAS_OK;
+}
+
 vmas_status launch_plan(vmas_batch* b, StepArgs a, hipStream_t s) {
   const Plan& p = b->plans[b->cur];
   if (p.groups == 0) return VMAS_OK;
@@ -579,7 +611,7 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
     p.rho = s == SPHERE ? p.d0 : 0.0f;
     p.mgx = mov ? m * params->gravity[0] : 0.0f;
     p.mgy = mov ? m * params->gravity[1] : 0.0f;
-    p.sf = s | (f << 8);
+    p.sf = s | (f << 8) | (s != SPHERE ? SF_ROTATES : 0);
     p.excl = -1;
     p.pad[0] = p.pad[1] = 0;
     if (s != SPHERE && (f & COLLIDABLE)) spheres_only = false;
@@ -588,6 +620,7 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
   // Joints: per-entity lists, contact exclusions, rest lengths.
   const int J = desc->n_joints;
   std::vector<JointK> joints(J);
+  std::vector<uint8_t> rest_from_state(J, 0);
   std::vector<int32_t> joff(N + 1, 0), jlist;
   std::vector<std::vector<int>> per(N);
   for (int q = 0; q < J; ++q) {
@@ -599,8 +632,15 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
     k.bx = desc->joint_anchor_b[2 * q];
     k.by = desc->joint_anchor_b[2 * q + 1];
     k.pad = 0;
+    // an anchor off a sphere's centre makes the sphere's orientation part
+    // of the geometry
+    if (shape[k.a] == SPHERE && (k.ax != 0.0f || k.ay != 0.0f)) ent[k.a].sf |= SF_ROTATES;
+    if (shape[k.b] == SPHERE && (k.bx != 0.0f || k.by != 0.0f)) ent[k.b].sf |= SF_ROTATES;
     float rest = desc->joint_rest[q];
     if (rest < 0) {
+      // replaced on the device by the same distance in the step's own FP32
+      // arithmetic (launch_joint_rest), so the spring is exactly at rest there
+      rest_from_state[q] = 1;
       const float* s0 = desc->init_state;
       double Pa[2], Pb[2];
       const int ids[2] = {k.a, k.b};
@@ -688,6 +728,37 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
       (s = upload(&b->d_env_off, h.off.data(), h.off.size())) != VMAS_OK) {
     free_batch(b);
     return s;
+  }
+  if (std::any_of(rest_from_state.begin(), rest_from_state.end(), [](uint8_t v) { return v != 0; })) {
+    // rest lengths taken from the initial state: the anchor distance in the
+    // step kernels' FP32 arithmetic
+    float* d_s0 = nullptr;
+    uint8_t* d_from = nullptr;
+    if ((s = upload(&d_s0, desc->init_state, 6 * (size_t)N)) != VMAS_OK ||
+        (s = upload(&d_from, rest_from_state.data(), rest_from_state.size())) != VMAS_OK) {
+      if (d_s0) (void)hipFree(d_s0);
+      if (d_from) (void)hipFree(d_from);
+      free_batch(b);
+      return s;
+    }
+    hipError_t e = launch_joint_rest(d_s0, N, b->d_ent, b->d_joints, d_from, J, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    (void)hipFree(d_s0);
+    (void)hipFree(d_from);
+    if (e != hipSuccess) {
+      free_batch(b);
+      return fail(VMAS_ERR_DEVICE, "joint rest lengths: %s", hipGetErrorString(e));
+    }
+  }
+  if (params->flags & VMAS_DEBUG_NONFINITE) {
+    b->debug_nonfinite = true;
+    const std::vector<uint32_t> zeros(E, 0u);
+    const uint32_t zc[2] = {0u, 0u};
+    if ((s = upload(&b->d_bad, zeros.data(), zeros.size())) != VMAS_OK ||
+        (s = upload(&b->d_bad_cnt, zc, 2)) != VMAS_OK) {
+      free_batch(b);
+      return s;
+    }
   }
   const int blocks[3] = {64, 128, 256};
   int first_valid = -1;
@@ -830,6 +901,8 @@ vmas_status vmas_step(vmas_batch* b, float* state, const float* actions, uint8_t
   if (!actions && b->A > 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "actions must not be NULL");
   DeviceGuard guard(b->device);
   hipStream_t s = (hipStream_t)stream;
+  vmas_status st = report_nonfinite(b, s);
+  if (st != VMAS_OK) return st;
   if (mask) HIPCHK(launch_fill_u8(mask, b->P, s));
   if (forces) HIPCHK(launch_fill_f32(forces, 3 * (int64_t)b->N, 0.0f, s));
   StepArgs a = make_args(b, b->plans[b->cur]);
@@ -841,20 +914,23 @@ vmas_status vmas_step(vmas_batch* b, float* state, const float* actions, uint8_t
   a.traj = nullptr;
   a.mask = mask;
   a.forces = forces;
-  return launch_plan(b, a, s);
+  if ((st = launch_plan(b, a, s)) != VMAS_OK) return st;
+  return check_nonfinite(b, state, s);
 }
 
-vmas_status vmas_rollout(vmas_batch* b, float* state, const float* actions, uint64_t seed,
-                         int32_t t0, int32_t T, float* traj, uint8_t* final_mask, void* stream) {
-  g_err.clear();
-  if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
+}  // extern "C"
+
+namespace {
+
+// vmas_rollout without the debug report and check (also the forward replays
+// of the adjoint driver and the autotuner's trials, on library workspaces).
+vmas_status rollout_impl(vmas_batch* b, float* state, const float* actions, uint64_t seed,
+                         int32_t t0, int32_t T, float* traj, uint8_t* final_mask, hipStream_t s) {
   if (!state) return fail(VMAS_ERR_INVALID_ARGUMENT, "state must not be NULL");
   if (T < 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "T must be >= 0");
   if (t0 < 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "t0 must be >= 0");
   if ((int64_t)T * b->A * 2 > ((int64_t)1 << 40))
     return fail(VMAS_ERR_INVALID_ARGUMENT, "T * A too large");
-  DeviceGuard guard(b->device);
-  hipStream_t s = (hipStream_t)stream;
   if (traj) HIPCHK(launch_replicate(state, traj, 6 * (int64_t)b->N, T + 1, s));
   if (T == 0) return VMAS_OK;
   if (final_mask) HIPCHK(launch_fill_u8(final_mask, b->P, s));
@@ -870,6 +946,27 @@ vmas_status vmas_rollout(vmas_batch* b, float* state, const float* actions, uint
   return launch_plan(b, a, s);
 }
 
+}  // namespace
+
+extern "C" {
+
+vmas_status vmas_rollout(vmas_batch* b, float* state, const float* actions, uint64_t seed,
+                         int32_t t0, int32_t T, float* traj, uint8_t* final_mask, void* stream) {
+  g_err.clear();
+  if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
+  if (!state) return fail(VMAS_ERR_INVALID_ARGUMENT, "state must not be NULL");
+  if (T < 0 || t0 < 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "T and t0 must be >= 0");
+  if ((int64_t)T * b->A * 2 > ((int64_t)1 << 40))
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "T * A too large");
+  DeviceGuard guard(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  vmas_status st = report_nonfinite(b, s);
+  if (st != VMAS_OK) return st;
+  if ((st = rollout_impl(b, state, actions, seed, t0, T, traj, final_mask, s)) != VMAS_OK)
+    return st;
+  return T > 0 ? check_nonfinite(b, state, s) : VMAS_OK;
+}
+
 vmas_status vmas_rollout_graph(vmas_batch* b, float* state, const float* actions, uint64_t seed,
                                int32_t t0, int32_t T, float* traj, uint8_t* final_mask,
                                void* stream) {
@@ -881,6 +978,8 @@ vmas_status vmas_rollout_graph(vmas_batch* b, float* state, const float* actions
   if (t0 < 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "t0 must be >= 0");
   DeviceGuard guard(b->device);
   hipStream_t s = (hipStream_t)stream;
+  vmas_status st0 = report_nonfinite(b, s);
+  if (st0 != VMAS_OK) return st0;
   const Plan& p = b->plans[b->cur];
   if (p.groups == 0) return VMAS_OK;
   StepArgs a = make_args(b, p);
@@ -918,7 +1017,7 @@ vmas_status vmas_rollout_graph(vmas_batch* b, float* state, const float* actions
     HIPCHK(hipGraphExecKernelNodeSetParams(b->gexec, b->gnode, &kp));
   }
   HIPCHK(hipGraphLaunch(b->gexec, s));
-  return VMAS_OK;
+  return check_nonfinite(b, state, s);
 }
 
 vmas_status vmas_autotune(vmas_batch* b, const float* state, const float* actions, int32_t T,
@@ -943,7 +1042,7 @@ vmas_status vmas_autotune(vmas_batch* b, const float* state, const float* action
     if (hipMemcpyAsync(scratch, state, n * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess)
       return fail(VMAS_ERR_DEVICE, "autotune copy failed");
     (void)hipEventRecord(e0, s);
-    vmas_status r = vmas_rollout(b, scratch, actions, 12345u, 0, T, nullptr, nullptr, stream);
+    vmas_status r = rollout_impl(b, scratch, actions, 12345u, 0, T, nullptr, nullptr, s);
     (void)hipEventRecord(e1, s);
     if (r != VMAS_OK) return r;
     if (hipEventSynchronize(e1) != hipSuccess) return fail(VMAS_ERR_DEVICE, "autotune sync failed");
@@ -1029,6 +1128,8 @@ vmas_status vmas_step_backward(vmas_batch* b, const float* state_t, const float*
   if (!b->back.valid)
     return fail(VMAS_ERR_UNSUPPORTED, "an environment is too large for the adjoint plan");
   DeviceGuard guard(b->device);
+  vmas_status st = report_nonfinite(b, (hipStream_t)stream);
+  if (st != VMAS_OK) return st;
   return adjoint_segment(b, state_t, actions_t, 1, grad_state_next, grad_state_t, grad_actions_t,
                          (hipStream_t)stream);
 }
@@ -1046,6 +1147,8 @@ vmas_status vmas_rollout_backward(vmas_batch* b, const float* state0, const floa
     return fail(VMAS_ERR_UNSUPPORTED, "an environment is too large for the adjoint plan");
   DeviceGuard guard(b->device);
   hipStream_t s = (hipStream_t)stream;
+  vmas_status st0 = report_nonfinite(b, s);
+  if (st0 != VMAS_OK) return st0;
   const int k = std::min(ckpt_every, T);
   const int nseg = (T + k - 1) / k;
   const size_t S6 = 6 * (size_t)b->N;
@@ -1072,8 +1175,8 @@ vmas_status vmas_rollout_backward(vmas_batch* b, const float* state0, const floa
   for (int q = 1; q < nseg; ++q) {
     HIPCHK(hipMemcpyAsync(ckpt + S6 * q, ckpt + S6 * (q - 1), S6 * sizeof(float),
                           hipMemcpyDeviceToDevice, s));
-    vmas_status st = vmas_rollout(b, ckpt + S6 * q, actions ? actions + A2 * (size_t)(q - 1) * k : nullptr,
-                                  0, 0, k, nullptr, nullptr, stream);
+    vmas_status st = rollout_impl(b, ckpt + S6 * q, actions ? actions + A2 * (size_t)(q - 1) * k : nullptr,
+                                  0, 0, k, nullptr, nullptr, s);
     if (st != VMAS_OK) return st;
   }
   // backward: replay each segment from its checkpoint, then step back through it
@@ -1084,8 +1187,8 @@ vmas_status vmas_rollout_backward(vmas_batch* b, const float* state0, const floa
     // seg[0 .. len]: states t0 .. t0 + len (the rollout writes them as a trajectory)
     float* st_tmp = g1;  // scratch for the rolled state, overwritten below
     HIPCHK(hipMemcpyAsync(st_tmp, seg, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
-    vmas_status st = vmas_rollout(b, st_tmp, actions ? actions + A2 * (size_t)t0 : nullptr, 0, 0, len,
-                                  seg, nullptr, stream);
+    vmas_status st = rollout_impl(b, st_tmp, actions ? actions + A2 * (size_t)t0 : nullptr, 0, 0, len,
+                                  seg, nullptr, s);
     if (st != VMAS_OK) return st;
     // the reverse steps of the segment in one launch
     st = adjoint_segment(b, seg, actions ? actions + A2 * (size_t)t0 : nullptr, len, g0, g1,
@@ -1128,6 +1231,8 @@ vmas_status vmas_step_surrogate(vmas_batch* b, vmas_mlp* mlp, float* state, cons
     return fail(VMAS_ERR_INVALID_ARGUMENT, "surrogate step supports fewer than 2^31 pair slots");
   DeviceGuard guard(b->device);
   hipStream_t s = (hipStream_t)stream;
+  vmas_status st0 = report_nonfinite(b, s);
+  if (st0 != VMAS_OK) return st0;
   if (!b->d_feat && b->P > 0) {
     hipError_t e;
     if ((e = hipMalloc((void**)&b->d_feat, (size_t)b->P * 12 * sizeof(float))) != hipSuccess ||
@@ -1163,6 +1268,30 @@ vmas_status vmas_step_surrogate(vmas_batch* b, vmas_mlp* mlp, float* state, cons
   }
   HIPCHK(launch_step_surrogate(a, b->d_yhat, band, fallback_frac, n_fallback, p.groups, p.block,
                                s));
+  return check_nonfinite(b, state, s);
+}
+
+vmas_status vmas_nonfinite_envs(vmas_batch* b, uint8_t* marks, int32_t* count, int32_t clear,
+                                void* stream) {
+  g_err.clear();
+  if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
+  if (!b->debug_nonfinite)
+    return fail(VMAS_ERR_INVALID_ARGUMENT, "the batch was created without VMAS_DEBUG_NONFINITE");
+  DeviceGuard guard(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<uint32_t> m(b->n_envs);
+  uint32_t c[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(m.data(), b->d_bad, m.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(c, b->d_bad_cnt, sizeof(c), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (marks)
+    for (int e = 0; e < b->n_envs; ++e) marks[e] = m[e] ? 1 : 0;
+  if (count) *count = (int32_t)c[1];
+  if (clear) {
+    HIPCHK(launch_fill_i32((int32_t*)b->d_bad, b->n_envs, 0, s));
+    HIPCHK(launch_fill_i32((int32_t*)b->d_bad_cnt, 2, 0, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
   return VMAS_OK;
 }
 

@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(MAXB) k_cand_features(CandArgs ca) {
     const int e = a.stage[s0 + s];
     const EntParam p = a.ent[e];
     float cs = 1.0f, sn = 0.0f;
-    if ((p.sf & 0xff) != SPHERE) sincosf(a.state[4 * N + e], &sn, &cs);
+    if (uses_rotation(p.sf)) sincosf(a.state[4 * N + e], &sn, &cs);
     pose[s] = make_float4(a.state[e], a.state[N + e], cs, sn);
     stat[s] = make_float4(p.d0, p.d1, p.rho, __int_as_float(p.sf));
     brad[s] = bound_radius(p.sf & 0xff, p.d0, p.d1);
@@ -314,7 +314,7 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
     const int e = a.stage[s0 + s];
     const EntParam p = a.ent[e];
     float cs = 1.0f, sn = 0.0f;
-    if ((p.sf & 0xff) != SPHERE) sincosf(a.state[4 * N + e], &sn, &cs);
+    if (uses_rotation(p.sf)) sincosf(a.state[4 * N + e], &sn, &cs);
     pose[s] = make_float4(a.state[e], a.state[N + e], cs, sn);
     stat[s] = make_float4(p.d0, p.d1, p.rho, __int_as_float(p.sf));
     brad[s] = bound_radius(p.sf & 0xff, p.d0, p.d1);
@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
   const EntParam p = a.ent[e];
   const int shape = p.sf & 0xff, fl = (p.sf >> 8) & 0xff;
   float cs = 1.0f, sn = 0.0f;
-  if (shape != SPHERE) sincosf(th, &sn, &cs);
+  if (uses_rotation(p.sf)) sincosf(th, &sn, &cs);
   float fx = p.mgx, fy = p.mgy, tq = 0.0f;
   if (r.agent >= 0) {
     fx += a.actions[2 * (size_t)r.agent];

@@ -134,6 +134,30 @@ def test_bad_joints():
     assert st == 1 and "init_state" in msg
 
 
+def test_debug_nonfinite_flag_validation():
+    """VMAS_DEBUG_NONFINITE is the one accepted world flag: with it the
+    description passes host validation (on a machine without a GPU the call
+    then stops at the device check); any other bit is rejected. Listing the
+    marked environments needs a handle."""
+    w = W.spread(2)
+    keep = []
+    p = _params(w)
+    p.flags = B.VMAS_DEBUG_NONFINITE
+    st, msg, h = _create(p, _desc(w, keep))
+    assert st != 1, msg
+    if st == 0:
+        B.lib().vmas_destroy_batch(h)
+    else:
+        assert st == 3 and "device" in msg, msg
+    for bad in (2, 4, 0x80000000, B.VMAS_DEBUG_NONFINITE | 8):
+        p.flags = bad
+        st, msg, _ = _create(p, _desc(w, keep))
+        assert st == 1 and "flags" in msg, (bad, msg)
+    cnt = ctypes.c_int32(-3)
+    assert B.lib().vmas_nonfinite_envs(None, None, ctypes.byref(cnt), 0, None) == 1
+    assert cnt.value == -3
+
+
 def test_python_binding_names_match_c():
     for n in ("vmas_create_batch", "vmas_step", "vmas_rollout", "vmas_step_backward",
               "vmas_rollout_backward"):
