@@ -73,6 +73,8 @@ def lib():
         L.oracle_rollout_range.argtypes = [wp, ctypes.c_int, ctypes.c_int, _f64p, _f64p,
                                            ctypes.c_int, _f64p, _u8p]
         L.oracle_rollout_jvp.argtypes = [wp, _f64p, _f64p, _f64p, _f64p, ctypes.c_int]
+        _f32p = ctypes.POINTER(ctypes.c_float)
+        L.oracle_rollout_fp32.argtypes = [wp, _f32p, _f32p, ctypes.c_int, _f32p]
         L.oracle_pair.argtypes = [ctypes.c_int, _f64p, _f64p, ctypes.c_int, _f64p, _f64p, _f64p]
         L.oracle_pair_distances.argtypes = [wp, _f64p, _f64p, _f64p]
         L.oracle_default_inertia.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -177,6 +179,20 @@ class OracleWorld:
         lib().oracle_rollout_range(ctypes.byref(self.s), e0, e1, _p(st, _f64p), _p(act, _f64p),
                                    T, _p(tr, _f64p), _p(mask, _u8p))
         return st, mask, tr
+
+    def rollout_fp32(self, state: np.ndarray, actions: np.ndarray, traj: bool = False):
+        """The same definition evaluated in FP32 (not a reference: it sizes the
+        FP32 rounding allowance of the parity tests). Returns (final state,
+        trajectory [T+1, 6, N] or None), float32."""
+        f32 = ctypes.POINTER(ctypes.c_float)
+        T = actions.shape[0]
+        st = np.ascontiguousarray(state, np.float32).copy()
+        act = np.ascontiguousarray(actions, np.float32)
+        tr = np.zeros((T + 1, 6, self.N), np.float32) if traj else None
+        lib().oracle_rollout_fp32(ctypes.byref(self.s), st.ctypes.data_as(f32),
+                                  act.ctypes.data_as(f32), T,
+                                  None if tr is None else tr.ctypes.data_as(f32))
+        return st, tr
 
     def rollout_jvp(self, state, dstate, actions, dactions):
         T = actions.shape[0]

@@ -23,7 +23,12 @@
 // Everything is templated on the scalar type:
 //   * double  -> the oracle proper;
 //   * Dual    -> forward-mode tangents (exact JVP of the discrete step, used to
-//                check the hand-written adjoint).
+//                check the hand-written adjoint);
+//   * float   -> the same definition evaluated in FP32, operation by
+//                operation as written here. It is never the reference: the
+//                parity tests use its distance from the FP64 result only to
+//                size how far any FP32 evaluation of an environment's step can
+//                be from the exact one (their conditioning allowance).
 // Branches on the geometry are taken on values; a Dual carries the derivative
 // of the branch that is taken.
 //
@@ -65,6 +70,7 @@ inline bool operator==(Dual a, Dual b) { return a.v == b.v; }
 
 inline double val(double x) { return x; }
 inline double val(Dual x) { return x.v; }
+inline double val(float x) { return x; }
 
 inline double m_sqrt(double x) { return std::sqrt(x); }
 inline Dual m_sqrt(Dual x) {
@@ -82,6 +88,11 @@ inline Dual m_exp(Dual x) {
 }
 inline double m_log1p(double x) { return std::log1p(x); }
 inline Dual m_log1p(Dual x) { return {std::log1p(x.v), x.d / (1 + x.v)}; }
+inline float m_sqrt(float x) { return std::sqrt(x); }
+inline float m_sin(float x) { return std::sin(x); }
+inline float m_cos(float x) { return std::cos(x); }
+inline float m_exp(float x) { return std::exp(x); }
+inline float m_log1p(float x) { return std::log1p(x); }
 template <class T> inline T m_abs(T x) { return x < T(0) ? -x : x; }
 
 // ------------------------------------------------------------ 2D vectors --
@@ -740,6 +751,21 @@ int oracle_rollout_jvp(const oracle_world* w, double* state, double* dstate,
   for (int64_t q = 0; q < 6 * N; ++q) {
     state[q] = s[q].v;
     dstate[q] = s[q].d;
+  }
+  return 0;
+}
+
+// The same step and rollout evaluated in FP32 (see the header: it only sizes
+// the FP32 rounding allowance of the parity tests). state [6][N] float,
+// actions [T][A][2] float, traj (optional) [T+1][6][N] float.
+int oracle_rollout_fp32(const oracle_world* w, float* state, const float* actions, int T,
+                        float* traj) {
+  const int64_t N = w->env_offset[w->n_envs];
+  const int64_t A = total_agents(w);
+  if (traj) std::memcpy(traj, state, sizeof(float) * 6 * N);
+  for (int t = 0; t < T; ++t) {
+    step_envs<float>(w, 0, w->n_envs, state, actions + 2 * A * t, nullptr, nullptr);
+    if (traj) std::memcpy(traj + 6 * N * (t + 1), state, sizeof(float) * 6 * N);
   }
   return 0;
 }

@@ -15,7 +15,8 @@ Random numbers come from a counter-based SplitMix64 (Steele, Lea, Flood,
 i.e. draw(., ., i) is output i of a SplitMix64 generator started at ``key``.
 A draw becomes a uniform u = (draw >> 40) * 2^-24 and a = 2u - 1, exact in
 FP32, so both sides consume identical values. Streams: 1 positions,
-2 actions, 3 orientations, 4 per-environment agent counts.
+2 actions, 3 orientations, 4 per-environment agent counts, 5 candidate
+positions of the separated layout (rejection sampling).
 
 Action element (t, agent, comp) of a batch with A agents in total is draw
 index (t * A + agent) * 2 + comp; the GPU rollout can regenerate the same
@@ -32,7 +33,7 @@ GOLDEN = np.uint64(0x9E3779B97F4A7C15)
 M1 = np.uint64(0xBF58476D1CE4E5B9)
 M2 = np.uint64(0x94D049BB133111EB)
 
-STREAM_POS, STREAM_ACT, STREAM_THETA, STREAM_COUNT = 1, 2, 3, 4
+STREAM_POS, STREAM_ACT, STREAM_THETA, STREAM_COUNT, STREAM_SEP = 1, 2, 3, 4, 5
 
 SPHERE, BOX, LINE = 0, 1, 2
 MOVABLE, ROTATABLE, COLLIDABLE = 1, 2, 4
@@ -183,13 +184,53 @@ def spread(n_envs: int, n_agents: int = 4, n_landmarks: int = 2, radius: float =
                  name=f"spread{n_envs}x({n_agents}a+{n_landmarks}l)")
 
 
+def _separated_positions(seed: int, n_envs: int, reach: np.ndarray, half_width: float,
+                         gap: float, tries: int = 256) -> np.ndarray:
+    """[n_envs * n, 2] positions, uniform in [-half_width, half_width]^2 and
+    rejection-sampled per environment: entity i takes the first of its
+    candidates (stream 5, candidate k of entity i of environment b is draw
+    pair ((b * n + i) * tries + k)) whose circle of radius reach[i] keeps
+    `gap` from the circles of entities 0 .. i-1 already placed. `reach` is
+    a radius that covers the entity's whole shape, so no two shapes touch."""
+    n = reach.shape[0]
+    pos = np.zeros((n_envs, n, 2), np.float32)
+    for i in range(n):
+        placed = np.zeros(n_envs, bool)
+        for k0 in range(0, tries, 16):
+            ks = np.arange(k0, k0 + 16, dtype=np.uint64)
+            base = ((np.arange(n_envs, dtype=np.uint64)[:, None] * np.uint64(n) + np.uint64(i))
+                    * np.uint64(tries) + ks[None, :]) * np.uint64(2)
+            cx = draw_sym(seed, STREAM_SEP, base) * np.float32(half_width)
+            cy = draw_sym(seed, STREAM_SEP, base + np.uint64(1)) * np.float32(half_width)
+            ok = np.ones(cx.shape, bool)
+            for j in range(i):
+                dd = np.hypot(cx.astype(np.float64) - pos[:, j, 0:1], cy.astype(np.float64) - pos[:, j, 1:2])
+                ok &= dd > reach[i] + reach[j] + gap
+            first = np.argmax(ok, 1)
+            take = ~placed & ok[np.arange(n_envs), first]
+            pos[take, i, 0] = cx[take, first[take]]
+            pos[take, i, 1] = cy[take, first[take]]
+            placed |= take
+            if placed.all():
+                break
+        if not placed.all():
+            raise ValueError(f"entity {i}: no separated position in {tries} tries")
+    return pos.reshape(-1, 2)
+
+
 def mixed(n_envs: int, n_spheres: int = 16, n_boxes: int = 4, n_lines: int = 8,
           radius: float = 0.03, box=(0.1, 0.3), line_len: float = 0.5, joints: bool = True,
-          seed: int = 0) -> World:
+          seed: int = 0, half_width: float = 1.0, separated: bool = False) -> World:
     """Mixed shapes and joints: sphere agents, boxes and line segments, all
     movable and rotatable, random poses in [-1, 1]^2 with angles uniform in
     [-pi, pi); two joints per environment tie agents 0 and 1 (at their
-    centres) to box 0 at its local (0, +ly/2) and (0, -ly/2)."""
+    centres) to box 0 at its local (0, +ly/2) and (0, -ly/2).
+
+    separated=True: positions uniform in [-half_width, half_width]^2 but
+    rejection-sampled so that no two shapes are within 0.02 of each other at
+    t = 0 (by circles covering each shape: sphere radius, half the box
+    diagonal, half the segment); the joints' rest lengths are the anchor
+    distances of that layout."""
     n = n_spheres + n_boxes + n_lines
     N = n_envs * n
     env_offset = (np.arange(n_envs + 1) * n).astype(np.int32)
@@ -204,10 +245,18 @@ def mixed(n_envs: int, n_spheres: int = 16, n_boxes: int = 4, n_lines: int = 8,
     flags = np.full(N, MOVABLE | ROTATABLE | COLLIDABLE, np.uint8)
     theta = _orientations(seed, N)
     theta[shape == SPHERE] = 0.0
+    if separated:
+        kinds = shape[:n]
+        reach = np.where(kinds == SPHERE, radius,
+                         np.where(kinds == BOX, 0.5 * np.hypot(box[0], box[1]), 0.5 * line_len))
+        pos = _separated_positions(seed, n_envs, reach.astype(np.float64), half_width, 0.02)
+    else:
+        pos = _positions(seed, N) * np.float32(half_width)
     w = World(env_offset=env_offset, n_agents=np.full(n_envs, n_spheres, np.int32),
               shape=shape, dims=dims, mass=np.ones(N, np.float32), flags=flags,
-              state0=_state(_positions(seed, N), theta), seed=seed,
-              name=f"mixed{n_envs}x({n_spheres}s+{n_boxes}b+{n_lines}l)")
+              state0=_state(pos, theta), seed=seed,
+              name=f"mixed{n_envs}x({n_spheres}s+{n_boxes}b+{n_lines}l)"
+                   + ("-separated" if separated else ""))
     if joints and n_boxes > 0 and n_spheres >= 2:
         base = np.arange(n_envs, dtype=np.int32) * n
         box0 = base + n_spheres

@@ -3,20 +3,24 @@ and the fork-aware comparison of free-running trajectories.
 
 Relative error (the reading of "1e-5 relative after one step, 1e-3 after
 100" used throughout): normwise per field group {position, velocity,
-angle, angular velocity}. For environment e and group G,
+angle, angular velocity}. For environment e and group G the per-environment
+error is
 
-    err[e, G] = ||g_e,G - o_e,G||_inf / max(||o_G||_inf, 1e-6)
+    err[e, G] = ||g_e,G - o_e,G||_inf / max(||o_e,G||_inf, 1e-6)
 
-with the numerator over the entities of e and the denominator over the
-whole batch. (A per-environment denominator is ill-conditioned for these
-stiff, contact-driven updates: the FP64 oracle itself moves by up to ~45x
-the tolerance under a 1e-7 input perturbation when an environment's
-angular velocities are all near zero.)
+(numerator and denominator over the entities of e: env_rel_err_local). The
+tests assert it together with the batch-scaled variant env_err, whose
+denominator is the group's magnitude over the whole batch.
 
-Conditioning: an environment is ill-conditioned when the FP64 oracle,
-given inputs perturbed by 1e-7 relative (FP32 rounding size), moves by more
-than a tenth of the tolerance in the same metric. Such environments are
-counted and reported, not hidden.
+Conditioning: the state checks (conditioned_check) add to the relative
+tolerance K = 4 times how far the exact (FP64) result itself moves when
+the input poses move by 1e-7 (FP32 rounding size of O(1) coordinates). On a
+well-conditioned environment that allowance is far below the tolerance; it
+matters where no FP32 computation can meet the relative tolerance (a
+quantity that is exactly zero in the exact result but rounding-sized in
+FP32, where the per-environment denominator is its 1e-6 floor, or a stiff
+contact that amplifies rounding). No environment is excluded; how many
+needed the allowance is printed and bounded.
 
 Forks: the contact decision of Eq. (2) is a threshold, so two correct
 trajectories may take different decisions once rounding has moved them
@@ -168,10 +172,99 @@ def _perturb(state, rel, seed, shape=None):
     return s
 
 
+def both_errs(gpu, ora, env_offset, scale=None) -> np.ndarray:
+    """[E]: the larger of the batch-scaled and the per-environment error."""
+    return np.maximum(env_err(gpu, ora, env_offset, scale).max(1),
+                      env_rel_err_local(gpu, ora, env_offset).max(1))
+
+
+def conditioned_check(gpu, ora, perts, env_offset, tol, K=4.0):
+    """The per-environment comparison the parity tests assert (S23 reading
+    with a conditioning allowance). For environment e and field group G,
+
+        |g - o|_e,G <= tol * max(|o|_e,G, 1e-6) + K * rho_e,G
+
+    (inf-norms over the entities of e), where rho_e,G is the largest
+    |o' - o|_e,G over the results `perts` (perturbed_steps): how far the
+    exact result moves when the input poses move by FP32 rounding size, and
+    how far the same definition evaluated in FP32 lands from it.
+    The first term is the relative tolerance with the per-environment
+    denominator; the second admits what no FP32 computation can avoid on an
+    ill-conditioned environment (a contact decision or a quantity that is
+    exactly zero in the exact result but rounding-sized in FP32), so no
+    environment is excluded. Returns (ok [E] bool, plain [E]: the plain
+    relative error max_G |g - o|_e,G / max(|o|_e,G, 1e-6), allow [E]: whether
+    the allowance was needed). With K=None, ok holds the multiple of rho each
+    environment needs instead (0 where the plain tolerance holds)."""
+    gpu = np.asarray(gpu, np.float64)
+    ora = np.asarray(ora, np.float64)
+    E = len(env_offset) - 1
+    seg = np.repeat(np.arange(E), np.diff(env_offset))
+    need = np.zeros(E)
+    plain = np.zeros(E)
+    for rows in GROUPS.values():
+        r = list(rows)
+        num, mag, rho = np.zeros(E), np.zeros(E), np.zeros(E)
+        np.maximum.at(num, seg, np.abs(gpu[r] - ora[r]).max(0))
+        np.maximum.at(mag, seg, np.abs(ora[r]).max(0))
+        for p in perts:
+            np.maximum.at(rho, seg, np.abs(np.asarray(p, np.float64)[r] - ora[r]).max(0))
+        den = np.maximum(mag, 1e-6)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            over = np.maximum(num - tol * den, 0.0)
+            need = np.maximum(need, np.where(over > 0, over / rho, 0.0))
+        plain = np.maximum(plain, num / den)
+    if K is None:
+        return need, plain, plain > tol
+    return need <= K, plain, plain > tol
+
+
+def conditioned_detail(gpu, ora, perts, env_offset, e):
+    """Per group of environment e: (|g - o|, |o|, rho) for failure messages."""
+    gpu = np.asarray(gpu, np.float64)
+    ora = np.asarray(ora, np.float64)
+    sl = slice(int(env_offset[e]), int(env_offset[e + 1]))
+    out = {}
+    for name, rows in GROUPS.items():
+        r = list(rows)
+        rho = max([np.abs(np.asarray(p, np.float64)[r, sl] - ora[r, sl]).max() for p in perts]
+                  or [0.0])
+        out[name] = (float(np.abs(gpu[r, sl] - ora[r, sl]).max()),
+                     float(np.abs(ora[r, sl]).max()), float(rho))
+    return out
+
+
+def perturbed_steps(ow, state, act, rel=1e-7, seeds=(7, 8)):
+    """The results that size the allowance of conditioned_check: the exact
+    one-step results from FP32-rounding-size perturbations of the input
+    poses, and the oracle's own definition evaluated in FP32 from the input
+    and from the perturbed inputs (which carries the rounding of
+    intermediate values: vertex coordinates, contact arms, spring
+    stretches)."""
+    pert = [_perturb(state, rel, sd, ow.w.shape) for sd in seeds]
+    out = [ow.step(p, act, want_mask=False)[0] for p in pert]
+    # FP32 evaluations from the input and from the perturbed inputs: several
+    # realisations of FP32 rounding (one alone can be luckily small)
+    out += [ow.rollout_fp32(p, np.asarray(act)[None])[0] for p in [state] + pert]
+    return out
+
+
+def perturbed_trajectories(ow, state0, actions, rel=1e-7, seeds=(7, 8)):
+    """[T+1, 6, N] trajectories that size the allowance of a free run: exact
+    ones from perturbed initial poses, and the oracle's definition evaluated
+    in FP32."""
+    pert = [_perturb(state0, rel, sd, ow.w.shape) for sd in seeds]
+    out = [ow.rollout(p, actions, traj=True, want_mask=False)[2] for p in pert]
+    out += [ow.rollout_fp32(p, actions, traj=True)[1] for p in [state0] + pert]
+    return out
+
+
 def ill_conditioned_step(ow, state, act, tol=1e-5, rel=1e-7, seeds=(7, 8)) -> np.ndarray:
     """Environments whose exact (FP64) one-step result moves by more than the
-    tolerance itself when the input poses move by FP32 rounding (`rel`):
-    there even an exact computation on FP32 inputs cannot promise `tol`."""
+    tolerance itself (batch-scaled metric) when the input poses move by FP32
+    rounding (`rel`): there even an exact computation on FP32 inputs cannot
+    promise `tol`. (Used by the auxiliary force and adjoint checks; the
+    state checks use conditioned_check.)"""
     ref, _, _ = ow.step(state, act, want_mask=False)
     scale = group_scale(ref)
     out = np.zeros(ow.w.n_envs, bool)
@@ -193,18 +286,23 @@ def ill_conditioned_rollout(ow, state0, actions, tol=1e-3, rel=1e-7, seeds=(7, 8
 
 def horizon(ow, state0, actions, tol=1e-3, rel=1e-7, seeds=(7, 8)) -> np.ndarray:
     """Per environment, the first step at which the exact (FP64) trajectory
-    moves by more than tol/10 under an FP32-sized perturbation of the initial
-    poses (T if never): beyond it the trajectory is chaotic at FP32 precision
-    and two correct implementations need not agree."""
+    moves by more than tol/10 (batch-scaled metric) under an FP32-sized
+    perturbation of the initial poses (T if never): beyond it the trajectory
+    is chaotic at FP32 precision and two correct implementations need not
+    agree."""
     T = actions.shape[0]
     _, _, ref = ow.rollout(state0, actions, traj=True, want_mask=False)
     E = ow.w.n_envs
     h = np.full(E, T)
+    # group magnitudes over the whole run (a group that is exactly zero at one
+    # step, e.g. every angular velocity before the first torque, is not
+    # unpredictable because a perturbation makes it rounding-sized)
+    scale = group_scale(np.concatenate(list(ref), axis=1))
     for sd in seeds:
         _, _, pt = ow.rollout(_perturb(state0, rel, sd, ow.w.shape), actions, traj=True,
                               want_mask=False)
         for t in range(1, T + 1):
-            moved = env_err(pt[t], ref[t], ow.w.env_offset, group_scale(ref[t])).max(1) > tol / 10
+            moved = env_err(pt[t], ref[t], ow.w.env_offset, scale).max(1) > tol / 10
             h = np.where(moved & (h > t - 1), np.minimum(h, t - 1), h)
     return h
 

@@ -9,6 +9,8 @@ printed; none allowed on the 32-environment configuration at seed 0). Every
 exclusion (ill-conditioned environment, valid trajectory fork) is counted,
 printed and bounded.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -19,96 +21,8 @@ from tests import parity as PU
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-def _batch(w):
-    from paper_2207_03530_amd import binding as B
-    return B.Batch(w, 0)
-
-
-def _dev(a, dtype=torch.float32):
-    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda:0", dtype)
-
-
-def _gpu_step(b, state, act, masks=True, forces=False):
-    st = _dev(state)
-    mk = torch.zeros(b.P, dtype=torch.uint8, device="cuda:0") if masks else None
-    fo = torch.zeros(3 * b.N, dtype=torch.float32, device="cuda:0") if forces else None
-    b.step(st, _dev(act), mk, fo)
-    torch.cuda.synchronize()
-    out = [st.cpu().numpy().reshape(6, -1)]
-    out.append(mk.cpu().numpy() if masks else None)
-    out.append(fo.cpu().numpy().reshape(3, -1) if forces else None)
-    return out
-
-
-def _gpu_run(b, state0, acts, ids=None, slots=None):
-    """Step loop on the GPU: states [T+1, 6, n] and masks [T, p] (restricted
-    to entity ids / pair slots when given)."""
-    T = acts.shape[0]
-    s = _dev(state0)
-    a = _dev(acts)
-    mk = torch.zeros(b.P, dtype=torch.uint8, device="cuda:0")
-    ids_t = None if ids is None else torch.as_tensor(ids, device="cuda:0")
-    sl_t = None if slots is None else torch.as_tensor(slots, device="cuda:0")
-    trs, mks = [], []
-    pick = (lambda x: x.view(6, -1)) if ids_t is None else (lambda x: x.view(6, -1)[:, ids_t])
-    trs.append(pick(s).cpu().numpy())
-    for t in range(T):
-        b.step(s, a[t], mk)
-        trs.append(pick(s).cpu().numpy())
-        mks.append((mk if sl_t is None else mk[sl_t]).cpu().numpy())
-    return s, np.stack(trs), np.stack(mks)
-
-
-def _mask_check(w, ow, state, gmask, omask, name=""):
-    """Masks equal except for band cases (tests/parity.py mask_compare);
-    returns the band slots."""
-    band = PU.mask_compare(ow, state, gmask, omask)
-    print(f"{name} mask: contacts {int(np.sum(omask))}, band cases {len(band)}, nearest "
-          f"|d - d_min| {PU.nearest_to_threshold(ow, state):.3g}")
-    return band
-
-
-def _one_step_check(w, ow, st, act, g, o, name, skip=None, max_ill_frac=0.02):
-    err = PU.env_err(g, o, w.env_offset)
-    ill = PU.ill_conditioned_step(ow, st, act)
-    if skip is not None:
-        ill = ill | skip
-    loc = PU.env_rel_err_local(g, o, w.env_offset)
-    good = ~ill
-    print(f"{name}: max err {err.max():.3g}, on well-conditioned {err[good].max():.3g}, "
-          f"ill-conditioned {ill.sum()}/{w.n_envs}, per-env-relative on well-conditioned "
-          f"median {np.median(loc[good].max(1)):.3g}")
-    assert ill.sum() <= max(1, int(max_ill_frac * w.n_envs))
-    assert err[good].max() <= 1e-5, f"{name}: worst env {np.argmax(np.where(good, err.max(1), 0))}"
-    return err
-
-
-def _free_run_check(w, ow, gtraj, gmasks, acts, name, tol=1e-3, min_full=0.75, min_steps=None):
-    """Free-running comparison up to each environment's cutoff: the first
-    valid mask fork or the FP64 predictability horizon, whichever comes
-    first. Every step up to the cutoff must agree within `tol`; at least a
-    fraction `min_full` of the environments must be comparable for
-    `min_steps` steps (default: all T)."""
-    ora, fork, invalid = PU.fork_compare(ow, gtraj, gmasks, w.state0, acts)
-    assert not invalid, f"{name}: mask forks outside the deviation band: {invalid[:5]}"
-    T = acts.shape[0]
-    hor = PU.horizon(ow, w.state0, acts, tol=tol)
-    cut = np.minimum(fork, hor)
-    worst = 0.0
-    for t in range(1, T + 1):
-        live = cut >= t
-        if not live.any():
-            break
-        e = PU.env_err(gtraj[t], ora[t], w.env_offset, PU.group_scale(ora[t])).max(1)
-        worst = max(worst, e[live].max())
-        assert e[live].max() <= tol, f"{name}: step {t}: err {e[live].max():.3g}"
-    need = T if min_steps is None else min_steps
-    full = (cut >= need).mean()
-    print(f"{name}: forks {(fork < T).sum()}, FP64 horizon < T {(hor < T).sum()}, "
-          f"median cutoff {np.median(cut):.0f}/{T}, comparable >= {need} steps {full:.2f}, "
-          f"max err up to cutoffs {worst:.3g}")
-    assert full >= min_full
-    return ora
+from tests.gpu_common import (_batch, _dev, _free_run_check, _gpu_run, _gpu_step,  # noqa: E402
+                               _mask_check, _one_step_check, _teacher_forced_check)
 
 
 # ------------------------------------------------------------ spheres ------
@@ -324,6 +238,56 @@ def test_mixed_multi_step_parity():
     _free_run_check(w, ow, gtraj, gmasks, acts, "mixed48 T=200", min_full=0.5, min_steps=5)
 
 
+def _sample_rows(w, envs):
+    """Action rows of the agents of `envs`."""
+    first = np.concatenate([[0], np.cumsum(w.n_agents)[:-1]])
+    return np.concatenate([first[e] + np.arange(w.n_agents[e]) for e in envs])
+
+
+def test_mixed4096_teacher_forced_200_steps():
+    """The full mixed configuration (4,096 environments, 200 steps, single
+    steps through the C boundary); 256 sampled environments are checked at
+    every step against the oracle started from the GPU's own state of that
+    step (teacher forcing): 1e-5 in both metrics, masks bit for bit up to
+    band cases, at most 2 % of environment-steps excluded."""
+    w = W.mixed(4096)
+    T = 200
+    acts = w.actions(T)
+    b = _batch(w)
+    rng = np.random.default_rng(1)
+    envs = np.sort(rng.choice(w.n_envs, 256, replace=False))
+    ids = np.concatenate([np.arange(w.env_offset[e], w.env_offset[e + 1]) for e in envs])
+    n = np.diff(w.env_offset).astype(np.int64)
+    poff = np.concatenate([[0], np.cumsum(n * (n - 1) // 2)])
+    slots = np.concatenate([np.arange(poff[e], poff[e + 1]) for e in envs])
+    _, gtraj, gmasks = _gpu_run(b, w.state0, acts, ids=ids, slots=slots)
+    ws = W.subset(w, envs)
+    _teacher_forced_check(ws, O.OracleWorld(ws), gtraj, gmasks, acts[:, _sample_rows(w, envs)],
+                          "mixed4096 sample, teacher-forced")
+
+
+def test_mixed_separated_hundred_steps():
+    """A well-conditioned mixed workload: the mixed layout (16 spheres, 4
+    boxes, 8 segments, 2 joints) with no two shapes within 0.02 of each other
+    at t = 0, in [-2, 2]^2, and joints of stiffness 25. (At the contact
+    stiffness 100 a joint from an agent to the end of a box is beyond the
+    stability bound of damped semi-implicit Euler, omega dt = 2.2 > 1.87,
+    so there the exact trajectory itself diverges from its own FP32-size
+    perturbation.) 256 environments run free for 100 steps: every step up to
+    an environment's first valid mask fork within 1e-3 (conditioned check),
+    and at least 75 % of the environments without a fork for all 100 steps."""
+    w = dataclasses.replace(W.mixed(256, seed=4, half_width=2.0, separated=True),
+                            joint_stiffness=25.0)
+    T = 100
+    acts = w.actions(T)
+    b = _batch(w)
+    _, gtraj, gmasks = _gpu_run(b, w.state0, acts)
+    ow = O.OracleWorld(w)
+    _free_run_check(w, ow, gtraj, gmasks, acts, "mixed256 separated T=100", min_full=0.75)
+    _teacher_forced_check(w, ow, gtraj, gmasks, acts, "mixed256 separated, teacher-forced",
+                          min_plain=0.5)
+
+
 SHAPE_CASES = [
     ("sphere-sphere", (W.SPHERE, 0.1, 0), (W.SPHERE, 0.08, 0)),
     ("sphere-box", (W.SPHERE, 0.1, 0), (W.BOX, 0.3, 0.2)),
@@ -364,7 +328,7 @@ def test_pair_type_micro_cases(name, a, c):
     assert om.sum() > E // 8
     skip = np.zeros(E, bool)
     skip[band] = True
-    _one_step_check(w, ow, st, act, g, o, name, skip=skip, max_ill_frac=0.03)
+    _one_step_check(w, ow, st, act, g, o, name, skip=skip)
     ok = ~np.repeat(skip | PU.ill_conditioned_step(ow, st, act), 2)
     fscale = np.abs(of).max(1, keepdims=True) + 1e-12
     ferr = (np.abs(gf - of)[:, ok] / fscale).max(1)
@@ -421,7 +385,7 @@ def test_uneven_batch_parity():
     g1, gm, _ = _gpu_step(b, w.state0, acts[0])
     ow = O.OracleWorld(w)
     o1, om, _ = ow.step(w.state0, acts[0])
-    _one_step_check(w, ow, w.state0, acts[0], g1, o1, "uneven96 step", max_ill_frac=0.15)
+    _one_step_check(w, ow, w.state0, acts[0], g1, o1, "uneven96 step")
     assert len(_mask_check(w, ow, w.state0, gm, om, "uneven96")) == 0
     _, gtraj, gmasks = _gpu_run(b, w.state0, acts)
     _free_run_check(w, ow, gtraj, gmasks, acts, "uneven96 T=40", min_full=0.5, min_steps=10)
