@@ -222,6 +222,23 @@ vmas_status vmas_rollout_backward(vmas_batch* batch, const float* state0, const 
                                   int32_t T, int32_t ckpt_every, const float* grad_state_T,
                                   float* grad_state0, float* grad_actions, void* stream);
 
+/* vmas_rollout_backward for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, results and kernels, but the checkpoint
+ * workspace lives in a fixed 64 MiB device array inside the library (one
+ * per device, held until the process ends) instead of memory the handle
+ * allocates; the call itself allocates nothing. The workspace needs
+ * 6 N (ceil(T / k) + k + 3) floats (k = min(ckpt_every, T)); a larger need
+ * returns VMAS_ERR_INVALID_ARGUMENT before any device work. All calls on one
+ * device share that array and leave their data in it: calls that overlap in
+ * time on one device (different streams, threads or handles) race and must
+ * be serialised by the caller. With VMAS_DEBUG_NONFINITE the call
+ * synchronises its stream first, like every call of such a batch. */
+vmas_status vmas_rollout_backward_noalloc(vmas_batch* batch, const float* state0,
+                                          const float* actions, int32_t T, int32_t ckpt_every,
+                                          const float* grad_state_T, float* grad_state0,
+                                          float* grad_actions, void* stream);
+
 /* Launch plans. Plan ids are 0 .. n_schedules-1 (see vmas_schedule_name);
  * every plan computes the same results bit for bit. Names:
  * "entity-lane/<block>/<natural|size-sorted>" (a lane per entity that moves

@@ -26,7 +26,7 @@ EXPORTS = ("vmas_create_batch", "vmas_destroy_batch", "vmas_batch_get_info", "vm
            "vmas_autotune", "vmas_schedule_name", "vmas_rollout_graph", "vmas_last_error",
            "vmas_mlp_num_params", "vmas_mlp_create", "vmas_mlp_destroy", "vmas_mlp_get_params",
            "vmas_mlp_forward", "vmas_mlp_backward", "vmas_mlp_train_step", "vmas_pair_features",
-           "vmas_step_surrogate", "vmas_nonfinite_envs")
+           "vmas_step_surrogate", "vmas_nonfinite_envs", "vmas_rollout_backward_noalloc")
 
 VMAS_DEBUG_NONFINITE = 1
 
@@ -89,6 +89,7 @@ def lib():
     L.vmas_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.vmas_rollout_backward.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,
                                         vp]
+    L.vmas_rollout_backward_noalloc.argtypes = L.vmas_rollout_backward.argtypes
     L.vmas_set_schedule.argtypes = [vp, ctypes.c_int32]
     L.vmas_autotune.argtypes = [vp, vp, vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int32)]
     L.vmas_schedule_name.argtypes = [vp, ctypes.c_int32]
@@ -297,11 +298,14 @@ class Batch:
         return run
 
     def rollout_backward(self, state0, actions, grad_final, ckpt_every: int = 10,
-                         grad_state0=None, grad_actions=None) -> None:
+                         grad_state0=None, grad_actions=None, noalloc: bool = False) -> None:
+        """vmas_rollout_backward, or vmas_rollout_backward_noalloc (workspace
+        in the library's fixed device scratch) when noalloc is set."""
         import torch
         f = torch.float32
         T = actions.shape[0]
-        _check(lib().vmas_rollout_backward(
+        fn = lib().vmas_rollout_backward_noalloc if noalloc else lib().vmas_rollout_backward
+        _check(fn(
             self.handle, _dptr(state0, 6 * self.N, f, "state0"),
             _dptr(actions, T * 2 * self.A, f, "actions"), T, ckpt_every,
             _dptr(grad_final, 6 * self.N, f, "grad_state_T"),
@@ -436,6 +440,13 @@ def vmas_step_backward(batch: Batch, state_t, actions_t, grad_state_next, grad_s
 def vmas_rollout_backward(batch: Batch, state0, actions, grad_state_T, ckpt_every: int = 10,
                           grad_state0=None, grad_actions=None) -> None:
     batch.rollout_backward(state0, actions, grad_state_T, ckpt_every, grad_state0, grad_actions)
+
+
+def vmas_rollout_backward_noalloc(batch: Batch, state0, actions, grad_state_T,
+                                  ckpt_every: int = 10, grad_state0=None,
+                                  grad_actions=None) -> None:
+    batch.rollout_backward(state0, actions, grad_state_T, ckpt_every, grad_state0, grad_actions,
+                           noalloc=True)
 
 
 def vmas_autotune(batch: Batch, state, T: int = 10, actions=None) -> int:

@@ -24,6 +24,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1134,10 +1135,14 @@ vmas_status vmas_step_backward(vmas_batch* b, const float* state_t, const float*
                          (hipStream_t)stream);
 }
 
-vmas_status vmas_rollout_backward(vmas_batch* b, const float* state0, const float* actions,
-                                  int32_t T, int32_t ckpt_every, const float* grad_state_T,
-                                  float* grad_state0, float* grad_actions, void* stream) {
-  g_err.clear();
+}  // extern "C"
+
+namespace {
+
+// Arguments of a rollout adjoint, checked on the host; sets the workspace
+// size in floats.
+vmas_status backward_args(vmas_batch* b, const float* state0, const float* actions, int32_t T,
+                          int32_t ckpt_every, const float* grad_state_T, size_t* need) {
   if (check_batch(b) != VMAS_OK) return VMAS_ERR_INVALID_ARGUMENT;
   if (!state0 || !grad_state_T) return fail(VMAS_ERR_INVALID_ARGUMENT, "state0 and grad_state_T are required");
   if (T < 1) return fail(VMAS_ERR_INVALID_ARGUMENT, "T must be >= 1");
@@ -1145,27 +1150,22 @@ vmas_status vmas_rollout_backward(vmas_batch* b, const float* state0, const floa
   if (!actions && b->A > 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "actions must not be NULL");
   if (!b->back.valid)
     return fail(VMAS_ERR_UNSUPPORTED, "an environment is too large for the adjoint plan");
-  DeviceGuard guard(b->device);
-  hipStream_t s = (hipStream_t)stream;
-  vmas_status st0 = report_nonfinite(b, s);
-  if (st0 != VMAS_OK) return st0;
+  const int k = std::min(ckpt_every, T);
+  const int nseg = (T + k - 1) / k;
+  // nseg checkpoints, k + 1 states of the segment being replayed, two
+  // gradient buffers
+  *need = 6 * (size_t)b->N * ((size_t)nseg + (size_t)k + 1 + 2);
+  return VMAS_OK;
+}
+
+// The checkpointed adjoint on a workspace of backward_args' size.
+vmas_status backward_on(vmas_batch* b, float* ws, const float* state0, const float* actions,
+                        int32_t T, int32_t ckpt_every, const float* grad_state_T,
+                        float* grad_state0, float* grad_actions, hipStream_t s) {
   const int k = std::min(ckpt_every, T);
   const int nseg = (T + k - 1) / k;
   const size_t S6 = 6 * (size_t)b->N;
-  // workspace: nseg checkpoints, k + 1 states of the segment being replayed,
-  // two gradient buffers
-  const size_t need = S6 * ((size_t)nseg + (size_t)k + 1 + 2);
-  if (b->ws_floats < need) {
-    if (b->d_ws) (void)hipFree(b->d_ws);
-    b->d_ws = nullptr;
-    b->ws_floats = 0;
-    hipError_t e = hipMalloc((void**)&b->d_ws, need * sizeof(float));
-    if (e != hipSuccess)
-      return fail(VMAS_ERR_OUT_OF_MEMORY, "checkpoint workspace (%zu bytes): %s", need * sizeof(float),
-                  hipGetErrorString(e));
-    b->ws_floats = need;
-  }
-  float* ckpt = b->d_ws;
+  float* ckpt = ws;
   float* seg = ckpt + S6 * nseg;
   float* g0 = seg + S6 * (k + 1);
   float* g1 = g0 + S6;
@@ -1199,6 +1199,82 @@ vmas_status vmas_rollout_backward(vmas_batch* b, const float* state0, const floa
   if (grad_state0)
     HIPCHK(hipMemcpyAsync(grad_state0, g0, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
   return VMAS_OK;
+}
+
+// Fixed scratch of the allocation-free adjoint: SCRATCH_FLOATS floats in a
+// file-scope device array (each device the library runs on holds its own
+// copy until the process ends). Host code never passes the array's name to
+// a kernel or a copy: it takes the device address from hipGetSymbolAddress,
+// once per device (with that device current), and uses that.
+constexpr size_t SCRATCH_FLOATS = (size_t)16 << 20;  // 64 MiB
+__device__ __align__(256) float scratch[SCRATCH_FLOATS];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[MAX_DEVICES] = {};
+
+vmas_status scratch_of(int device, float** out) {
+  if (device < 0 || device >= MAX_DEVICES)
+    return fail(VMAS_ERR_UNSUPPORTED, "device %d: static scratch supports devices 0..%d", device,
+                MAX_DEVICES - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(VMAS_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return VMAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vmas_status vmas_rollout_backward(vmas_batch* b, const float* state0, const float* actions,
+                                  int32_t T, int32_t ckpt_every, const float* grad_state_T,
+                                  float* grad_state0, float* grad_actions, void* stream) {
+  g_err.clear();
+  size_t need = 0;
+  vmas_status st0 = backward_args(b, state0, actions, T, ckpt_every, grad_state_T, &need);
+  if (st0 != VMAS_OK) return st0;
+  DeviceGuard guard(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  if ((st0 = report_nonfinite(b, s)) != VMAS_OK) return st0;
+  if (b->ws_floats < need) {
+    if (b->d_ws) (void)hipFree(b->d_ws);
+    b->d_ws = nullptr;
+    b->ws_floats = 0;
+    hipError_t e = hipMalloc((void**)&b->d_ws, need * sizeof(float));
+    if (e != hipSuccess)
+      return fail(VMAS_ERR_OUT_OF_MEMORY, "checkpoint workspace (%zu bytes): %s", need * sizeof(float),
+                  hipGetErrorString(e));
+    b->ws_floats = need;
+  }
+  return backward_on(b, b->d_ws, state0, actions, T, ckpt_every, grad_state_T, grad_state0,
+                     grad_actions, s);
+}
+
+vmas_status vmas_rollout_backward_noalloc(vmas_batch* b, const float* state0, const float* actions,
+                                          int32_t T, int32_t ckpt_every, const float* grad_state_T,
+                                          float* grad_state0, float* grad_actions, void* stream) {
+  g_err.clear();
+  size_t need = 0;
+  vmas_status st = backward_args(b, state0, actions, T, ckpt_every, grad_state_T, &need);
+  if (st != VMAS_OK) return st;
+  if (need > SCRATCH_FLOATS)
+    return fail(VMAS_ERR_INVALID_ARGUMENT,
+                "the checkpoint workspace of %zu bytes exceeds the static scratch of %zu bytes "
+                "(6 N (ceil(T / k) + k + 3) floats must fit)",
+                need * sizeof(float), SCRATCH_FLOATS * sizeof(float));
+  DeviceGuard guard(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = report_nonfinite(b, s)) != VMAS_OK) return st;
+  float* ws = nullptr;
+  if ((st = scratch_of(b->device, &ws)) != VMAS_OK) return st;
+  return backward_on(b, ws, state0, actions, T, ckpt_every, grad_state_T, grad_state0,
+                     grad_actions, s);
 }
 
 vmas_status vmas_pair_features(vmas_batch* b, const float* state, float band,
