@@ -97,7 +97,7 @@ struct StepArgs {
   const QuadEnv* quad;       // [n_envs] quad schedule, or NULL
   const int32_t* env_off;    // [n_envs + 1] first entity of each environment
   int32_t n_envs;
-  int32_t pad;
+  int32_t quad_ordered;      // quad schedule whose movers are local 0..m-1 on lanes 0..m-1
   // pair-queue plans (batches with boxes or segments, environments of at
   // most 32 entities): queue capacity per pair class (sphere-box,
   // sphere-segment, box-box, box-segment, segment-segment) and their sum;
@@ -154,7 +154,7 @@ hipError_t launch_backward(const BackArgs& a, int groups, int block, bool sphere
 // Device function of the rollout kernel launched by launch_rollout (for
 // explicit graph construction) and its dynamic LDS size.
 const void* rollout_kernel(bool spheres_only, bool quad, bool pq, int block, int max_n,
-                           float min_dist, bool out);
+                           float min_dist, bool out, bool quad_ordered = false);
 size_t rollout_lds_bytes(int max_stage, bool spheres_only, bool quad, int pq_total, int pq_pairs,
                          int block, int max_n);
 // Rest lengths of the joints marked in from_state ([J], 1 = take the anchor

@@ -520,7 +520,10 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
 // a 64-bit hit mask. NB = 0: any size, 32 partners per pass. MD: the world has a nonzero minimum
 // distance. The arithmetic of a contact is the same, operation for operation,
 // in every variant and as the sphere path of k_rollout (pair_force on two spheres).
-constexpr int KCH = 8;
+#ifndef VMAS_KCH
+#define VMAS_KCH 8
+#endif
+constexpr int KCH = VMAS_KCH;
 
 template <int MAXB, int NB, bool MD, bool OUT>
 __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
@@ -1058,6 +1061,284 @@ __global__ void __launch_bounds__(256) k_rollout_quad(StepArgs a) {
   }
 }
 
+// Quad schedule with ordered partners, for sphere batches whose every
+// environment puts its (at most 4) movers first -- local indices 0 .. m-1 on
+// quad lanes 0 .. m-1 -- and its (at most NS) static collidable entities
+// after them (e.g. 4 agents and 2 landmarks). Partner slot k of quad lane q
+// is mover k + [k >= q], read with a quad permutation that serves slot k in
+// local-index order on every lane, and static s comes after all movers, so
+// the slots are in local-index order: contacts are added in the order every
+// other schedule uses, and a partner's values are never selected at run
+// time. Per step a lane tests its NS + 3 partners (the partner's centre is
+// used once, in the difference, where the compiler folds the permutation
+// into the subtraction), and a wavefront runs the contact code of slot k
+// only when some lane hit partner k (about a quarter of the wavefront-steps
+// of the 30,000-environment workload have a contact at all). The angular
+// update of a sphere is the identity while omega is +0 (no torque on a
+// sphere), so it is skipped for a wavefront whose angular velocities are
+// all +0 and whose angles hold no -0. Results are bitwise those of the other
+// sphere schedules.
+template <int CTRL>
+__device__ __forceinline__ float quad_src(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+
+template <bool MD, int NS, bool OUT>
+__global__ void __launch_bounds__(64) k_rollout_quad_ord(StepArgs a) {
+  const int gl = blockIdx.x * blockDim.x + threadIdx.x;
+  const int env = gl >> 2, qp = gl & 3;
+  const int N = a.w.N;
+  // Set-up in two rounds of independent loads (every load issued
+  // unconditionally from a valid index, the value selected afterwards): the
+  // environment's record and offsets, then the lane's own state and
+  // parameters and the static partners' centres, radii and flags. The
+  // movers' radii and flags come from their own lanes (quad permutations).
+  // The environment record is read as one 16-byte word and unpacked with
+  // shifts (no per-lane array, which the compiler would place in LDS).
+  const bool in = env < a.n_envs;
+  const int envc = in ? env : 0;
+  const int4 qw = reinterpret_cast<const int4*>(a.quad)[envc];
+  const int o = a.env_off[envc], n = a.env_off[envc + 1] - o;
+  const int agent_row = qw.x, n_agents = in ? qw.y : 0;
+  // local index of the mover on quad lane u (-1: idle) / of static u (-1: none)
+  auto lane_loc = [&](int u) { return in ? (int)(int8_t)((uint32_t)qw.z >> (8 * u)) : -1; };
+  auto stat_loc = [&](int u) { return in ? (int)(int8_t)((uint32_t)qw.w >> (8 * u)) : -1; };
+  const bool act = lane_loc(qp) >= 0;  // lane qp holds local entity qp
+  const int e = o + qp;
+  const int ec = act ? e : min(o, N - 1);  // a valid index for the loads
+  float x = a.state[ec], y = a.state[N + ec], vx = a.state[2 * N + ec],
+        vy = a.state[3 * N + ec], th = a.state[4 * N + ec], om = a.state[5 * N + ec];
+  EntParam p = a.ent[ec];
+  float srad[NS > 0 ? NS : 1], sx[NS > 0 ? NS : 1], sy[NS > 0 ? NS : 1];
+  int sfl[NS > 0 ? NS : 1], sloc[NS > 0 ? NS : 1];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    sloc[s] = stat_loc(s);
+    const int es = min(o + (sloc[s] >= 0 ? sloc[s] : 0), N - 1);
+    const float r = a.ent[es].rho;
+    const int sfv = a.ent[es].sf;
+    const float cx = a.state[es], cy = a.state[N + es];
+    srad[s] = r;
+    sfl[s] = sloc[s] >= 0 ? (sfv >> 8) & 0xff : 0;
+    sx[s] = cx;
+    sy[s] = cy;
+  }
+  if (!act) {
+    x = y = vx = vy = th = om = 0.0f;
+    p = EntParam{};
+  }
+  const int fl = (p.sf >> 8) & 0xff;
+  const bool movable = act && (fl & MOVABLE) != 0, rotatable = act && (fl & ROTATABLE) != 0;
+  const bool collide = act && (fl & COLLIDABLE) != 0;
+  const bool agent = act && qp < n_agents;
+  const WorldK w = a.w;
+  // slots 0..2: movers k + [k >= qp] (their radius and whether they collide
+  // from their lanes); slots 3..: statics. Contact distance squared (-1:
+  // never in contact), contact distance, local index.
+  constexpr int NP = 3 + NS;
+  float prad[3];
+  int pcol[3];
+  prad[0] = quad_src<0x01>(p.rho);
+  prad[1] = quad_src<0x5A>(p.rho);
+  prad[2] = quad_src<0xBF>(p.rho);
+  {
+    const float c = collide ? 1.0f : 0.0f;
+    pcol[0] = quad_src<0x01>(c) != 0.0f;
+    pcol[1] = quad_src<0x5A>(c) != 0.0f;
+    pcol[2] = quad_src<0xBF>(c) != 0.0f;
+  }
+  float dm2[NP], pdm[NP];
+  int ploc[NP];
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    int loc;
+    bool pc;
+    float pr;
+    if (u < 3) {
+      loc = u + (u >= qp ? 1 : 0);
+      pc = loc < 4 && lane_loc(loc) >= 0 && pcol[u];
+      pr = prad[u];
+    } else {
+      loc = sloc[u - 3];
+      pc = loc >= 0 && (sfl[u - 3] & COLLIDABLE);
+      pr = srad[u - 3];
+    }
+    ploc[u] = loc < 0 ? 255 : loc;
+    float dmin = p.rho + pr;
+    if (MD) dmin += w.min_dist;
+    const bool ok = collide && pc;
+    dm2[u] = ok ? __fmul_rn(dmin, dmin) : -1.0f;
+    pdm[u] = ok ? dmin : 0.0f;
+  }
+  const int T = a.T;
+  const size_t A = (size_t)w.A;
+  const int arow = agent ? agent_row + qp : 0;  // a lane without an action reads row 0
+  const bool drawn = a.actions == nullptr;  // uniform
+  const float2* ap = reinterpret_cast<const float2*>(a.actions) + arow;
+  // angles and angular velocities change only while some omega is not +0
+  // or some angle is -0 (see above); otherwise the update is the identity
+  const bool spin = __builtin_amdgcn_ballot_w64(rotatable && (__float_as_uint(om) != 0u ||
+                                                              __float_as_uint(th) == 0x80000000u)) != 0;
+  // a mover that is not an agent takes no action (zero force); otherwise
+  // every lane's action row is read as is
+  const bool mute = __builtin_amdgcn_ballot_w64(act && !agent) != 0;
+  // unit masses: f / m is f itself (x * 1 is exact), so the multiply goes
+  const bool unit = __builtin_amdgcn_ballot_w64(movable && p.inv_m != 1.0f) == 0;
+  // Actions of KCH steps per chunk, two chunks in flight (ping-pong, no
+  // register copies); rows past the rollout are clamped to its last row
+  // (read, never used), so every load is unconditional.
+  auto load_chunk = [&](float2* dst, int c) {
+    if (!drawn) {
+      if (A > 0) {
+#pragma unroll
+        for (int k = 0; k < KCH; ++k) dst[k] = ap[(size_t)min(c + k, T - 1) * A];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < KCH; ++k) {
+        const uint64_t base =
+            ((uint64_t)(a.t0 + min(c + k, T - 1)) * (uint64_t)w.A + (uint64_t)arow) * 2ull;
+        dst[k] = make_float2(draw_sym(a.key, base), draw_sym(a.key, base + 1));
+      }
+    }
+  };
+  auto run = [&](auto spin_tag, auto mute_tag, auto unit_tag) {
+    constexpr bool SPIN = decltype(spin_tag)::value, MUTE = decltype(mute_tag)::value;
+    constexpr bool UNIT = decltype(unit_tag)::value;
+    // one step with the actions f of step t
+    auto step = [&](float2 f, int t) {
+      if (MUTE && !agent) f = make_float2(0.0f, 0.0f);
+      float dx[NP], dy[NP], sq[NP];
+      bool hit[NP];
+      // movers in local order: lane q takes slot k from lane k + [k >= q]
+      dx[0] = x - quad_src<0x01>(x);  // quad_perm [1, 0, 0, 0]
+      dy[0] = y - quad_src<0x01>(y);
+      dx[1] = x - quad_src<0x5A>(x);  // quad_perm [2, 2, 1, 1]
+      dy[1] = y - quad_src<0x5A>(y);
+      dx[2] = x - quad_src<0xBF>(x);  // quad_perm [3, 3, 3, 2]
+      dy[2] = y - quad_src<0xBF>(y);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        dx[3 + s] = x - sx[s];
+        dy[3 + s] = y - sy[s];
+      }
+      bool any = false;
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        sq[u] = fmaf(dx[u], dx[u], __fmul_rn(dy[u], dy[u]));
+        hit[u] = sq[u] <= dm2[u];
+        any |= hit[u];
+      }
+      float fx = f.x + p.mgx, fy = f.y + p.mgy;
+      uint8_t* mk = (OUT && t == T - 1 && a.mask) ? a.mask : nullptr;
+      if (__builtin_amdgcn_ballot_w64(any) != 0) {
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+          if (hit[u]) {  // partner order: lowest local index first
+            const float rs = __frsqrt_rn(sq[u]);
+            float d = sq[u] * rs, nx = dx[u] * rs, ny = dy[u] * rs;
+            if (__builtin_amdgcn_ballot_w64(sq[u] == 0.0f) != 0) {  // coincident centres (rare)
+              const bool self_lo = u >= 3 || u >= qp;
+              if (sq[u] == 0.0f) {
+                d = 0.0f;
+                nx = self_lo ? 1.0f : -1.0f;
+                ny = 0.0f;
+              }
+            }
+            const float F = contact_mag(pdm[u], d, w);
+            fx = fmaf(F, nx, fx);
+            fy = fmaf(F, ny, fy);
+            if (mk) {
+              const int pl = ploc[u];
+              const int pf = u >= 3 ? sfl[u - 3] : fl;
+              if (qp < pl || (pf & (MOVABLE | ROTATABLE)) == 0) {
+                const int ia = min(qp, pl), ib = max(qp, pl);
+                const int64_t idx = (int64_t)ia * n - (int64_t)ia * (ia + 1) / 2 + (ib - ia - 1);
+                mk[a.pair_off[env] + idx] = 1;
+              }
+            }
+          }
+        }
+      }
+      if (OUT && t == T - 1 && a.forces && act) {
+        a.forces[e] = fx;
+        a.forces[N + e] = fy;
+        a.forces[2 * N + e] = 0.0f;
+      }
+      if (movable) {
+        const float ax = UNIT ? fx : fx * p.inv_m, ay = UNIT ? fy : fy * p.inv_m;
+        vx = fmaf(ax, w.dt, w.damp * vx);
+        vy = fmaf(ay, w.dt, w.damp * vy);
+        if (p.vmax > 0.0f) {
+          const float sp = sqrtf(fmaf(vx, vx, vy * vy));
+          if (sp > p.vmax) {
+            const float sc = p.vmax / sp;
+            vx *= sc;
+            vy *= sc;
+          }
+        }
+        x = fmaf(vx, w.dt, x);
+        y = fmaf(vy, w.dt, y);
+      }
+      if (SPIN && rotatable) {
+        om = fmaf(0.0f * p.inv_I, w.dt, w.damp * om);
+        th = fmaf(om, w.dt, th);
+      }
+      if (OUT && a.traj && act) {
+        float* out = a.traj + (size_t)(t + 1) * 6 * N;
+        out[e] = x;
+        out[N + e] = y;
+        out[2 * N + e] = vx;
+        out[3 * N + e] = vy;
+        out[4 * N + e] = th;
+        out[5 * N + e] = om;
+      }
+    };
+    float2 bufA[KCH], bufB[KCH];
+#pragma unroll
+    for (int k = 0; k < KCH; ++k) bufA[k] = bufB[k] = make_float2(0.0f, 0.0f);
+    load_chunk(bufA, 0);
+    for (int c = 0; c < T; c += 2 * KCH) {
+      load_chunk(bufB, c + KCH);
+#pragma unroll
+      for (int k = 0; k < KCH; ++k)
+        if (c + k < T) step(bufA[k], c + k);  // uniform
+      if (c + KCH >= T) break;
+      load_chunk(bufA, c + 2 * KCH);
+#pragma unroll
+      for (int k = 0; k < KCH; ++k)
+        if (c + KCH + k < T) step(bufB[k], c + KCH + k);
+    }
+  };
+  if (T > 0) {
+    // the wavefront-uniform special cases, each its own instance of the loop
+    // (the general instance is correct for every wavefront: with spin set the
+    // angular update of a wavefront at rest is the identity, with mute set an
+    // agent keeps its action, a mass of 1 divides exactly); launches with
+    // outputs take the general instance only
+    using Y = std::true_type;
+    using Nn = std::false_type;
+    if (OUT) {
+      run(Y{}, Y{}, Nn{});
+    } else if (spin || mute) {
+      if (spin && mute) run(Y{}, Y{}, Nn{});
+      else if (spin) run(Y{}, Nn{}, Nn{});
+      else run(Nn{}, Y{}, Nn{});
+    } else {
+      if (unit) run(Nn{}, Nn{}, Y{});
+      else run(Nn{}, Nn{}, Nn{});
+    }
+  }
+  if (act && T > 0) {
+    a.state[e] = x;
+    a.state[N + e] = y;
+    a.state[2 * N + e] = vx;
+    a.state[3 * N + e] = vy;
+    a.state[4 * N + e] = th;
+    a.state[5 * N + e] = om;
+  }
+}
+
 // Partner-slot bound of the sphere kernel for a plan whose largest
 // environment has max_n entities (0: the any-size loop).
 int sph_nb(int max_n) {
@@ -1085,6 +1366,15 @@ const void* sph_kernel256(int nb, bool md, bool out) {
     case 64: return sph_pick<256, 64>(md, out);
     default: return sph_pick<256, 0>(md, out);
   }
+}
+
+template <int NS>
+const void* quad_ord_pick(bool md, bool out) {
+  if (md)
+    return out ? (const void*)k_rollout_quad_ord<true, NS, true>
+               : (const void*)k_rollout_quad_ord<true, NS, false>;
+  return out ? (const void*)k_rollout_quad_ord<false, NS, true>
+             : (const void*)k_rollout_quad_ord<false, NS, false>;
 }
 
 template <int NS>
@@ -1176,9 +1466,12 @@ int grid_for(int64_t n) {
 int sph_pad(int block, int max_n) { return block <= 256 ? sph_nb(max_n) : 0; }
 
 const void* rollout_kernel(bool spheres_only, bool quad, bool pq, int block, int max_n,
-                           float min_dist, bool out) {
+                           float min_dist, bool out, bool quad_ordered) {
   const bool md = min_dist != 0.0f;
   // quad: max_n carries the most static collidable entities of an environment
+  if (quad && quad_ordered)
+    return max_n == 0 ? quad_ord_pick<0>(md, out)
+                      : (max_n <= 2 ? quad_ord_pick<2>(md, out) : quad_ord_pick<4>(md, out));
   if (quad) return max_n <= 2 ? quad_pick<2>(md, out) : quad_pick<4>(md, out);
   if (spheres_only)
     return block > 256 ? sph_pick<1024, 0>(md, out) : sph_kernel256(sph_pad(block, max_n), md, out);
@@ -1202,7 +1495,8 @@ hipError_t launch_rollout(const StepArgs& a, int groups, int block, bool spheres
   const bool quad = a.quad != nullptr;
   const bool out = a.traj || a.mask || a.forces;
   const int pq_total = a.pq_cap[PQ_CLASSES];
-  const void* f = rollout_kernel(spheres_only, quad, pq_total > 0, block, a.max_n, a.w.min_dist, out);
+  const void* f = rollout_kernel(spheres_only, quad, pq_total > 0, block, a.max_n, a.w.min_dist, out,
+                                 a.quad_ordered != 0);
   const size_t shm =
       rollout_lds_bytes(a.max_stage, spheres_only, quad, pq_total, a.pq_max_pairs, block, a.max_n);
   StepArgs args = a;

@@ -64,6 +64,7 @@ struct Plan {
   int max_stage = 0;
   int max_n = 0;  // largest environment of the plan
   bool quad = false;          // quad schedule (d_quad), no lane records
+  bool quad_ordered = false;  // quad schedule with movers at local 0..m-1 (ordered partners)
   bool pq = false;            // pair-queue variant of the entity-lane kernel
   int32_t pq_cap[6] = {0, 0, 0, 0, 0, 0};  // queue capacity per pair class, then the sum
   uint32_t* d_pq_pairs = nullptr;   // eligible pairs of each group
@@ -478,10 +479,11 @@ vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8
 // most 4 entities that move or rotate, at most 4 static collidable ones and
 // at most 32 entities); p.valid stays false when the batch does not qualify.
 vmas_status build_quad_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8_t>& flags,
-                            Plan& p) {
-  p.name = "quad/256";
-  p.block = 256;
+                            Plan& p, bool ordered = false) {
+  p.name = ordered ? "quad-ordered/64" : "quad/256";
+  p.block = ordered ? 64 : 256;
   p.quad = true;
+  p.quad_ordered = ordered;
   p.valid = false;
   if (!b->spheres_only) return VMAS_OK;
   const int E = b->n_envs;
@@ -499,6 +501,7 @@ vmas_status build_quad_plan(vmas_batch* b, const HostDesc& h, const std::vector<
       const uint8_t f = flags[o + i];
       if (f & (MOVABLE | ROTATABLE)) {
         if (nl == 4) return VMAS_OK;
+        if (ordered && i != nl) return VMAS_OK;  // movers must be local 0 .. m-1
         r.lane_loc[nl++] = (int8_t)i;
       } else if (f & COLLIDABLE) {
         if (nsx == 4) return VMAS_OK;
@@ -510,7 +513,7 @@ vmas_status build_quad_plan(vmas_batch* b, const HostDesc& h, const std::vector<
   if ((int64_t)E * 4 > INT32_MAX - 256) return VMAS_OK;
   vmas_status s = upload(&p.d_quad, q.data(), q.size());
   if (s != VMAS_OK) return s;
-  p.groups = (int)(((int64_t)E * 4 + 255) / 256);
+  p.groups = (int)(((int64_t)E * 4 + p.block - 1) / p.block);
   p.max_n = max_static;  // the quad kernels size their static slots by it
   p.valid = E > 0;
   return VMAS_OK;
@@ -530,6 +533,7 @@ StepArgs make_args(vmas_batch* b, const Plan& p) {
   a.max_stage = p.max_stage;
   a.max_n = p.max_n;
   a.quad = p.quad ? p.d_quad : nullptr;
+  a.quad_ordered = p.quad_ordered ? 1 : 0;
   a.env_off = b->d_env_off;
   a.n_envs = b->n_envs;
   for (int c = 0; c < 6; ++c) a.pq_cap[c] = p.pq ? p.pq_cap[c] : 0;
@@ -826,9 +830,9 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
       }
     }
   }
-  {
+  for (int ordered = 0; ordered < 2; ++ordered) {
     Plan p;
-    if ((s = build_quad_plan(b, h, flags, p)) != VMAS_OK) {
+    if ((s = build_quad_plan(b, h, flags, p, ordered != 0)) != VMAS_OK) {
       free_plan(p);
       free_batch(b);
       return s;
@@ -993,7 +997,8 @@ vmas_status vmas_rollout_graph(vmas_batch* b, float* state, const float* actions
   void* args[1] = {&a};
   hipKernelNodeParams kp{};
   kp.func = const_cast<void*>(
-      rollout_kernel(b->spheres_only, p.quad, p.pq, p.block, p.max_n, b->w.min_dist, false));
+      rollout_kernel(b->spheres_only, p.quad, p.pq, p.block, p.max_n, b->w.min_dist, false,
+                     p.quad_ordered));
   kp.gridDim = dim3(p.groups);
   kp.blockDim = dim3(p.block);
   kp.sharedMemBytes = (unsigned)rollout_lds_bytes(p.max_stage, b->spheres_only, p.quad,

@@ -1,5 +1,6 @@
-"""The quad schedule (the movers of an environment on one aligned lane quad,
-partner centres by DPP, static partners in registers, no LDS) against the
+"""The quad schedules (the movers of an environment on one aligned lane
+quad, partner centres by DPP, static partners in registers, no LDS; the
+ordered variant for environments whose movers come first) against the
 entity-lane schedule, bit for bit: final state, trajectory, final contact
 mask and forces, with given and in-kernel actions, idle lanes, zero to four
 static entities, a static entity that does not collide, a minimum distance
@@ -15,6 +16,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 QUAD = "quad/256"
+QUADS = ["quad/256", "quad-ordered/64"]
 
 
 def _dev(a, dtype=torch.float32):
@@ -30,13 +32,25 @@ def _worlds():
     fl[2::5] = 0  # the first landmark of every environment takes no part
     odd = dataclasses.replace(odd, flags=fl, min_dist=0.01,
                               max_speed=np.full(odd.n_entities, 0.5, np.float32))
-    return {"dense": dense, "idle": idle, "ragged": ragged, "odd": odd}
+    # spinning spheres (omega != 0, angles that turn) of unequal masses, and
+    # environments whose last movers are not agents (no action)
+    spin = W.spread(300, 4, 2, radius=0.15, seed=5)
+    st = spin.state0.copy()
+    rng = np.random.default_rng(5)
+    st[5] = rng.uniform(-2, 2, spin.n_entities).astype(np.float32)
+    st[4] = rng.uniform(-3, 3, spin.n_entities).astype(np.float32)
+    spin = dataclasses.replace(spin, state0=st,
+                               mass=rng.uniform(0.5, 2.0, spin.n_entities).astype(np.float32))
+    mute = W.spread(300, 4, 2, radius=0.15, seed=6)
+    mute = dataclasses.replace(mute, n_agents=np.full(300, 2, np.int32))
+    return {"dense": dense, "idle": idle, "ragged": ragged, "odd": odd, "spin": spin,
+            "mute": mute}
 
 
-def _schedules(b):
+def _schedules(b, quad=QUAD):
     names = {b.schedule_name(q): q for q in range(b.n_schedules)}
-    assert QUAD in names, names
-    return names[QUAD], 0
+    assert quad in names, names
+    return names[quad], 0
 
 
 def _run(b, w, q, T, drawn):
@@ -56,13 +70,14 @@ def _run(b, w, q, T, drawn):
     return s, traj, mk, s1, m1, f1
 
 
-@pytest.mark.parametrize("name", ["dense", "idle", "ragged", "odd"])
+@pytest.mark.parametrize("quad", QUADS)
+@pytest.mark.parametrize("name", ["dense", "idle", "ragged", "odd", "spin", "mute"])
 @pytest.mark.parametrize("drawn", [False, True])
-def test_quad_schedule_bitwise_equals_lane_schedule(name, drawn):
+def test_quad_schedule_bitwise_equals_lane_schedule(name, drawn, quad):
     from paper_2207_03530_amd import binding as B
     w = _worlds()[name]
     b = B.Batch(w, 0)
-    q_quad, q_lane = _schedules(b)
+    q_quad, q_lane = _schedules(b, quad)
     print(f"{name}: {w.n_envs} envs, {w.n_entities} entities, drawn={drawn}", flush=True)
     ref = _run(b, w, q_lane, 40, drawn)
     out = _run(b, w, q_quad, 40, drawn)
@@ -72,11 +87,12 @@ def test_quad_schedule_bitwise_equals_lane_schedule(name, drawn):
     assert int(ref[2].sum()) > 0  # contacts happened
 
 
-def test_quad_schedule_graph_replay():
+@pytest.mark.parametrize("quad", QUADS)
+def test_quad_schedule_graph_replay(quad):
     from paper_2207_03530_amd import binding as B
     w = _worlds()["dense"]
     b = B.Batch(w, 0)
-    q_quad, q_lane = _schedules(b)
+    q_quad, q_lane = _schedules(b, quad)
     acts = _dev(w.actions(24))
     b.set_schedule(q_lane)
     ref = _dev(w.state0)
@@ -98,3 +114,13 @@ def test_quad_schedule_offered_only_where_it_fits():
         b = B.Batch(w, 0)
         names = [b.schedule_name(q) for q in range(b.n_schedules)]
         assert (QUAD in names) == ok, (w.name, names)
+        assert ("quad-ordered/64" in names) == ok, (w.name, names)
+    # movers not first: the quad schedule fits, the ordered one does not
+    w = W.spread(40, 4, 2, seed=1)
+    fl = w.flags.copy()
+    fl[0::6] = W.COLLIDABLE
+    fl[4::6] = W.MOVABLE | W.ROTATABLE | W.COLLIDABLE
+    w = dataclasses.replace(w, flags=fl)
+    b = B.Batch(w, 0)
+    names = [b.schedule_name(q) for q in range(b.n_schedules)]
+    assert QUAD in names and "quad-ordered/64" not in names, names
