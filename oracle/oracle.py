@@ -18,7 +18,9 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# VMAS_ORACLE_LIB selects another build of the same source (the sanitizer
+# build of oracle/build.py --sanitize)
+LIB_PATH = os.environ.get("VMAS_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 _lib = None
 

@@ -14,7 +14,9 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvmas.so")
+# VMAS_LIB selects another build of the same sources (the host-sanitizer
+# build of `python -m paper_2207_03530_amd.build --sanitize`)
+LIB_PATH = os.environ.get("VMAS_LIB") or os.path.join(HERE, "libvmas.so")
 
 VMAS_OK = 0
 STATUS = {0: "VMAS_OK", 1: "VMAS_ERR_INVALID_ARGUMENT", 2: "VMAS_ERR_OUT_OF_MEMORY",

@@ -18,6 +18,13 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.normpath(os.path.join(HERE, "..", "include"))
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvmas.so")
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build of the C
+# boundary (argument validation, plan building): --sanitize. Device code is
+# built as usual (each -fsanitize= applies to the host pass only).
+LIB_SAN = os.path.join(HERE, "libvmas_san.so")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer",
+             "-g"]
 SOURCES = ["vmas_runtime.hip", "vmas_kernels.hip", "vmas_backward.hip", "vmas_mlp.hip",
            "vmas_mlp_api.hip", "vmas_surrogate.hip"]
 ARCH = os.environ.get("VMAS_OFFLOAD_ARCH", "gfx950")
@@ -39,14 +46,31 @@ def _headers():
     return hs
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + FLAGS + ["-c", "-o", obj + ".tmp", os.path.join(CSRC, src)]
+def _compile(src: str, verbose: bool, sanitize: bool = False) -> str:
+    obj = os.path.join(OBJ, os.path.splitext(src)[0] + (".san.o" if sanitize else ".o"))
+    cmd = [hipcc()] + FLAGS + (SAN_FLAGS if sanitize else []) + ["-c", "-o", obj + ".tmp",
+                                                                 os.path.join(CSRC, src)]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(obj + ".tmp", obj)
     return obj
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """libvmas_san.so: the host code of the C boundary under ASan and UBSan
+    (the runtime source; the kernel sources are linked from the plain
+    build's objects, which build() must have made)."""
+    os.makedirs(OBJ, exist_ok=True)
+    san = _compile("vmas_runtime.hip", verbose, sanitize=True)
+    objs = [san] + [os.path.join(OBJ, os.path.splitext(s)[0] + ".o") for s in SOURCES[1:]]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host",
+           "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-o", LIB_SAN + ".tmp"] + objs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_SAN + ".tmp", LIB_SAN)
+    return LIB_SAN
 
 
 def build(verbose: bool = False, incremental: bool = False) -> str:
@@ -73,5 +97,8 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True, incremental="--incremental" in sys.argv[1:])
+    if "--sanitize" in sys.argv[1:]:
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True, incremental="--incremental" in sys.argv[1:])
     sys.exit(0)
