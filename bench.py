@@ -17,6 +17,25 @@ the FP64 CPU oracle timed on the host cores on the same workload.
 environments of 16 sphere agents (r = 0.03), 4 boxes (0.1 x 0.3) and 8
 segments (length 0.5), all movable and rotatable, two joints each, one
 200-step rollout per bench step; its roofline is the FP32 vector peak.
+
+--workload uneven16384: 16,384 environments of 2..64 sphere agents
+(r = 0.05, uniform counts), one 500-step rollout per bench step replayed
+from the rollout graph with the actions drawn in the kernel; FP32 vector
+roofline by the model count (5 FLOP per pair test, 16 per agent update).
+
+--workload adjoint16384: the same batch, one 50-step rollout adjoint per
+bench step (checkpoints every 10 steps: the forward replays and the reverse
+steps), actions from HBM, the gradient of sum |x_T|^2 seeded as 2 x_T.
+
+--workload surrogate65536: the learned contact surrogate. The network is
+trained on the GPU (its own kernels) on pair samples of exact rollouts, then
+the surrogate step and the exact step run from the same states of an exact
+trajectory of 65,536 environments x 16 sphere agents (r = 0.03) at three
+fallback fractions; the line reports the surrogate's speed relative to the
+exact step at the largest fraction whose contact-force error stays within
+1e-2 at every step, the network kernel's BF16 matrix-core roofline, and the
+same comparison on the mixed 4,096-environment batch (box pairs through
+the network, segment pairs exact).
 """
 import argparse
 import hashlib
@@ -54,6 +73,10 @@ STATIC_PER_ENTITY = 12
 # segment-box 32 x 150, box-box 6 x 200 (11,900), integration 28 x 16 and
 # box/segment geometry 12 x 20.
 MIXED_FLOP_PER_ENV_STEP = 12600
+# Model FLOP count of the uneven sphere workload: 5 per pair test, 16 per
+# agent update (the survey's count for sphere batches).
+UNEVEN_FLOP_PER_PAIR = 5
+UNEVEN_FLOP_PER_AGENT = 16
 
 
 def kernel_sha() -> str:
@@ -74,6 +97,8 @@ def kernel_of(schedule: str, spheres_only: bool = True) -> str:
     """Device function that runs a rollout under the given schedule."""
     if not spheres_only:
         return "k_rollout"
+    if schedule.startswith("quad-ordered"):
+        return "k_rollout_quad_ord"
     return "k_rollout_quad" if schedule.startswith("quad") else "k_rollout_sph"
 
 
@@ -121,12 +146,98 @@ def cpu_baseline(w, acts, T):
                                       f"median {sec1:.3f} s"}}
 
 
+MLP_FLOP_PER_ROW = 2 * (12 * 128 + 128 * 128 + 128 * 2)  # the three products of one row
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def surrogate_bench(args):
+    """The surrogate workload (see the module docstring): one JSON line."""
+    import torch
+    from paper_2207_03530_amd import binding as B, surrogate as S, workloads as W
+    t = time.perf_counter()
+    X, Y = S.training_set([
+        S.make_dataset(W.mixed(16384, seed=21), T=600, stride=1, max_samples=6_000_000),
+        S.make_dataset(W.uneven(65536, lo=16, hi=16, radius=0.03, seed=22), T=300, stride=1,
+                       max_samples=4_000_000)])
+    t_data = time.perf_counter() - t
+    net = B.Mlp(seed=0)
+    t = time.perf_counter()
+    hist = S.train(net, X, Y, epochs=300, batch=8192, lr=3e-3, lr_final=1e-5)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t
+    print(f"surrogate: {X.shape[0]} samples in {t_data:.1f} s, trained in {t_train:.1f} s, "
+          f"loss {hist[0]:.4g} -> {hist[-1]:.4g}", file=sys.stderr, flush=True)
+    reps = max(5, args.steps)
+    results = {}
+    for name, w in (("spheres65536x16", S.inference_world(65536)), ("mixed4096", W.mixed(4096))):
+        rows = []
+        for frac in (0.5, 0.25, 0.1):
+            errs, fbs = S.contact_force_error(w, net, steps=5, fallback=frac)
+            times = S.time_steps(w, net, reps=reps, fallback=frac)
+            rows.append({"fallback_frac": frac, "max_rel_force_err": float(np.max(errs)),
+                         "rel_force_err_per_step": [round(float(e), 5) for e in errs],
+                         "exact_ms": times["exact"], "surrogate_ms": times["surrogate"],
+                         "speed_vs_exact": times["exact"] / times["surrogate"]})
+            print(f"{name} fallback {frac}: err {np.round(errs, 4)}, exact {times['exact']:.4f} ms, "
+                  f"surrogate {times['surrogate']:.4f} ms", file=sys.stderr, flush=True)
+        results[name] = rows
+    # the network kernel alone on as many rows as the sphere batch has candidates
+    w = S.inference_world(65536)
+    b = B.Batch(w, 0)
+    st = torch.as_tensor(w.state0).cuda().contiguous()
+    fl = torch.zeros(b.P, dtype=torch.uint8, device="cuda:0")
+    fb = torch.zeros(b.P, 12, device="cuda:0")
+    b.pair_features(st, fb, fl, band=S.BAND)
+    n_cand = int((fl & 1).sum())
+    b.close()
+    n_rows = max(n_cand, 1 << 20)
+    Xr = X[:n_rows].contiguous() if X.shape[0] >= n_rows else X.repeat(n_rows // X.shape[0] + 1, 1)[:n_rows].contiguous()
+    Yr = torch.zeros(n_rows, 2, device="cuda:0")
+    for _ in range(3):
+        net.forward(Xr, Yr)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        net.forward(Xr, Yr)
+    e1.record()
+    torch.cuda.synchronize()
+    mlp_ms = e0.elapsed_time(e1) / reps
+    achieved = MLP_FLOP_PER_ROW * n_rows / (mlp_ms * 1e-3) / 1e12
+    sph = results["spheres65536x16"]
+    within = [r for r in sph if r["max_rel_force_err"] <= 1e-2]
+    best = within[0] if within else None
+    out = {
+        "metric": "surrogate step speed relative to the exact step at <= 1e-2 relative "
+                  "contact-force error (65,536 envs x 16 sphere agents)",
+        "value": best["speed_vs_exact"] if best else None,
+        "unit": "x exact step",
+        "n_gpus": 1, "steps": reps, "warmup": 3,
+        "ms_per_step": best["surrogate_ms"] if best else None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 (network) / f32 (step)", "data": "synthetic",
+        "config": {"workload": "surrogate65536: 12-128-128-2 MLP trained on the GPU on exact "
+                               "pair samples, surrogate step vs exact step from the same states",
+                   "n_envs": 65536, "agents_per_env": 16, "fallback_frac":
+                       best["fallback_frac"] if best else None,
+                   "training_samples": int(X.shape[0]), "training_s": round(t_train, 1)},
+        "surrogate": results,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_mlp_infer", "kernel_ms": mlp_ms, "rows": n_rows,
+                     "algorithmic_flop_per_row": MLP_FLOP_PER_ROW,
+                     "candidate_rows_per_step": n_cand},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", choices=("spread30000", "mixed4096"), default="spread30000")
+    ap.add_argument("--workload", choices=("spread30000", "mixed4096", "uneven16384", "adjoint16384",
+                                           "surrogate65536"), default="spread30000")
     ap.add_argument("--envs", type=int, default=None,
                     help="environments (default 30000 spread, 4096 mixed)")
     ap.add_argument("--T", type=int, default=None, help="rollout length (default 100 spread, 200 mixed)")
@@ -148,9 +259,20 @@ def main():
     import torch
     from paper_2207_03530_amd import binding, workloads as W
 
+    if args.workload == "surrogate65536":
+        return surrogate_bench(args)
     mixed = args.workload == "mixed4096"
-    T = args.T or (200 if mixed else 100)
-    w = W.mixed(args.envs or 4096) if mixed else W.spread(args.envs or 30000)
+    uneven = args.workload in ("uneven16384", "adjoint16384")
+    adjoint = args.workload == "adjoint16384"
+    if uneven:
+        T = args.T or (50 if adjoint else 500)
+        w = W.uneven(args.envs or 16384, lo=2, hi=64, seed=0)
+        if not adjoint:
+            args.graph = True
+            args.drawn_actions = True
+    else:
+        T = args.T or (200 if mixed else 100)
+        w = W.mixed(args.envs or 4096) if mixed else W.spread(args.envs or 30000)
     acts_np = w.actions(T)
     dev = torch.device("cuda", 0)
     batch = binding.vmas_create_batch(w, 0)
@@ -183,8 +305,17 @@ def main():
               f"{2 * src.numel() * 4 / sec / 1e9:.0f} GB/s (read + write)",
               file=sys.stderr, flush=True)
 
-    # one step = one T-step rollout of the whole batch; arguments marshalled once
-    if args.drawn_actions:
+    # one step = one T-step rollout of the whole batch (for adjoint16384 one
+    # rollout adjoint); arguments marshalled once
+    if adjoint:
+        s0 = state.clone()
+        gT = torch.zeros_like(state)
+        gs = torch.zeros_like(state)
+        ga = torch.zeros_like(acts)
+
+        def one_step():
+            batch.rollout_backward(s0, acts, gT, 10, gs, ga)
+    elif args.drawn_actions:
         one_step = batch.prepare_rollout(state, None, T=T, seed=w.seed, graph=args.graph)
     else:
         one_step = batch.prepare_rollout(state, acts, graph=args.graph)
@@ -210,11 +341,39 @@ def main():
     value = agent_steps / (ms_per_step * 1e-3)
 
     kernel = kernel_of(batch.schedule_name(plan), not mixed)
-    tag = "mixed4096" if mixed else "spread30k"
+    if adjoint:
+        kernel = "k_step_backward"
+    tag = "mixed4096" if mixed else ("uneven16384" if uneven else "spread30k")
     default_size = w.n_envs == (4096 if mixed else 30000) and T == (200 if mixed else 100)
     traffic = (traffic_per_launch(kernel, tag)
                if not (args.drawn_actions or args.graph) and default_size else None)
-    if mixed:
+    if uneven:
+        n = np.diff(w.env_offset).astype(np.int64)
+        pairs = int((n * (n - 1) // 2).sum())
+        # model count per step: 5 FLOP per pair test, 16 per agent update;
+        # the adjoint counts its forward replays (one per step) and its
+        # reverse step at twice the forward work (value and three tangents
+        # on the contacting pairs only, the reverse of the update)
+        flop_step = UNEVEN_FLOP_PER_PAIR * pairs + UNEVEN_FLOP_PER_AGENT * w.n_agents_total
+        flop = flop_step * T * (3 if adjoint else 1)
+        achieved = flop / (kernel_ms * 1e-3) / 1e12
+        roofline = {
+            "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+            "kernel": kernel, "kernel_ms": kernel_ms, "algorithmic_flop_per_launch": flop,
+            "algorithmic_flop_per_env_step": flop / (w.n_envs * T),
+        }
+        if adjoint:
+            workload = (f"adjoint{w.n_envs}: {w.n_envs} envs x 2..64 sphere agents, backward of "
+                        f"sum |x_T|^2 through a {T}-step rollout, checkpoints every 10 steps")
+            metric = f"agent-steps/s of the {T}-step rollout adjoint at {w.n_envs} uneven envs"
+        else:
+            workload = (f"uneven{w.n_envs}: {w.n_envs} envs x 2..64 sphere agents, one {T}-step "
+                        f"rollout per step replayed from the rollout graph, actions drawn in-kernel")
+            metric = f"agent-steps/s at {w.n_envs} uneven envs (2..64 agents)"
+        shape = {"n_envs": w.n_envs, "agents_per_env": "2..64 (uniform)",
+                 "pair_slots": pairs}
+    elif mixed:
         flop = MIXED_FLOP_PER_ENV_STEP * w.n_envs * T
         achieved = flop / (kernel_ms * 1e-3) / 1e12
         roofline = {

@@ -154,7 +154,7 @@ typedef struct {
   int32_t schedule;      /* current launch plan id (see vmas_set_schedule) */
   int32_t n_schedules;   /* number of launch plans available */
   int32_t max_env_size;  /* largest n_b */
-  int32_t reserved;
+  int32_t tune_cached;   /* 1: the last vmas_autotune took its choice from the cache */
 } vmas_batch_info;
 
 /* Creates a batch on HIP device `device`: validates the description, copies
@@ -246,14 +246,27 @@ vmas_status vmas_rollout_backward_noalloc(vmas_batch* batch, const float* state0
  * or size order), "pair-queue/<block>/<order>" (batches with boxes or
  * segments, environments of at most 32 entities: every pair tested and
  * evaluated once from LDS queues), "quad/256" (sphere batches with at most 4
- * movers and 4 static collidable entities per environment); "" for an id
- * whose plan does not fit the batch. vmas_autotune times each
- * plan on a T-step rollout of a scratch copy of `state` (state itself is not
- * modified) with the given actions (device float32 [T][A][2]; NULL: actions
- * drawn in the kernel, seed 12345): about 20 ms of warm-up on the current
- * plan, then three rounds over all plans with two timed runs each; a plan's
- * time is its fastest run, and a later plan replaces the current choice
- * only when it is at least 3 % faster. Returns the plan id in *chosen (and makes it
+ * movers and 4 static collidable entities per environment),
+ * "quad-ordered/64" (the same when the movers are the first entities of
+ * every environment), "bucketed/<lo>-<hi>:<plan>/..." (sphere batches whose
+ * environment sizes span several of the buckets 1-4, 5-8, 9-16, 17-32,
+ * 33-64, 65-: every bucket runs its own plan, chosen per bucket, and the
+ * buckets' launches run at the same time on side streams of the handle,
+ * joined back into the caller's stream); "" for an id whose plan does not
+ * fit the batch. vmas_autotune first times, for every size bucket, each
+ * candidate plan on that bucket alone and chooses per bucket, then times
+ * each plan on a T-step rollout of a scratch copy of `state` (state itself
+ * is not modified) with the given actions (device float32 [T][A][2]; NULL:
+ * actions drawn in the kernel, seed 12345): about 20 ms of warm-up on the
+ * current plan, then three rounds over all plans with two timed runs each;
+ * a plan's time is its fastest run, and a later plan replaces the current
+ * choice only when it is at least 3 % faster. The choice is cached in the
+ * process, keyed by the device architecture, the histogram of environment
+ * shapes (size, movers, static collidables) and the rollout length rounded
+ * up to a power of two; a later batch of the same key takes it without
+ * timing (vmas_batch_info.tune_cached). With the environment variable
+ * VMAS_AUTOTUNE_CACHE naming a file, the cache is also read from and
+ * appended to that file. Returns the plan id in *chosen (and makes it
  * current). It synchronises the stream; it allocates one state-sized scratch
  * buffer for the duration of the call. */
 vmas_status vmas_set_schedule(vmas_batch* batch, int32_t schedule);

@@ -65,7 +65,7 @@ class BatchInfo(ctypes.Structure):
                 ("n_agents", ctypes.c_int32), ("n_joints", ctypes.c_int32),
                 ("n_pair_slots", ctypes.c_int64), ("schedule", ctypes.c_int32),
                 ("n_schedules", ctypes.c_int32), ("max_env_size", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("tune_cached", ctypes.c_int32)]
 
 
 _lib = None

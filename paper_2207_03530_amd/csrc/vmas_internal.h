@@ -109,7 +109,9 @@ struct StepArgs {
   const uint32_t* pq_pairs;
   const int32_t* pq_pair_off;  // [groups + 1]
   int32_t pq_max_pairs;        // most pairs of one group (at most 32 x block)
-  int32_t pad2;
+  int32_t n_list;              // quad schedules: environments in env_list
+  const int32_t* env_list;     // quad schedules on a subset of the environments
+                               // ([n_list] environment ids), or NULL: all
   WorldK w;
 };
 

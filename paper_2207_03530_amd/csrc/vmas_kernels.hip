@@ -862,19 +862,22 @@ __device__ __forceinline__ float quad_perm(float v) {
 template <bool MD, int NS, bool OUT>
 __global__ void __launch_bounds__(256) k_rollout_quad(StepArgs a) {
   const int gl = blockIdx.x * blockDim.x + threadIdx.x;
-  const int env = gl >> 2, qp = gl & 3;
+  const int qi = gl >> 2, qp = gl & 3;
+  const bool in = qi < (a.env_list ? a.n_list : a.n_envs);
+  const int env = in ? (a.env_list ? a.env_list[qi] : qi) : 0;
   const int N = a.w.N;
-  QuadEnv Q;
-  Q.agent_row = 0;
-  Q.n_agents = 0;
-  for (int u = 0; u < 4; ++u) Q.lane_loc[u] = Q.stat_loc[u] = -1;
+  // the environment record as one 16-byte word, unpacked with shifts (no
+  // per-lane array, which the compiler would place in LDS)
+  int4 qw = make_int4(0, 0, -1, -1);
   int o = 0, n = 0;
-  if (env < a.n_envs) {
-    Q = a.quad[env];
+  if (in) {
+    qw = reinterpret_cast<const int4*>(a.quad)[env];
     o = a.env_off[env];
     n = a.env_off[env + 1] - o;
   }
-  const int myloc = Q.lane_loc[qp];
+  auto lane_loc = [&](int u) { return (int)(int8_t)((uint32_t)qw.z >> (8 * u)); };
+  auto stat_loc = [&](int u) { return (int)(int8_t)((uint32_t)qw.w >> (8 * u)); };
+  const int myloc = lane_loc(qp);
   const bool act = myloc >= 0;
   const int e = o + myloc;
   float x = 0, y = 0, vx = 0, vy = 0, th = 0, om = 0;
@@ -891,7 +894,7 @@ __global__ void __launch_bounds__(256) k_rollout_quad(StepArgs a) {
   const int fl = (p.sf >> 8) & 0xff;
   const bool movable = act && (fl & MOVABLE) != 0, rotatable = act && (fl & ROTATABLE) != 0;
   const bool collide = act && (fl & COLLIDABLE) != 0;
-  const bool agent = act && myloc < Q.n_agents;
+  const bool agent = act && myloc < qw.y;
   const WorldK w = a.w;
   // partners: quad lanes qp ^ 1, qp ^ 2, qp ^ 3, then NS static entities
   // (NS: the most any environment of the batch has); bit (1 << local index)
@@ -903,7 +906,7 @@ __global__ void __launch_bounds__(256) k_rollout_quad(StepArgs a) {
   int pfl[NP];
 #pragma unroll
   for (int u = 0; u < NP; ++u) {
-    const int loc = u < 3 ? Q.lane_loc[qp ^ (u + 1)] : Q.stat_loc[u - 3];
+    const int loc = u < 3 ? lane_loc(qp ^ (u + 1)) : stat_loc(u - 3);
     bit[u] = loc >= 0 ? 1u << loc : 0u;
     rad[u] = 0.0f;
     pfl[u] = 0;
@@ -929,7 +932,7 @@ __global__ void __launch_bounds__(256) k_rollout_quad(StepArgs a) {
   }
   const int T = a.T;
   const size_t A = (size_t)w.A;
-  const int arow = Q.agent_row + (agent ? myloc : 0);
+  const int arow = agent ? qw.x + myloc : 0;
   const bool drawn = a.actions == nullptr;  // uniform
   const float2* ap = reinterpret_cast<const float2*>(a.actions) + arow;
   float2 cur[KCH], nxt[KCH];
@@ -1086,7 +1089,8 @@ __device__ __forceinline__ float quad_src(float v) {
 template <bool MD, int NS, bool OUT>
 __global__ void __launch_bounds__(64) k_rollout_quad_ord(StepArgs a) {
   const int gl = blockIdx.x * blockDim.x + threadIdx.x;
-  const int env = gl >> 2, qp = gl & 3;
+  const int qi = gl >> 2, qp = gl & 3;
+  const bool in = qi < (a.env_list ? a.n_list : a.n_envs);
   const int N = a.w.N;
   // Set-up in two rounds of independent loads (every load issued
   // unconditionally from a valid index, the value selected afterwards): the
@@ -1095,8 +1099,8 @@ __global__ void __launch_bounds__(64) k_rollout_quad_ord(StepArgs a) {
   // movers' radii and flags come from their own lanes (quad permutations).
   // The environment record is read as one 16-byte word and unpacked with
   // shifts (no per-lane array, which the compiler would place in LDS).
-  const bool in = env < a.n_envs;
-  const int envc = in ? env : 0;
+  const int envc = in ? (a.env_list ? a.env_list[qi] : qi) : 0;
+  const int env = envc;
   const int4 qw = reinterpret_cast<const int4*>(a.quad)[envc];
   const int o = a.env_off[envc], n = a.env_off[envc + 1] - o;
   const int agent_row = qw.x, n_agents = in ? qw.y : 0;

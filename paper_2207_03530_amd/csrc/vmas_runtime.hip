@@ -23,9 +23,12 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "vmas.h"
@@ -71,6 +74,9 @@ struct Plan {
   int32_t* d_pq_pair_off = nullptr;
   int pq_max_pairs = 0;
   QuadEnv* d_quad = nullptr;
+  int32_t* d_env_list = nullptr;  // quad plans on a subset of the environments
+  int n_list = 0;
+  bool composite = false;  // size-bucketed plan: the chosen part of every bucket, launched at once
   LaneRec* d_lanes = nullptr;
   int32_t* d_stage_off = nullptr;
   int32_t* d_stage = nullptr;
@@ -104,6 +110,14 @@ vmas_status set_error(vmas_status st, const char* fmt, ...) {
 }
 }  // namespace vmas
 
+// One bucket of environment sizes of a size-bucketed plan: its candidate
+// plans (each over the bucket's environments only) and the chosen one.
+struct Bucket {
+  int lo = 0, hi = 0;  // environment sizes lo .. hi
+  std::vector<Plan> cands;
+  int choice = 0;
+};
+
 struct vmas_batch {
   int device = 0;
   int n_envs = 0, N = 0, A = 0, J = 0, max_env = 0;
@@ -132,9 +146,18 @@ struct vmas_batch {
   // cached rollout graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  hipGraphNode_t gnode = nullptr;
   int graph_T = -1, graph_plan = -1;
+  int graph_gen = -1, plan_gen = 0;  // plan_gen changes with a bucketed plan's choices
   bool graph_drawn = false;
+  // size-bucketed plan (sphere batches of uneven sizes): buckets, and the
+  // side streams and events on which its parts run at the same time
+  std::vector<Bucket> buckets;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> side_done;
+  hipEvent_t fork = nullptr;
+  std::vector<hipGraphNode_t> gnodes;  // graph nodes of a composite plan
+  std::string tune_key;                // autotune cache key
+  bool tune_cached = false;            // the last autotune came from the cache
   // debug check of the state after every step call (VMAS_DEBUG_NONFINITE)
   bool debug_nonfinite = false;
   uint32_t* d_bad = nullptr;      // [n_envs] 1: the environment reached a non-finite state
@@ -151,6 +174,8 @@ void free_plan(Plan& p) {
   if (p.d_quad) (void)hipFree(p.d_quad);
   if (p.d_pq_pairs) (void)hipFree(p.d_pq_pairs);
   if (p.d_pq_pair_off) (void)hipFree(p.d_pq_pair_off);
+  if (p.d_env_list) (void)hipFree(p.d_env_list);
+  p.d_env_list = nullptr;
   p.d_pq_pairs = nullptr;
   p.d_pq_pair_off = nullptr;
   p.d_quad = nullptr;
@@ -165,6 +190,11 @@ void free_batch(vmas_batch* b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (auto& p : b->plans) free_plan(p);
+  for (auto& bk : b->buckets)
+    for (auto& p : bk.cands) free_plan(p);
+  for (hipStream_t st : b->side) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : b->side_done) (void)hipEventDestroy(ev);
+  if (b->fork) (void)hipEventDestroy(b->fork);
   free_plan(b->back);
   free_plan(b->cand);
   if (b->d_ent) (void)hipFree(b->d_ent);
@@ -332,7 +362,8 @@ bool excludes(int32_t excl, int loc) {
 // pq_ent: entity table of a pair-queue plan (NULL for the other plans).
 vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8_t>& shape,
                        const std::vector<uint8_t>& flags, int block, bool sorted, Plan& p,
-                       bool all_lanes = false, const std::vector<EntParam>* pq_ent = nullptr) {
+                       bool all_lanes = false, const std::vector<EntParam>* pq_ent = nullptr,
+                       const std::vector<char>* subset = nullptr) {
   p.block = block;
   p.sorted = sorted;
   p.all_lanes = all_lanes;
@@ -346,7 +377,8 @@ vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8
     for (int i = h.off[e]; i < h.off[e + 1]; ++i) active[e] += has_lane(i);
   std::vector<int> order;
   for (int e = 0; e < E; ++e)
-    if (active[e] > 0 && (all_lanes ? h.off[e + 1] > h.off[e] : true)) order.push_back(e);
+    if (active[e] > 0 && (all_lanes ? h.off[e + 1] > h.off[e] : true) && (!subset || (*subset)[e]))
+      order.push_back(e);
   if (sorted)
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
       return (h.off[x + 1] - h.off[x]) > (h.off[y + 1] - h.off[y]);
@@ -479,7 +511,7 @@ vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8
 // most 4 entities that move or rotate, at most 4 static collidable ones and
 // at most 32 entities); p.valid stays false when the batch does not qualify.
 vmas_status build_quad_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8_t>& flags,
-                            Plan& p, bool ordered = false) {
+                            Plan& p, bool ordered = false, const std::vector<char>* subset = nullptr) {
   p.name = ordered ? "quad-ordered/64" : "quad/256";
   p.block = ordered ? 64 : 256;
   p.quad = true;
@@ -488,8 +520,16 @@ vmas_status build_quad_plan(vmas_batch* b, const HostDesc& h, const std::vector<
   if (!b->spheres_only) return VMAS_OK;
   const int E = b->n_envs;
   std::vector<QuadEnv> q(std::max(E, 1));
+  for (auto& r : q) {
+    r.agent_row = 0;
+    r.n_agents = 0;
+    for (int u = 0; u < 4; ++u) r.lane_loc[u] = r.stat_loc[u] = -1;
+  }
+  std::vector<int32_t> list;
   int max_static = 0;
   for (int e = 0; e < E; ++e) {
+    if (subset && !(*subset)[e]) continue;
+    list.push_back(e);
     const int o = h.off[e], n = h.off[e + 1] - o;
     if (n > 32) return VMAS_OK;
     QuadEnv& r = q[e];
@@ -513,10 +553,95 @@ vmas_status build_quad_plan(vmas_batch* b, const HostDesc& h, const std::vector<
   if ((int64_t)E * 4 > INT32_MAX - 256) return VMAS_OK;
   vmas_status s = upload(&p.d_quad, q.data(), q.size());
   if (s != VMAS_OK) return s;
-  p.groups = (int)(((int64_t)E * 4 + p.block - 1) / p.block);
+  const int n_quads = subset ? (int)list.size() : E;
+  if (subset) {
+    if ((s = upload(&p.d_env_list, list.data(), std::max<size_t>(list.size(), 1))) != VMAS_OK)
+      return s;
+    p.n_list = (int)list.size();
+  }
+  p.groups = (int)(((int64_t)n_quads * 4 + p.block - 1) / p.block);
   p.max_n = max_static;  // the quad kernels size their static slots by it
-  p.valid = E > 0;
+  p.valid = n_quads > 0;
   return VMAS_OK;
+}
+
+// Environment-size buckets of the size-bucketed plan.
+constexpr int BUCKET_HI[] = {4, 8, 16, 32, 64, 1 << 30};
+
+// Builds the buckets and their candidate plans (sphere-only batches whose
+// environment sizes span at least two buckets): per bucket the size-sorted
+// entity-lane plans of 64, 128 and 256 lanes and, where every environment of
+// the bucket fits it, the ordered quad plan, each over the bucket's
+// environments only. The first valid candidate is the initial choice.
+vmas_status build_buckets(vmas_batch* b, const HostDesc& h, const std::vector<uint8_t>& shape,
+                          const std::vector<uint8_t>& flags) {
+  if (!b->spheres_only || b->n_envs < 32) return VMAS_OK;
+  const int E = b->n_envs;
+  std::vector<int> bucket_of(E, -1), count(6, 0);
+  for (int e = 0; e < E; ++e) {
+    const int n = h.off[e + 1] - h.off[e];
+    int k = 0;
+    while (n > BUCKET_HI[k]) ++k;
+    bucket_of[e] = k;
+    if (n > 0) ++count[k];
+  }
+  int used = 0;
+  for (int k = 0; k < 6; ++k) used += count[k] > 0;
+  if (used < 2) return VMAS_OK;
+  for (int k = 0; k < 6; ++k) {
+    if (count[k] == 0) continue;
+    std::vector<char> subset(E, 0);
+    for (int e = 0; e < E; ++e) subset[e] = bucket_of[e] == k;
+    Bucket bk;
+    bk.lo = k == 0 ? 1 : BUCKET_HI[k - 1] + 1;
+    bk.hi = BUCKET_HI[k];
+    vmas_status s;
+    {
+      Plan p;
+      if ((s = build_quad_plan(b, h, flags, p, true, &subset)) != VMAS_OK) {
+        free_plan(p);
+        return s;
+      }
+      if (p.valid) bk.cands.push_back(p);
+      else free_plan(p);
+    }
+    for (int block : {64, 128, 256}) {
+      Plan p;
+      if ((s = build_plan(b, h, shape, flags, block, true, p, false, nullptr, &subset)) != VMAS_OK) {
+        free_plan(p);
+        return s;
+      }
+      if (p.valid) bk.cands.push_back(p);
+      else free_plan(p);
+    }
+    if (bk.cands.empty()) {  // a bucket no candidate fits: no bucketed plan
+      for (auto& bb : b->buckets)
+        for (auto& p : bb.cands) free_plan(p);
+      b->buckets.clear();
+      return VMAS_OK;
+    }
+    b->buckets.push_back(std::move(bk));
+  }
+  for (size_t k = 0; k < b->buckets.size(); ++k) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    b->side.push_back(st);
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    b->side_done.push_back(ev);
+  }
+  HIPCHK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  return VMAS_OK;
+}
+
+// Name of the size-bucketed plan from its current choices.
+std::string bucketed_name(const vmas_batch* b) {
+  std::string n = "bucketed";
+  for (const auto& bk : b->buckets)
+    n += "/" + std::to_string(bk.lo) + "-" + (bk.hi >= (1 << 30) ? std::string("") :
+                                                 std::to_string(bk.hi)) + ":" +
+         bk.cands[bk.choice].name;
+  return n;
 }
 
 StepArgs make_args(vmas_batch* b, const Plan& p) {
@@ -534,6 +659,8 @@ StepArgs make_args(vmas_batch* b, const Plan& p) {
   a.max_n = p.max_n;
   a.quad = p.quad ? p.d_quad : nullptr;
   a.quad_ordered = p.quad_ordered ? 1 : 0;
+  a.env_list = p.d_env_list;
+  a.n_list = p.n_list;
   a.env_off = b->d_env_off;
   a.n_envs = b->n_envs;
   for (int c = 0; c < 6; ++c) a.pq_cap[c] = p.pq ? p.pq_cap[c] : 0;
@@ -572,8 +699,42 @@ vmas_status check_nonfinite(vmas_batch* b, const float* state, hipStream_t s) {
   return VMAS_OK;
 }
 
+// The call's own arguments (buffers, actions, steps) carried over to the
+// arguments of another plan.
+StepArgs with_call(vmas_batch* b, const Plan& p, const StepArgs& call) {
+  StepArgs a = make_args(b, p);
+  a.state = call.state;
+  a.actions = call.actions;
+  a.key = call.key;
+  a.t0 = call.t0;
+  a.T = call.T;
+  a.traj = call.traj;
+  a.mask = call.mask;
+  a.forces = call.forces;
+  return a;
+}
+
+// Size-bucketed plan: the chosen part of every bucket on its own side
+// stream, all forked from and joined back into s (the parts touch disjoint
+// environments, so they run at the same time).
+vmas_status launch_composite(vmas_batch* b, const StepArgs& call, hipStream_t s) {
+  HIPCHK(hipEventRecord(b->fork, s));
+  for (size_t k = 0; k < b->buckets.size(); ++k) {
+    const Plan& part = b->buckets[k].cands[b->buckets[k].choice];
+    if (part.groups == 0) continue;
+    const StepArgs pa = with_call(b, part, call);
+    HIPCHK(hipStreamWaitEvent(b->side[k], b->fork, 0));
+    hipError_t e = launch_rollout(pa, part.groups, part.block, b->spheres_only, b->side[k]);
+    if (e != hipSuccess) return fail(VMAS_ERR_DEVICE, "rollout launch failed: %s", hipGetErrorString(e));
+    HIPCHK(hipEventRecord(b->side_done[k], b->side[k]));
+    HIPCHK(hipStreamWaitEvent(s, b->side_done[k], 0));
+  }
+  return VMAS_OK;
+}
+
 vmas_status launch_plan(vmas_batch* b, StepArgs a, hipStream_t s) {
   const Plan& p = b->plans[b->cur];
+  if (p.composite) return launch_composite(b, a, s);
   if (p.groups == 0) return VMAS_OK;
   hipError_t e = launch_rollout(a, p.groups, p.block, b->spheres_only, s);
   if (e != hipSuccess) return fail(VMAS_ERR_DEVICE, "rollout launch failed: %s", hipGetErrorString(e));
@@ -839,6 +1000,38 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
     }
     b->plans.push_back(p);
   }
+  if ((s = build_buckets(b, h, shape, flags)) != VMAS_OK) {
+    free_batch(b);
+    return s;
+  }
+  if (!b->buckets.empty()) {
+    Plan p;
+    p.composite = true;
+    p.valid = true;
+    p.name = bucketed_name(b);
+    b->plans.push_back(p);
+  }
+  {
+    // autotune cache key: device architecture and the histogram of
+    // (size, movers, static collidables) over the environments
+    hipDeviceProp_t prop{};
+    std::string arch = hipGetDeviceProperties(&prop, device) == hipSuccess ? prop.gcnArchName : "?";
+    std::map<std::tuple<int, int, int>, int> hist;
+    for (int e = 0; e < E; ++e) {
+      int mv = 0, st = 0;
+      for (int i = h.off[e]; i < h.off[e + 1]; ++i) {
+        if (flags[i] & (MOVABLE | ROTATABLE)) ++mv;
+        else if (flags[i] & COLLIDABLE) ++st;
+      }
+      ++hist[std::make_tuple(h.off[e + 1] - h.off[e], mv, st)];
+    }
+    std::string key = arch + (spheres_only ? "|spheres" : "|shapes") + "|J" + std::to_string(J) +
+                      "|md" + std::to_string(params->min_dist != 0.0f);
+    for (const auto& kv : hist)
+      key += "|" + std::to_string(std::get<0>(kv.first)) + "," + std::to_string(std::get<1>(kv.first)) +
+             "," + std::to_string(std::get<2>(kv.first)) + "x" + std::to_string(kv.second);
+    b->tune_key = key;
+  }
   if (P > 0 && (s = build_plan(b, h, shape, flags, 1024, false, b->cand)) != VMAS_OK) {
     free_batch(b);
     return s;
@@ -880,7 +1073,7 @@ vmas_status vmas_batch_get_info(const vmas_batch* b, vmas_batch_info* info) {
   info->schedule = b->cur;
   info->n_schedules = (int32_t)b->plans.size();
   info->max_env_size = b->max_env;
-  info->reserved = 0;
+  info->tune_cached = b->tune_cached ? 1 : 0;
   return VMAS_OK;
 }
 
@@ -986,45 +1179,143 @@ vmas_status vmas_rollout_graph(vmas_batch* b, float* state, const float* actions
   vmas_status st0 = report_nonfinite(b, s);
   if (st0 != VMAS_OK) return st0;
   const Plan& p = b->plans[b->cur];
-  if (p.groups == 0) return VMAS_OK;
-  StepArgs a = make_args(b, p);
-  a.state = state;
-  a.actions = actions;
-  a.key = action_key(seed);
-  a.t0 = t0;
-  a.T = T;
+  // the plan's launches: the plan itself, or the chosen part of every
+  // bucket of a size-bucketed plan (independent graph nodes, which may run
+  // at the same time)
+  std::vector<const Plan*> parts;
+  if (p.composite) {
+    for (const auto& bk : b->buckets)
+      if (bk.cands[bk.choice].groups > 0) parts.push_back(&bk.cands[bk.choice]);
+  } else if (p.groups > 0) {
+    parts.push_back(&p);
+  }
+  if (parts.empty()) return VMAS_OK;
+  StepArgs call{};
+  call.state = state;
+  call.actions = actions;
+  call.key = action_key(seed);
+  call.t0 = t0;
+  call.T = T;
   const bool drawn = actions == nullptr;
-  void* args[1] = {&a};
-  hipKernelNodeParams kp{};
-  kp.func = const_cast<void*>(
-      rollout_kernel(b->spheres_only, p.quad, p.pq, p.block, p.max_n, b->w.min_dist, false,
-                     p.quad_ordered));
-  kp.gridDim = dim3(p.groups);
-  kp.blockDim = dim3(p.block);
-  kp.sharedMemBytes = (unsigned)rollout_lds_bytes(p.max_stage, b->spheres_only, p.quad,
-                                                  p.pq ? p.pq_cap[5] : 0, p.pq_max_pairs, p.block,
-                                                  p.max_n);
-  kp.kernelParams = args;
-  kp.extra = nullptr;
-  if (!b->gexec || b->graph_T != T || b->graph_plan != b->cur || b->graph_drawn != drawn) {
+  std::vector<StepArgs> args(parts.size());
+  std::vector<void*> argp(parts.size());
+  std::vector<hipKernelNodeParams> kps(parts.size());
+  for (size_t k = 0; k < parts.size(); ++k) {
+    const Plan& q = *parts[k];
+    args[k] = with_call(b, q, call);
+    argp[k] = &args[k];
+    hipKernelNodeParams& kp = kps[k];
+    kp = hipKernelNodeParams{};
+    kp.func = const_cast<void*>(rollout_kernel(b->spheres_only, q.quad, q.pq, q.block, q.max_n,
+                                               b->w.min_dist, false, q.quad_ordered));
+    kp.gridDim = dim3(q.groups);
+    kp.blockDim = dim3(q.block);
+    kp.sharedMemBytes = (unsigned)rollout_lds_bytes(q.max_stage, b->spheres_only, q.quad,
+                                                    q.pq ? q.pq_cap[5] : 0, q.pq_max_pairs, q.block,
+                                                    q.max_n);
+    kp.kernelParams = &argp[k];
+    kp.extra = nullptr;
+  }
+  if (!b->gexec || b->graph_T != T || b->graph_plan != b->cur || b->graph_drawn != drawn ||
+      b->graph_gen != b->plan_gen) {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->gexec = nullptr;
     b->graph = nullptr;
-    // The graph holds the single rollout kernel node; it is built explicitly
-    // (no stream capture), so any stream, the default one included, works.
+    b->gnodes.clear();
+    // The graph holds the rollout kernel nodes, without dependencies; it is
+    // built explicitly (no stream capture), so any stream, the default one
+    // included, works.
     HIPCHK(hipGraphCreate(&b->graph, 0));
-    HIPCHK(hipGraphAddKernelNode(&b->gnode, b->graph, nullptr, 0, &kp));
+    for (size_t k = 0; k < parts.size(); ++k) {
+      hipGraphNode_t node = nullptr;
+      HIPCHK(hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kps[k]));
+      b->gnodes.push_back(node);
+    }
     HIPCHK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
     b->graph_T = T;
     b->graph_plan = b->cur;
     b->graph_drawn = drawn;
+    b->graph_gen = b->plan_gen;
   } else {
-    HIPCHK(hipGraphExecKernelNodeSetParams(b->gexec, b->gnode, &kp));
+    for (size_t k = 0; k < parts.size(); ++k)
+      HIPCHK(hipGraphExecKernelNodeSetParams(b->gexec, b->gnodes[k], &kps[k]));
   }
   HIPCHK(hipGraphLaunch(b->gexec, s));
   return check_nonfinite(b, state, s);
 }
+
+}  // extern "C"
+
+namespace {
+
+// Autotune choices cached across handles in this process, keyed by device
+// architecture and the batch's histogram of environment shapes (plus the
+// rollout length bucket): the plan id and the part chosen for every size
+// bucket. With VMAS_AUTOTUNE_CACHE set, the cache is also read from and
+// appended to that file (one line per key: key, plan id, part choices).
+struct TuneChoice {
+  int plan = 0;
+  std::vector<int> parts;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneChoice> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load_file() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("VMAS_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[16384];
+  while (std::fgets(line, sizeof(line), f)) {
+    char* tab1 = std::strchr(line, '\t');
+    if (!tab1) continue;
+    *tab1 = 0;
+    char* tab2 = std::strchr(tab1 + 1, '\t');
+    TuneChoice c;
+    c.plan = std::atoi(tab1 + 1);
+    if (tab2)
+      for (char* q = tab2 + 1; *q && *q != '\n';) {
+        c.parts.push_back((int)std::strtol(q, &q, 10));
+        if (*q == ',') ++q;
+      }
+    g_tune[line] = c;
+  }
+  std::fclose(f);
+}
+
+void tune_store(const std::string& key, const TuneChoice& c) {
+  g_tune[key] = c;
+  const char* path = std::getenv("VMAS_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s\t%d\t", key.c_str(), c.plan);
+  for (size_t k = 0; k < c.parts.size(); ++k) std::fprintf(f, k ? ",%d" : "%d", c.parts[k]);
+  std::fprintf(f, "\n");
+  std::fclose(f);
+}
+
+std::string tune_key_T(const vmas_batch* b, int T) {
+  int tb = 1;
+  while (tb < T && tb < 1024) tb *= 2;  // rollout length bucket
+  return b->tune_key + "|T" + std::to_string(tb);
+}
+
+void set_bucket_choice(vmas_batch* b, const std::vector<int>& parts) {
+  for (size_t k = 0; k < b->buckets.size() && k < parts.size(); ++k)
+    if (parts[k] >= 0 && parts[k] < (int)b->buckets[k].cands.size()) b->buckets[k].choice = parts[k];
+  for (auto& p : b->plans)
+    if (p.composite) p.name = bucketed_name(b);
+  ++b->plan_gen;
+}
+
+}  // namespace
+
+extern "C" {
 
 vmas_status vmas_autotune(vmas_batch* b, const float* state, const float* actions, int32_t T,
                           void* stream, int32_t* chosen) {
@@ -1033,6 +1324,22 @@ vmas_status vmas_autotune(vmas_batch* b, const float* state, const float* action
   if (!state || T < 1) return fail(VMAS_ERR_INVALID_ARGUMENT, "state must be given and T >= 1");
   DeviceGuard guard(b->device);
   hipStream_t s = (hipStream_t)stream;
+  const int nplans = (int)b->plans.size();
+  const std::string key = tune_key_T(b, T);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_load_file();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end() && it->second.plan >= 0 && it->second.plan < nplans &&
+        b->plans[it->second.plan].valid && it->second.parts.size() == b->buckets.size()) {
+      set_bucket_choice(b, it->second.parts);
+      b->cur = it->second.plan;
+      b->tune_cached = true;
+      if (chosen) *chosen = b->cur;
+      return VMAS_OK;
+    }
+  }
+  b->tune_cached = false;
   const size_t n = 6 * (size_t)b->N;
   float* scratch = nullptr;
   HIPCHK(hipMalloc((void**)&scratch, n * sizeof(float)));
@@ -1040,7 +1347,6 @@ vmas_status vmas_autotune(vmas_batch* b, const float* state, const float* action
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   const int prev = b->cur;
-  const int nplans = (int)b->plans.size();
   std::vector<float> ms_min(nplans, INFINITY);
   vmas_status st = VMAS_OK;
   auto trial = [&](int q, float* ms_out) {
@@ -1055,6 +1361,25 @@ vmas_status vmas_autotune(vmas_batch* b, const float* state, const float* action
     (void)hipEventElapsedTime(ms_out, e0, e1);
     return VMAS_OK;
   };
+  // one candidate part of size bucket k alone (its environments only)
+  auto trial_part = [&](size_t k, int c, float* ms_out) {
+    const Plan& part = b->buckets[k].cands[c];
+    if (hipMemcpyAsync(scratch, state, n * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return fail(VMAS_ERR_DEVICE, "autotune copy failed");
+    StepArgs call{};
+    call.state = scratch;
+    call.actions = actions;
+    call.key = action_key(12345u);
+    call.T = T;
+    const StepArgs pa = with_call(b, part, call);
+    (void)hipEventRecord(e0, s);
+    hipError_t e = launch_rollout(pa, part.groups, part.block, b->spheres_only, s);
+    (void)hipEventRecord(e1, s);
+    if (e != hipSuccess) return fail(VMAS_ERR_DEVICE, "autotune launch failed: %s", hipGetErrorString(e));
+    if (hipEventSynchronize(e1) != hipSuccess) return fail(VMAS_ERR_DEVICE, "autotune sync failed");
+    (void)hipEventElapsedTime(ms_out, e0, e1);
+    return VMAS_OK;
+  };
   // Warm-up (clocks and code objects settle): about 20 ms of the first plan.
   {
     float ms = 0, spent = 0;
@@ -1063,6 +1388,23 @@ vmas_status vmas_autotune(vmas_batch* b, const float* state, const float* action
       spent += ms;
     }
   }
+  // Size buckets first: every candidate part of a bucket timed on the
+  // bucket alone, two rounds of two runs; the fastest run decides.
+  std::vector<int> parts(b->buckets.size(), 0);
+  for (size_t k = 0; k < b->buckets.size() && st == VMAS_OK; ++k) {
+    const int nc = (int)b->buckets[k].cands.size();
+    std::vector<float> best(nc, INFINITY);
+    for (int round = 0; round < 2 && st == VMAS_OK && nc > 1; ++round)
+      for (int c = 0; c < nc && st == VMAS_OK; ++c)
+        for (int rep = 0; rep < 2 && st == VMAS_OK; ++rep) {
+          float ms = 0;
+          st = trial_part(k, c, &ms);
+          if (st == VMAS_OK && ms < best[c]) best[c] = ms;
+        }
+    for (int c = 1; c < nc; ++c)
+      if (best[c] < 0.97f * best[parts[k]]) parts[k] = c;
+  }
+  if (st == VMAS_OK && !b->buckets.empty()) set_bucket_choice(b, parts);
   // Three rounds over all plans, two timed runs each: the fastest run of a
   // plan over the rounds is its time.
   for (int round = 0; round < 3 && st == VMAS_OK; ++round) {
@@ -1090,6 +1432,13 @@ vmas_status vmas_autotune(vmas_batch* b, const float* state, const float* action
     return st;
   }
   b->cur = best;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    TuneChoice c;
+    c.plan = best;
+    c.parts = parts;
+    tune_store(key, c);
+  }
   if (chosen) *chosen = best;
   return VMAS_OK;
 }
