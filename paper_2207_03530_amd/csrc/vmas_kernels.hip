@@ -1108,6 +1108,35 @@ __global__ void __launch_bounds__(64) k_rollout_quad_ord(StepArgs a) {
   auto lane_loc = [&](int u) { return in ? (int)(int8_t)((uint32_t)qw.z >> (8 * u)) : -1; };
   auto stat_loc = [&](int u) { return in ? (int)(int8_t)((uint32_t)qw.w >> (8 * u)) : -1; };
   const bool act = lane_loc(qp) >= 0;  // lane qp holds local entity qp
+  const int T = a.T;
+  const size_t A = (size_t)a.w.A;
+  const bool agent = act && qp < n_agents;
+  const int arow = agent ? agent_row + qp : 0;  // a lane without an action reads row 0
+  const bool drawn = a.actions == nullptr;  // uniform
+  const float2* ap = reinterpret_cast<const float2*>(a.actions) + arow;
+  // Actions of KCH steps per chunk, two chunks in flight (ping-pong, no
+  // register copies); rows past the rollout are clamped to its last row
+  // (read, never used), so every load is unconditional. The first chunk is
+  // requested here, with the lane's own state, before anything waits.
+  auto load_chunk = [&](float2* dst, int c) {
+    if (!drawn) {
+      if (A > 0) {
+#pragma unroll
+        for (int k = 0; k < KCH; ++k) dst[k] = ap[(size_t)min(c + k, T - 1) * A];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < KCH; ++k) {
+        const uint64_t base =
+            ((uint64_t)(a.t0 + min(c + k, T - 1)) * (uint64_t)a.w.A + (uint64_t)arow) * 2ull;
+        dst[k] = make_float2(draw_sym(a.key, base), draw_sym(a.key, base + 1));
+      }
+    }
+  };
+  float2 bufA[KCH];
+#pragma unroll
+  for (int k = 0; k < KCH; ++k) bufA[k] = make_float2(0.0f, 0.0f);
+  if (T > 0) load_chunk(bufA, 0);
   const int e = o + qp;
   const int ec = act ? e : min(o, N - 1);  // a valid index for the loads
   float x = a.state[ec], y = a.state[N + ec], vx = a.state[2 * N + ec],
@@ -1134,7 +1163,6 @@ __global__ void __launch_bounds__(64) k_rollout_quad_ord(StepArgs a) {
   const int fl = (p.sf >> 8) & 0xff;
   const bool movable = act && (fl & MOVABLE) != 0, rotatable = act && (fl & ROTATABLE) != 0;
   const bool collide = act && (fl & COLLIDABLE) != 0;
-  const bool agent = act && qp < n_agents;
   const WorldK w = a.w;
   // slots 0..2: movers k + [k >= qp] (their radius and whether they collide
   // from their lanes); slots 3..: statics. Contact distance squared (-1:
@@ -1174,11 +1202,6 @@ __global__ void __launch_bounds__(64) k_rollout_quad_ord(StepArgs a) {
     dm2[u] = ok ? __fmul_rn(dmin, dmin) : -1.0f;
     pdm[u] = ok ? dmin : 0.0f;
   }
-  const int T = a.T;
-  const size_t A = (size_t)w.A;
-  const int arow = agent ? agent_row + qp : 0;  // a lane without an action reads row 0
-  const bool drawn = a.actions == nullptr;  // uniform
-  const float2* ap = reinterpret_cast<const float2*>(a.actions) + arow;
   // angles and angular velocities change only while some omega is not +0
   // or some angle is -0 (see above); otherwise the update is the identity
   const bool spin = __builtin_amdgcn_ballot_w64(rotatable && (__float_as_uint(om) != 0u ||
@@ -1188,24 +1211,6 @@ __global__ void __launch_bounds__(64) k_rollout_quad_ord(StepArgs a) {
   const bool mute = __builtin_amdgcn_ballot_w64(act && !agent) != 0;
   // unit masses: f / m is f itself (x * 1 is exact), so the multiply goes
   const bool unit = __builtin_amdgcn_ballot_w64(movable && p.inv_m != 1.0f) == 0;
-  // Actions of KCH steps per chunk, two chunks in flight (ping-pong, no
-  // register copies); rows past the rollout are clamped to its last row
-  // (read, never used), so every load is unconditional.
-  auto load_chunk = [&](float2* dst, int c) {
-    if (!drawn) {
-      if (A > 0) {
-#pragma unroll
-        for (int k = 0; k < KCH; ++k) dst[k] = ap[(size_t)min(c + k, T - 1) * A];
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < KCH; ++k) {
-        const uint64_t base =
-            ((uint64_t)(a.t0 + min(c + k, T - 1)) * (uint64_t)w.A + (uint64_t)arow) * 2ull;
-        dst[k] = make_float2(draw_sym(a.key, base), draw_sym(a.key, base + 1));
-      }
-    }
-  };
   auto run = [&](auto spin_tag, auto mute_tag, auto unit_tag) {
     constexpr bool SPIN = decltype(spin_tag)::value, MUTE = decltype(mute_tag)::value;
     constexpr bool UNIT = decltype(unit_tag)::value;
@@ -1298,10 +1303,9 @@ __global__ void __launch_bounds__(64) k_rollout_quad_ord(StepArgs a) {
         out[5 * N + e] = om;
       }
     };
-    float2 bufA[KCH], bufB[KCH];
+    float2 bufB[KCH];
 #pragma unroll
-    for (int k = 0; k < KCH; ++k) bufA[k] = bufB[k] = make_float2(0.0f, 0.0f);
-    load_chunk(bufA, 0);
+    for (int k = 0; k < KCH; ++k) bufB[k] = make_float2(0.0f, 0.0f);
     for (int c = 0; c < T; c += 2 * KCH) {
       load_chunk(bufB, c + KCH);
 #pragma unroll
