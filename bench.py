@@ -115,6 +115,53 @@ def traffic_per_launch(kernel: str, tag: str = "spread30k"):
     return d.get("hbm_bytes_per_launch")
 
 
+CALIBRATION_BYTES = 256 * 1024 * 1024  # the --pmc-calibration copy, read and written
+
+
+def _counter_dispatches(csv_path):
+    """Per dispatch of a rocprofv3 counter collection: kernel name, grid size
+    and the sum over instances of every counter."""
+    import csv
+    out = {}
+    for r in csv.DictReader(open(csv_path)):
+        d = out.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"],
+                                                   "grid": int(r["Grid_Size"]), "c": {}})
+        d["c"][r["Counter_Name"]] = d["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def write_traffic_summary(kernel, tag, fetch_csv, write_csv, schedule, workload):
+    """profiles/<kernel>_<tag>_traffic.json from the FETCH_SIZE and WRITE_SIZE
+    passes of a --pmc-calibration bench run: the kernel's mean per dispatch,
+    scaled by what the same counter reads for the 256 MiB copy."""
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        ds = _counter_dispatches(path).values()
+        kv = [d["c"][counter] for d in ds
+              if f"::{kernel}<" in d["name"] or f"::{kernel}(" in d["name"]]
+        copies = [d for d in ds if "copyBuffer" in d["name"]]
+        big = max(d["grid"] for d in copies)
+        cv = sorted(d["c"][counter] for d in copies if d["grid"] == big)
+        if not kv or not cv:
+            sys.exit(f"no {kernel} or calibration copy dispatches in {path}")
+        per[counter] = (float(np.mean(kv)), cv[len(cv) // 2], len(kv))
+    fetch_kib, fetch_copy, n = per["FETCH_SIZE"]
+    write_kib, write_copy, _ = per["WRITE_SIZE"]
+    fs, ws = CALIBRATION_BYTES / (fetch_copy * 1024), CALIBRATION_BYTES / (write_copy * 1024)
+    d = {"kernel": kernel, "schedule": schedule, "workload": workload,
+         "kernel_source_sha": kernel_sha(), "dispatches": n,
+         "fetch_kib_per_dispatch_raw": fetch_kib, "write_kib_per_dispatch_raw": write_kib,
+         "copy_fetch_kib_raw": fetch_copy, "copy_write_kib_raw": write_copy,
+         "fetch_scale_from_copy": fs, "write_scale_from_copy": ws,
+         "fetch_bytes_per_launch": fetch_kib * 1024 * fs,
+         "write_bytes_per_launch": write_kib * 1024 * ws}
+    d["hbm_bytes_per_launch"] = d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]
+    path = os.path.join(PROFILES, f"{kernel}_{tag}_traffic.json")
+    with open(path, "w") as f:
+        json.dump(d, f, indent=1)
+    print(json.dumps(d))
+
+
 def cpu_baseline(w, acts, T):
     """The FP64 oracle, unchanged, on the same workload, environments split
     over the host cores (one thread per core, contiguous ranges)."""
@@ -249,10 +296,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="also run a plain copy of known size (traffic counter calibration)")
+    ap.add_argument("--traffic-summary", nargs=6,
+                    metavar=("KERNEL", "TAG", "FETCH_CSV", "WRITE_CSV", "SCHEDULE", "WORKLOAD"),
+                    help="write the traffic summary of KERNEL from two rocprofv3 counter "
+                         "collections (FETCH_SIZE, WRITE_SIZE) of a --pmc-calibration run")
     args = ap.parse_args()
+    if args.traffic_summary:
+        return write_traffic_summary(*args.traffic_summary)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs a single MI355X (--gpus 1); "
-              "environments are independent, see the sharding notes in DESIGN.md",
+              "environments are independent and shard by environment range",
               file=sys.stderr)
         sys.exit(2)
 

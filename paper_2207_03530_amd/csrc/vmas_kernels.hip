@@ -216,6 +216,39 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
     cls_sph0 |= (so == SPHERE ? 1u : 0u) << u;
     cls_box0 |= (so == BOX ? 1u : 0u) << u;
   }
+  // The lane's pairs of the broad phase (pair l + i B) and their summed
+  // bounding radii never change: with at most PPL per lane they are kept in
+  // registers (padding reads slot 0, its bit is masked off), so a step reads
+  // only the two poses of each pair, all pairs of a block of 4 at once.
+  constexpr int PPL = 16;
+  const int npl = PQ ? (npairs + B - 1) / B : 0;  // the same for every lane
+  const bool preg = PQ && npl <= PPL;
+  uint32_t pw[PPL];
+  float prad[PPL];
+  uint32_t pvalid = 0;
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) {
+    const int k = l + i * B;
+    const bool ok = preg && k < npairs;
+    pw[i] = ok ? pairs[k] : 0u;
+    prad[i] = ok ? brad[pw[i] & 0x7ff] + brad[(pw[i] >> 11) & 0x7ff] : 0.0f;
+    pvalid |= (ok ? 1u : 0u) << i;
+  }
+  // The lane's first two joints (static) in registers; further ones are
+  // read from memory each step.
+  int nj = 0, jslot[2] = {0, 0};
+  bool jis_a[2] = {false, false};
+  JointK jr[2] = {};
+  const int j0 = act ? a.joff[r.ent] : 0;
+  if (act) nj = a.joff[r.ent + 1] - j0;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    if (q < nj) {
+      jr[q] = a.joints[a.jlist[j0 + q]];
+      jis_a[q] = jr[q].a == r.ent;
+      jslot[q] = r.lo + ((jis_a[q] ? jr[q].b : jr[q].a) - r.first);
+    }
+  }
   for (int t = 0; t < a.T; ++t) {
     float4* cur = (t & 1) ? buf1 : buf0;
     float cs = 1.0f, sn = 0.0f;
@@ -254,15 +287,36 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
       // marked for both of their lanes, the others go to their class queue.
       // Tests first (no LDS atomic waits in between), then the candidates.
       uint32_t pc = 0;  // bit i: pair l + i B passed
-      for (int k = l, i = 0; k < npairs; k += B, ++i) {
-        const uint32_t pe = pairs[k];
-        const int qa = pe & 0x7ff, qb = (pe >> 11) & 0x7ff;
-        const float4 Pa = cur[qa], Pb = cur[qb];
+      auto bp_test = [&](float2 Pa, float2 Pb, float rsum) {
         const float dx = Pa.x - Pb.x, dy = Pa.y - Pb.y;
         const float reach =
             w.min_dist + 1e-4f + 1e-5f * fmaxf(fabsf(Pa.x) + fabsf(Pa.y), fabsf(Pb.x) + fabsf(Pb.y));
-        const float lim = (brad[qa] + brad[qb]) + reach;
-        pc |= (dx * dx + dy * dy <= lim * lim ? 1u : 0u) << i;
+        const float lim = rsum + reach;
+        return dx * dx + dy * dy <= lim * lim;
+      };
+      if (preg) {
+#pragma unroll
+        for (int i0 = 0; i0 < PPL; i0 += 4) {
+          if (i0 < npl) {
+            float2 A[4], Bp[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              A[j] = *reinterpret_cast<const float2*>(cur + (pw[i0 + j] & 0x7ff));
+              Bp[j] = *reinterpret_cast<const float2*>(cur + ((pw[i0 + j] >> 11) & 0x7ff));
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pc |= (bp_test(A[j], Bp[j], prad[i0 + j]) ? 1u : 0u) << (i0 + j);
+          }
+        }
+        pc &= pvalid;
+      } else {
+        for (int k = l, i = 0; k < npairs; k += B, ++i) {
+          const uint32_t pe = pairs[k];
+          const int qa = pe & 0x7ff, qb = (pe >> 11) & 0x7ff;
+          const float4 Pa = cur[qa], Pb = cur[qb];
+          pc |= (bp_test(make_float2(Pa.x, Pa.y), make_float2(Pb.x, Pb.y), brad[qa] + brad[qb]) ? 1u : 0u)
+                << i;
+        }
       }
       while (pc) {
         const int i = __builtin_ctz(pc);
@@ -289,23 +343,24 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
         }
       }
       lds_barrier();
-      // Every lane of the group works through the queues, class by class.
-      int n_c[PQ_CLASSES], total = 0;
+      // Every lane of the group works through the queues, class by class;
+      // each class starts at a multiple of 64 of the work index, so every
+      // 64-wide chunk (one wavefront's share) holds a single class and a
+      // wavefront runs one narrow-phase routine per chunk.
+      int n_c[PQ_CLASSES], cstart[PQ_CLASSES + 1];
+      cstart[0] = 0;
 #pragma unroll
       for (int c = 0; c < PQ_CLASSES; ++c) {
         n_c[c] = min(qcnt[c], a.pq_cap[c]);
-        total += n_c[c];
+        cstart[c + 1] = cstart[c] + ((n_c[c] + 63) & ~63);
       }
-      for (int i = l; i < total; i += B) {
-        // class of the i-th queued pair (classes back to back)
-        int c = 0, k = i;
+      for (int i = l; i < cstart[PQ_CLASSES]; i += B) {
+        int c = 0;
 #pragma unroll
-        for (int cc = 0; cc < PQ_CLASSES - 1; ++cc) {
-          if (c == cc && k >= n_c[cc]) {
-            k -= n_c[cc];
-            c = cc + 1;
-          }
-        }
+        for (int cc = 1; cc < PQ_CLASSES; ++cc) c += i >= cstart[cc] ? 1 : 0;
+        c = __builtin_amdgcn_readfirstlane(c);  // the same on every lane of the wavefront
+        const int k = i - cstart[c];
+        if (k >= n_c[c]) continue;
         const int e = qbase[c] + k;
         const uint32_t ent = qent[e];
         const int qa = ent & 0x7ff, qb = (ent >> 11) & 0x7ff;
@@ -436,14 +491,10 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
         run(std::integral_constant<int, LINE>{}, cand & ~(msph | mbox));
       }
     }
-    if (act) {
+    if (act && nj > 0) {
       // Joints: spring between world anchors, evaluated in joint order.
-      const int j0 = a.joff[r.ent], j1 = a.joff[r.ent + 1];
-      for (int jj = j0; jj < j1; ++jj) {
-        const JointK J = a.joints[a.jlist[jj]];
-        const bool is_a = J.a == r.ent;
-        const int other = is_a ? J.b : J.a;
-        const float4 P = cur[r.lo + (other - r.first)];
+      auto joint = [&](const JointK& J, bool is_a, int q) {
+        const float4 P = cur[q];
         V2 f;
         float ts, to;
         if (joint_eval<float>(V2{x, y}, cs, sn, V2{P.x, P.y}, P.z, P.w, is_a, J, w.joint_k, &f, &ts,
@@ -452,6 +503,14 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
           fy += f.y;
           tq += ts;
         }
+      };
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (q < nj) joint(jr[q], jis_a[q], jslot[q]);
+      for (int jj = j0 + 2; jj < j0 + nj; ++jj) {
+        const JointK J = a.joints[a.jlist[jj]];
+        const bool is_a = J.a == r.ent;
+        joint(J, is_a, r.lo + ((is_a ? J.b : J.a) - r.first));
       }
     }
     if (last && a.forces && act) {

@@ -1,7 +1,8 @@
 // Contact-force surrogate: a 12 -> 128 -> 128 -> 2 tanh MLP on pair
 // features, with hand-written forward, backward and Adam kernels for gfx950.
-// Products run on the matrix cores (v_mfma_f32_16x16x16_bf16: BF16 operands,
-// FP32 accumulation); biases, activations, losses and optimiser state are
+// Products run on the matrix cores (v_mfma_f32_16x16x16_bf16, and for the
+// K = 128 layers of inference v_mfma_f32_16x16x32_bf16: BF16 operands, FP32
+// accumulation); biases, activations, losses and optimiser state are
 // FP32.
 //
 // Fragment layouts of the 16x16x16 BF16 MFMA (wave64): for A (16 x 16,
@@ -104,6 +105,47 @@ __device__ void stage_weights(const MlpArgs& m, unsigned short* w1, unsigned sho
   }
 }
 
+// The weights of the inference kernel: W1 as stage_weights stores it; in W2
+// and W3 every 32-column block is permuted so that the K values lane group
+// g (= lane / 16) supplies to a 16x16x32 product -- columns 4g .. 4g+3 and
+// 16+4g .. 16+4g+3 of the block -- are the 8 consecutive columns 8g .. 8g+7
+// (one 16-byte LDS read). Each 4-column group moves as a whole (8 bytes).
+__device__ __forceinline__ int k32_col(int c) {
+  const int r = c & 31;
+  return (c & ~31) + 8 * ((r & 15) >> 2) + 4 * (r >> 4) + (r & 3);
+}
+__device__ void stage_weights_k32(const MlpArgs& m, unsigned short* w1, unsigned short* w2,
+                                  unsigned short* w3) {
+  using u2 = uint2;
+  using u4 = uint4;
+  const u4* g1 = reinterpret_cast<const u4*>(m.W1);
+  const u4* g2 = reinterpret_cast<const u4*>(m.W2);
+  const u4* g3 = reinterpret_cast<const u4*>(m.W3);
+  for (int i = threadIdx.x; i < NH * NIP / 8; i += blockDim.x) {
+    const int row = i / (NIP / 8), col = (i % (NIP / 8)) * 8;
+    *reinterpret_cast<u4*>(w1 + row * LDI + col) = g1[i];
+  }
+  auto put = [](unsigned short* w, int row, int col, u4 v) {
+    *reinterpret_cast<u2*>(w + row * LDH + k32_col(col)) = make_uint2(v.x, v.y);
+    *reinterpret_cast<u2*>(w + row * LDH + k32_col(col + 4)) = make_uint2(v.z, v.w);
+  };
+#pragma unroll 4
+  for (int i = threadIdx.x; i < NH * NH / 8; i += blockDim.x)
+    put(w2, i / (NH / 8), (i % (NH / 8)) * 8, g2[i]);
+  for (int i = threadIdx.x; i < NOP * NH / 8; i += blockDim.x)
+    put(w3, i / (NH / 8), (i % (NH / 8)) * 8, g3[i]);
+}
+
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+// 8 consecutive bf16 of a staged (permuted) row as one 16x16x32 fragment
+__device__ __forceinline__ b8 frag8(const unsigned short* base, int ld, int row, int k0) {
+  return *reinterpret_cast<const b8*>(base + row * ld + k0);
+}
+// the B fragment of one 32-wide K step from two 16-unit result fragments
+__device__ __forceinline__ b8 cat8(s4 lo, s4 hi) {
+  return __builtin_bit_cast(b8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
 // Forward pass over 64-row tiles. X [n][12] -> Y [n][2]; TRAIN: also the FP32
 // activations H1, H2 [n][128] for the backward pass. With n_dev set, the row
 // count is min(n, *n_dev), read on the device.
@@ -191,10 +233,18 @@ __global__ void __launch_bounds__(256) k_mlp_forward(MlpArgs m, const float* __r
 // Inference forward pass with the layers transposed: a wavefront computes
 // H1^T = tanh(W1 X^T + b1), H2^T = tanh(W2 H1^T + b2), Y^T = W3 H2^T + b3 for
 // 16 rows. The 16 x 16 result of one matrix-core product gives lane l the
-// hidden units 4 (l / 16) .. +3 of row l % 16, which is exactly the B
-// fragment (k = those hidden units, column = that row) of the next layer's
-// product, so activations stay in registers: no LDS round trip and no
-// barrier between layers. The weights are staged in LDS once per workgroup.
+// hidden units 4 (l / 16) .. +3 of row l % 16, which is the B fragment
+// (k = those hidden units, column = that row) of the next layer's product,
+// so activations stay in registers: no LDS round trip and no barrier between
+// layers. The weights are staged in LDS once per workgroup.
+//
+// Layers 2 and 3 (K = 128) run on the 16x16x32 BF16 product of gfx950 (half
+// the instructions of 16x16x16 at the same FLOP): lane l supplies 8 values
+// of K, and the same 8 positions of K for the A and the B operand. Those 8
+// are taken as the hidden units 4 (l / 16) .. +3 of two consecutive 16-unit
+// blocks -- the two result fragments the lane already holds -- so the K
+// order of a 32-wide step is a permutation of the hidden units, which the
+// staging applies to the weight columns (stage_weights_k32).
 constexpr int INFER_WAVES = 8;                  // wavefronts per workgroup (one weight copy)
 constexpr int INFER_ROWS = 16 * INFER_WAVES;     // rows per workgroup tile
 __global__ void __launch_bounds__(64 * INFER_WAVES)
@@ -205,7 +255,7 @@ k_mlp_infer(MlpArgs m, const float* __restrict__ X, int64_t n, const int32_t* __
   if ((int64_t)blockIdx.x >= tiles) return;  // uniform per workgroup, before any barrier
   __shared__ __attribute__((aligned(16))) unsigned short w1[NH * LDI], w2[NH * LDH], w3[NOP * LDH];
   __shared__ __attribute__((aligned(16))) float bias[NH + NH + NOP];
-  stage_weights(m, w1, w2, w3);
+  stage_weights_k32(m, w1, w2, w3);
   for (int i = threadIdx.x; i < NH; i += blockDim.x) {
     bias[i] = m.b1[i];
     bias[NH + i] = m.b2[i];
@@ -237,16 +287,17 @@ k_mlp_infer(MlpArgs m, const float* __restrict__ X, int64_t n, const int32_t* __
       h1[t] = activate(acc, t * 16);
     }
     // layer 2: the 8 output blocks advance together (independent
-    // accumulators keep the matrix cores busy), input block by input block
+    // accumulators keep the matrix cores busy), 32 input units at a time
     f4 acc2[NH / 16];
 #pragma unroll
     for (int u = 0; u < NH / 16; ++u) acc2[u] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int t = 0; t < NH / 16; ++t) {
+    for (int t = 0; t < NH / 32; ++t) {
+      const b8 bh = cat8(h1[2 * t], h1[2 * t + 1]);
 #pragma unroll
       for (int u = 0; u < NH / 16; ++u)
-        acc2[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag(w2, LDH, u * 16 + col, t * 16 + kq),
-                                                            h1[t], acc2[u], 0, 0, 0);
+        acc2[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag8(w2, LDH, u * 16 + col, t * 32 + 2 * kq),
+                                                          bh, acc2[u], 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);  // 8 weight fragments live at a time
     }
     s4 h2[NH / 16];
@@ -255,9 +306,9 @@ k_mlp_infer(MlpArgs m, const float* __restrict__ X, int64_t n, const int32_t* __
     // layer 3: outputs 0 and 1 land in lanes 0 .. 15, elements 0 and 1
     f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int u = 0; u < NH / 16; ++u)
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag(w3, LDH, col, u * 16 + kq), h2[u], acc, 0,
-                                                      0, 0);
+    for (int t = 0; t < NH / 32; ++t)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag8(w3, LDH, col, t * 32 + 2 * kq),
+                                                    cat8(h2[2 * t], h2[2 * t + 1]), acc, 0, 0, 0);
     if (kq == 0 && row < n) {
       const int64_t o = out_idx ? (int64_t)out_idx[row] : row;
       Y[o * NO] = acc[0] + bias[2 * NH];

@@ -341,7 +341,7 @@ vmas_status validate(const vmas_world_params* pr, const vmas_batch_desc* d, Host
 // workgroups, against that slower path).
 constexpr int PQ_CAP_PER_ENV = 32;
 constexpr int PQ_CAP_MAX = 256;
-constexpr size_t PQ_LDS_MAX = 64 * 1024;
+constexpr size_t PQ_LDS_MAX = 80 * 1024;
 
 int pq_pair_class(int sa, int sb) {
   const int lo = std::min(sa, sb), hi = std::max(sa, sb);

@@ -3,8 +3,13 @@
 Orchestration only: the dataset comes from the exact HIP step
 (vmas_rollout trajectories and vmas_pair_features), the network is
 trained by the HIP MLP kernels (vmas_mlp_train_step), and evaluation runs
-vmas_step_surrogate next to the exact vmas_step. Host code only selects
-which pair slots become samples and shuffles minibatch order.
+vmas_step_surrogate next to the exact vmas_step. Host code selects which
+pair slots become samples, shapes the training set and shuffles minibatch
+order. The shaping evaluates Eq. (2) and its inverse on the targets (torch,
+on the device): targets of contacts deeper than twice the fallback depth
+are scaled to the force at that depth, and contacts within 2 k of onset are
+repeated. This prepares training data only; the surrogate step itself,
+including its fallback rule, runs in the HIP kernels.
 """
 from __future__ import annotations
 

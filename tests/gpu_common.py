@@ -184,6 +184,6 @@ def _teacher_forced_check(w, ow, gtraj, gmasks, acts, name, tol=1e-5, min_plain=
           f"{nband}, plain {tol:g} met by {frac:.4f} of env-steps, allowance K > 1 on "
           f"{(needs > 1).mean():.4f}, K > 4 on {over4:.5f}, largest K {needs.max():.3g}, max plain "
           f"err {worst:.3g}")
-    assert frac >= min_plain
+    assert frac >= min_plain, f"{name}: plain {tol:g} met by {frac:.4f} of env-steps < {min_plain}"
     assert over4 <= 1e-3
     return worst

@@ -13,14 +13,18 @@ tests assert it together with the batch-scaled variant env_err, whose
 denominator is the group's magnitude over the whole batch.
 
 Conditioning: the state checks (conditioned_check) add to the relative
-tolerance K = 4 times how far the exact (FP64) result itself moves when
-the input poses move by 1e-7 (FP32 rounding size of O(1) coordinates). On a
-well-conditioned environment that allowance is far below the tolerance; it
-matters where no FP32 computation can meet the relative tolerance (a
-quantity that is exactly zero in the exact result but rounding-sized in
-FP32, where the per-environment denominator is its 1e-6 floor, or a stiff
-contact that amplifies rounding). No environment is excluded; how many
-needed the allowance is printed and bounded.
+tolerance K times rho, the largest distance from the exact (FP64) result
+of five other results that are equally correct at FP32 precision: the exact
+results from two FP32-rounding-size (1e-7 relative) perturbations of the
+input poses, and the oracle's own definition evaluated in FP32 from the
+input and from both perturbed inputs (perturbed_steps,
+perturbed_trajectories). On a well-conditioned environment that allowance is
+far below the tolerance; it matters where no FP32 computation can meet the
+relative tolerance (a quantity that is exactly zero in the exact result but
+rounding-sized in FP32, where the per-environment denominator is its 1e-6
+floor, or a stiff contact that amplifies rounding). No environment is
+excluded; the tests bound K for all environments and, tighter, for all but
+a small tail, and print how many needed the allowance at all.
 
 Forks: the contact decision of Eq. (2) is a threshold, so two correct
 trajectories may take different decisions once rounding has moved them

@@ -25,7 +25,7 @@ from tests.gpu_common import (_batch, _dev, _gpu_run, _gpu_step, _mask_check,  #
                               _one_step_check, _teacher_forced_check)
 
 
-def _check_world(w, name, T=30):
+def _check_world(w, name, T=30, min_plain=0.85):
     """One step from t = 0 (forces and torques too), then teacher forcing
     along a T-step GPU trajectory."""
     b = _batch(w)
@@ -48,7 +48,8 @@ def _check_world(w, name, T=30):
     assert ferr.max() <= 1e-5
     assert om.sum() > 0, f"{name}: the world has no contact at t = 0"
     _, gtraj, gmasks = _gpu_run(b, w.state0, acts)
-    _teacher_forced_check(w, ow, gtraj, gmasks, acts, f"{name}, teacher-forced")
+    _teacher_forced_check(w, ow, gtraj, gmasks, acts, f"{name}, teacher-forced",
+                          min_plain=min_plain)
     return b, gtraj
 
 
@@ -137,6 +138,32 @@ def test_joint_anchor_off_sphere_centre():
     _, gtraj = _check_world(w, "anchors off sphere centres")
     agents = np.nonzero((np.arange(w.n_entities) % n) < 4)[0]
     assert np.abs(gtraj[-1][5, agents]).max() > 1e-3  # the joints turn the spheres
+
+
+def test_entity_with_four_joints():
+    """Box 0 of every environment tied to agents 0 .. 3 (four joints on one
+    entity, evaluated in joint order: the first two kept in registers, the
+    others read each step), rest lengths from the initial state, agents
+    started off their rest positions by their actions."""
+    w = W.mixed(64, seed=17)
+    n = 28
+    base = np.arange(64, dtype=np.int32) * n
+    ja = np.stack([base + k for k in range(4)], 1).reshape(-1).astype(np.int32)
+    jb = np.repeat(base + 16, 4).astype(np.int32)
+    J = len(ja)
+    w.joint_a, w.joint_b = ja, jb
+    w.anchor_a = np.zeros((J, 2), np.float32)
+    w.anchor_b = np.tile(np.array([[0.0, 0.15], [0.0, -0.15], [0.05, 0.0], [-0.05, 0.1]],
+                                  np.float32), (64, 1))
+    w.joint_rest = np.full(J, -1.0, np.float32)
+    # four springs of stiffness 100 on one box are stiff enough that even the
+    # oracle's own definition evaluated in FP32 meets the plain 1e-5 on only
+    # 0.76 of the teacher-forced environment-steps; at stiffness 25 it meets
+    # it on 0.88 (every step is still held to the conditioning allowance)
+    w = dataclasses.replace(w, joint_stiffness=25.0)
+    _, gtraj = _check_world(w, "four joints on one entity", min_plain=0.8)
+    boxes = base + 16
+    assert np.abs(gtraj[-1][5, boxes]).max() > 1e-3  # the joints turn the boxes
 
 
 def test_joint_rest_from_state_is_exactly_at_rest():

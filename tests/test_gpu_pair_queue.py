@@ -3,8 +3,9 @@ from per-class queues in LDS, results summed per entity in the plain order)
 against the entity-lane schedule of the same block size, bit for bit: final
 state, trajectory, final contact mask and one step's forces, with given and
 in-kernel actions, joints, a minimum distance, static boxes and segments
-(pairs owned by the lane of the moving side), and queues that overflow (the
-pairs beyond a full queue are evaluated by both of their lanes)."""
+(pairs owned by the lane of the moving side), queues that overflow (the
+pairs beyond a full queue are evaluated by both of their lanes), and more
+broad-phase pairs per lane than the registers hold."""
 import dataclasses
 
 import numpy as np
@@ -35,7 +36,14 @@ def _worlds():
     # segments of length 2 in a 2 x 2 square: nearly all of the 378
     # segment pairs of an environment are candidates, beyond the queue's 256
     dense = W.mixed(6, n_spheres=2, n_boxes=2, n_lines=28, line_len=2.0, joints=False, seed=13)
-    return {"mixed": base, "static": static, "dense": dense}
+    # 4 sphere movers among 28 static segments: 118 pairs per environment
+    # and 16 environments per 64 lanes, about 30 pairs per lane (more than a
+    # lane keeps in registers: the broad phase reads its pairs from LDS)
+    walls = W.mixed(48, n_spheres=4, n_boxes=0, n_lines=28, joints=False, seed=14)
+    fl = walls.flags.copy()
+    fl[(np.arange(walls.n_entities) % 32) >= 4] = W.COLLIDABLE
+    walls = dataclasses.replace(walls, flags=fl)
+    return {"mixed": base, "static": static, "dense": dense, "walls": walls}
 
 
 def _plans(b):
@@ -67,7 +75,7 @@ def _run(b, w, q, T, drawn):
     return s, traj, mk, s1, m1, f1
 
 
-@pytest.mark.parametrize("name", ["mixed", "static", "dense"])
+@pytest.mark.parametrize("name", ["mixed", "static", "dense", "walls"])
 @pytest.mark.parametrize("drawn", [False, True])
 def test_pair_queue_bitwise_equals_entity_lane(name, drawn):
     from paper_2207_03530_amd import binding as B
