@@ -123,7 +123,7 @@ __device__ __forceinline__ bool queued_pair(const float4* cur, const float4* sta
   return true;
 }
 
-// Persistent rollout: T steps of every environment of the group. A lane's
+// Persistent rollout: T steps of every environment of the group.// Persistent rollout: T steps of every environment of the group. A lane's
 // contacts are accumulated partner class by partner class (spheres, boxes,
 // segments), each class in partner order.
 // Broad phase: a partner whose bounding circle stays farther than d_min plus
@@ -234,6 +234,23 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
     prad[i] = ok ? brad[pw[i] & 0x7ff] + brad[(pw[i] >> 11) & 0x7ff] : 0.0f;
     pvalid |= (ok ? 1u : 0u) << i;
   }
+  // Class of each of the lane's pairs (static): bit i of pm[c] is set when
+  // pair l + i B belongs to queue class c, of pm_ss when it joins two
+  // spheres.
+  uint32_t pm[PQ_CLASSES] = {0u, 0u, 0u, 0u, 0u}, pm_ss = 0u;
+  if (PQ) {
+    for (int k = l, i = 0; k < npairs; k += B, ++i) {
+      const uint32_t pe = pairs[k];
+      const int sa = __float_as_int(stat[pe & 0x7ff].w) & 0xff;
+      const int sb = __float_as_int(stat[(pe >> 11) & 0x7ff].w) & 0xff;
+      const uint32_t bit = 1u << i;
+      const int c = pair_class(sa, sb);
+      const bool ss = sa == SPHERE && sb == SPHERE;
+      pm_ss |= ss ? bit : 0u;
+#pragma unroll
+      for (int cc = 0; cc < PQ_CLASSES; ++cc) pm[cc] |= (!ss && c == cc) ? bit : 0u;
+    }
+  }
   // The lane's first two joints (static) in registers; further ones are
   // read from memory each step.
   int nj = 0, jslot[2] = {0, 0};
@@ -318,20 +335,23 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
                 << i;
         }
       }
-      while (pc) {
-        const int i = __builtin_ctz(pc);
-        pc &= pc - 1;
-        const uint32_t pe = pairs[l + i * B];
+      // Sphere pairs: a bit for each of the two lanes.
+      for (uint32_t m = pc & pm_ss; m; m &= m - 1) {
+        const uint32_t pe = pairs[l + __builtin_ctz(m) * B];
+        atomicOr(&sphw[pe & 0x7ff], 1u << (pe >> 27));
+        atomicOr(&sphw[(pe >> 11) & 0x7ff], 1u << ((pe >> 22) & 31));
+      }
+      // Other pairs, in bit order: the class comes from the lane's static
+      // masks, so the reservation does not wait for the pair's word.
+      for (uint32_t m = pc & ~pm_ss; m; m &= m - 1) {
+        const uint32_t bit = m & (0u - m);
+        const uint32_t pe = pairs[l + __builtin_ctz(m) * B];
+        int c = 0;
+#pragma unroll
+        for (int cc = 1; cc < PQ_CLASSES; ++cc) c = (pm[cc] & bit) ? cc : c;
+        const int kq = atomicAdd(&qcnt[c], 1);
         const int qa = pe & 0x7ff, qb = (pe >> 11) & 0x7ff;
         const int la = (pe >> 22) & 31, lb = pe >> 27;
-        const int sa = __float_as_int(stat[qa].w) & 0xff, sb = __float_as_int(stat[qb].w) & 0xff;
-        if (sa == SPHERE && sb == SPHERE) {
-          atomicOr(&sphw[qa], 1u << lb);
-          atomicOr(&sphw[qb], 1u << la);
-          continue;
-        }
-        const int c = pair_class(sa, sb);
-        const int kq = atomicAdd(&qcnt[c], 1);
         if (kq < qcap[c]) {
           const int e = qbase[c] + kq;
           qent[e] = pe;
