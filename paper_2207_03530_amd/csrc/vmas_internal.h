@@ -32,6 +32,15 @@ struct EntParam {
   int32_t pad[2];
 };
 
+// The fields of EntParam that the quad schedules read, in one 16-byte
+// record per entity (a third of EntParam's bytes).
+struct alignas(16) SphRec {
+  float rho;     // radius added to d_min
+  float inv_m;   // 1/m
+  float vmax;    // <= 0: no speed cap
+  int32_t sf;    // shape | flags << 8 | SF_ROTATES
+};
+
 // One lane of a launch group: the entity it integrates and where it sits.
 struct LaneRec {
   int32_t ent;    // global entity id, -1 = idle lane
@@ -112,6 +121,10 @@ struct StepArgs {
   int32_t n_list;              // quad schedules: environments in env_list
   const int32_t* env_list;     // quad schedules on a subset of the environments
                                // ([n_list] environment ids), or NULL: all
+  const SphRec* sph;           // [N] compact records of EntParam's fields
+  int32_t sph_only;            // 1: every entity has zero gravity force (+0) and a
+                               // finite 1/I >= 0, so SphRec alone describes it
+  int32_t pad3;
   WorldK w;
 };
 

@@ -1220,15 +1220,30 @@ __global__ void __launch_bounds__(64) k_rollout_quad_ord(StepArgs a) {
   const int ec = act ? e : min(o, N - 1);  // a valid index for the loads
   float x = a.state[ec], y = a.state[N + ec], vx = a.state[2 * N + ec],
         vy = a.state[3 * N + ec], th = a.state[4 * N + ec], om = a.state[5 * N + ec];
-  EntParam p = a.ent[ec];
+  // the lane's parameters from its 16-byte record; gravity and 1/I from
+  // the full record only where the batch has them (uniform)
+  const SphRec ps = a.sph[ec];
+  EntParam p{};
+  p.rho = ps.rho;
+  p.inv_m = ps.inv_m;
+  p.vmax = ps.vmax;
+  p.sf = ps.sf;
+  p.inv_I = 1.0f;  // 0 x 1/I is +0 for every finite 1/I >= 0
+  if (!a.sph_only) {
+    const EntParam& q = a.ent[ec];
+    p.mgx = q.mgx;
+    p.mgy = q.mgy;
+    p.inv_I = q.inv_I;
+  }
   float srad[NS > 0 ? NS : 1], sx[NS > 0 ? NS : 1], sy[NS > 0 ? NS : 1];
   int sfl[NS > 0 ? NS : 1], sloc[NS > 0 ? NS : 1];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     sloc[s] = stat_loc(s);
     const int es = min(o + (sloc[s] >= 0 ? sloc[s] : 0), N - 1);
-    const float r = a.ent[es].rho;
-    const int sfv = a.ent[es].sf;
+    const SphRec rs = a.sph[es];
+    const float r = rs.rho;
+    const int sfv = rs.sf;
     const float cx = a.state[es], cy = a.state[N + es];
     srad[s] = r;
     sfl[s] = sloc[s] >= 0 ? (sfv >> 8) & 0xff : 0;

@@ -125,6 +125,8 @@ struct vmas_batch {
   bool spheres_only = true;
   WorldK w{};
   EntParam* d_ent = nullptr;
+  SphRec* d_sph = nullptr;
+  bool sph_only = false;
   int32_t* d_joff = nullptr;
   int32_t* d_jlist = nullptr;
   JointK* d_joints = nullptr;
@@ -198,6 +200,7 @@ void free_batch(vmas_batch* b) {
   free_plan(b->back);
   free_plan(b->cand);
   if (b->d_ent) (void)hipFree(b->d_ent);
+  if (b->d_sph) (void)hipFree(b->d_sph);
   if (b->d_joff) (void)hipFree(b->d_joff);
   if (b->d_jlist) (void)hipFree(b->d_jlist);
   if (b->d_joints) (void)hipFree(b->d_joints);
@@ -647,6 +650,8 @@ std::string bucketed_name(const vmas_batch* b) {
 StepArgs make_args(vmas_batch* b, const Plan& p) {
   StepArgs a{};
   a.ent = b->d_ent;
+  a.sph = b->d_sph;
+  a.sph_only = b->sph_only ? 1 : 0;
   a.lanes = p.d_lanes;
   a.stage_off = p.d_stage_off;
   a.stage = p.d_stage;
@@ -885,8 +890,20 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
   b->w.joint_k = params->joint_stiffness;
   b->w.A = (int)A;
   b->w.N = N;
+  std::vector<SphRec> sph(ent.size());
+  b->sph_only = true;
+  for (size_t i = 0; i < ent.size(); ++i) {
+    sph[i] = SphRec{ent[i].rho, ent[i].inv_m, ent[i].vmax, ent[i].sf};
+    uint32_t gx, gy, ii;
+    std::memcpy(&gx, &ent[i].mgx, 4);
+    std::memcpy(&gy, &ent[i].mgy, 4);
+    std::memcpy(&ii, &ent[i].inv_I, 4);
+    if (gx != 0u || gy != 0u || (ii >> 31) != 0u || !std::isfinite(ent[i].inv_I))
+      b->sph_only = false;
+  }
   vmas_status s;
   if ((s = upload(&b->d_ent, ent.data(), ent.size())) != VMAS_OK ||
+      (s = upload(&b->d_sph, sph.data(), std::max<size_t>(sph.size(), 1))) != VMAS_OK ||
       (s = upload(&b->d_joff, joff.data(), joff.size())) != VMAS_OK ||
       (s = upload(&b->d_jlist, jlist.data(), jlist.size())) != VMAS_OK ||
       (s = upload(&b->d_joints, joints.data(), joints.size())) != VMAS_OK ||

@@ -3,8 +3,8 @@ quad, partner centres by DPP, static partners in registers, no LDS; the
 ordered variant for environments whose movers come first) against the
 entity-lane schedule, bit for bit: final state, trajectory, final contact
 mask and forces, with given and in-kernel actions, idle lanes, zero to four
-static entities, a static entity that does not collide, a minimum distance
-and a speed limit."""
+static entities, a static entity that does not collide, a minimum distance,
+a speed limit, and gravity."""
 import dataclasses
 
 import numpy as np
@@ -43,8 +43,13 @@ def _worlds():
                                mass=rng.uniform(0.5, 2.0, spin.n_entities).astype(np.float32))
     mute = W.spread(300, 4, 2, radius=0.15, seed=6)
     mute = dataclasses.replace(mute, n_agents=np.full(300, 2, np.int32))
+    # gravity on the movers (the quad kernels then read the full entity
+    # record for m g), with explicit moments of inertia
+    grav = W.spread(300, 4, 2, radius=0.15, seed=7)
+    grav = dataclasses.replace(grav, gravity=(0.3, -0.5),
+                               inertia=np.full(grav.n_entities, 0.02, np.float32))
     return {"dense": dense, "idle": idle, "ragged": ragged, "odd": odd, "spin": spin,
-            "mute": mute}
+            "mute": mute, "grav": grav}
 
 
 def _schedules(b, quad=QUAD):
@@ -71,7 +76,7 @@ def _run(b, w, q, T, drawn):
 
 
 @pytest.mark.parametrize("quad", QUADS)
-@pytest.mark.parametrize("name", ["dense", "idle", "ragged", "odd", "spin", "mute"])
+@pytest.mark.parametrize("name", ["dense", "idle", "ragged", "odd", "spin", "mute", "grav"])
 @pytest.mark.parametrize("drawn", [False, True])
 def test_quad_schedule_bitwise_equals_lane_schedule(name, drawn, quad):
     from paper_2207_03530_amd import binding as B
