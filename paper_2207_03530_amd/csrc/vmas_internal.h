@@ -122,8 +122,10 @@ struct StepArgs {
   const int32_t* env_list;     // quad schedules on a subset of the environments
                                // ([n_list] environment ids), or NULL: all
   const SphRec* sph;           // [N] compact records of EntParam's fields
-  int32_t sph_only;            // 1: every entity has zero gravity force (+0) and a
-                               // finite 1/I >= 0, so SphRec alone describes it
+  int32_t sph_only;            // 1: no joints, and every entity has zero gravity
+                               // force (+0) and a finite 1/I >= 0: a sphere is then
+                               // fully described by its SphRec (d0 = rho, d1 = 0,
+                               // no joint exclusions, m g = 0; 0 x 1/I = +0)
   int32_t pad3;
   WorldK w;
 };
@@ -193,10 +195,11 @@ hipError_t launch_pair_features(const float* state, const EntParam* ent, const i
 vmas_status mlp_forward_counted(vmas_mlp* m, const float* X, int64_t max_n, const int32_t* d_n,
                                 const int32_t* out_idx, float* Y, hipStream_t s);
 hipError_t launch_candidate_features(const StepArgs& a, int groups, int block, float band,
-                                     float* feat, int32_t* slot_of, int32_t* count, hipStream_t s);
+                                     float* feat, int32_t* slot_of, int32_t* count,
+                                     bool spheres_only, hipStream_t s);
 hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat_slot,
                                  float band, float frac, int32_t* n_fallback, int groups,
-                                 int block, hipStream_t s);
+                                 int block, bool spheres_only, hipStream_t s);
 
 // Host-side SplitMix64 key of (seed, stream): mix64(seed + (stream + 1) * golden).
 uint64_t action_key(uint64_t seed);

@@ -891,7 +891,7 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
   b->w.A = (int)A;
   b->w.N = N;
   std::vector<SphRec> sph(ent.size());
-  b->sph_only = true;
+  b->sph_only = J == 0;  // joints bring exclusions and anchor torques
   for (size_t i = 0; i < ent.size(); ++i) {
     sph[i] = SphRec{ent[i].rho, ent[i].inv_m, ent[i].vmax, ent[i].sf};
     uint32_t gx, gy, ii;
@@ -1705,16 +1705,17 @@ vmas_status vmas_step_surrogate(vmas_batch* b, vmas_mlp* mlp, float* state, cons
       StepArgs ac = make_args(b, b->cand);
       ac.state = state;
       HIPCHK(launch_candidate_features(ac, b->cand.groups, b->cand.block, band, b->d_feat, b->d_rows,
-                                       count, s));
+                                       count, b->spheres_only, s));
     } else {
-      HIPCHK(launch_candidate_features(a, p.groups, p.block, band, b->d_feat, b->d_rows, count, s));
+      HIPCHK(launch_candidate_features(a, p.groups, p.block, band, b->d_feat, b->d_rows, count,
+                                       b->spheres_only, s));
     }
     // outputs scattered to the candidates' pair slots
     vmas_status st = mlp_forward_counted(mlp, b->d_feat, b->P, count, b->d_rows, b->d_yhat, s);
     if (st != VMAS_OK) return st;
   }
   HIPCHK(launch_step_surrogate(a, b->d_yhat, band, fallback_frac, n_fallback, p.groups, p.block,
-                               s));
+                               b->spheres_only, s));
   return check_nonfinite(b, state, s);
 }
 

@@ -177,13 +177,32 @@ struct CandArgs {
   int32_t* count;      // number of candidate rows (starts at 0)
 };
 
+// The parameters of entity e: from its 16-byte SphRec where that describes
+// it fully (a sphere-only batch with sph_only), else the 48-byte EntParam.
+template <bool SPH>
+__device__ __forceinline__ EntParam ent_of(const StepArgs& a, int e) {
+  if (SPH && a.sph_only) {
+    const SphRec q = a.sph[e];
+    EntParam p{};
+    p.d0 = q.rho;
+    p.rho = q.rho;
+    p.inv_m = q.inv_m;
+    p.vmax = q.vmax;
+    p.sf = q.sf;
+    p.inv_I = 1.0f;  // never scales a nonzero torque here: 0 x 1/I = +0 either way
+    p.excl = -1;
+    return p;
+  }
+  return a.ent[e];
+}
+
 // Candidate features for the surrogate step, in consecutive rows: lane per
 // entity that can move or rotate, poses staged in LDS as in the exact step.
 // A pair is written by its lower entity, or by the higher one when the lower
 // one has no lane. Rows: each lane counts its candidates, the workgroup
 // scans the counts in LDS and takes its block of rows with one atomic, then
 // every lane writes its candidates in partner order.
-template <int MAXB>
+template <int MAXB, bool SPH>
 __global__ void __launch_bounds__(MAXB) k_cand_features(CandArgs ca) {
   const StepArgs& a = ca.s;
   extern __shared__ float4 lds[];
@@ -198,7 +217,7 @@ __global__ void __launch_bounds__(MAXB) k_cand_features(CandArgs ca) {
   const int s0 = a.stage_off[g], ns = a.stage_off[g + 1] - s0;
   for (int s = l; s < ns; s += B) {
     const int e = a.stage[s0 + s];
-    const EntParam p = a.ent[e];
+    const EntParam p = ent_of<SPH>(a, e);
     float cs = 1.0f, sn = 0.0f;
     if (uses_rotation(p.sf)) sincosf(a.state[4 * N + e], &sn, &cs);
     pose[s] = make_float4(a.state[e], a.state[N + e], cs, sn);
@@ -209,7 +228,7 @@ __global__ void __launch_bounds__(MAXB) k_cand_features(CandArgs ca) {
   __syncthreads();
   EntParam p{};
   p.excl = -1;
-  if (r.ent >= 0) p = a.ent[r.ent];
+  if (r.ent >= 0) p = ent_of<SPH>(a, r.ent);
   const int shape = p.sf & 0xff;
   const bool live = r.ent >= 0 && ((p.sf >> 8) & COLLIDABLE);
   const float4 me = live ? pose[r.slot] : make_float4(0.0f, 0.0f, 1.0f, 0.0f);
@@ -300,6 +319,9 @@ struct SurArgs {
 // used instead; otherwise f is replaced by the nearest force Eq. (2) can
 // produce, 0 when |f| < F0 / 2 and at least F0 = c k ln 2 (the force at zero
 // penetration) along f otherwise.
+// SPH: every collidable or moving entity of the batch is a sphere (the
+// sphere narrow phase alone is compiled in; the same arithmetic).
+template <bool SPH>
 __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
   const StepArgs& a = sa.s;
   extern __shared__ float4 lds[];
@@ -312,7 +334,7 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
   const int s0 = a.stage_off[g], ns = a.stage_off[g + 1] - s0;
   for (int s = l; s < ns; s += B) {
     const int e = a.stage[s0 + s];
-    const EntParam p = a.ent[e];
+    const EntParam p = ent_of<SPH>(a, e);
     float cs = 1.0f, sn = 0.0f;
     if (uses_rotation(p.sf)) sincosf(a.state[4 * N + e], &sn, &cs);
     pose[s] = make_float4(a.state[e], a.state[N + e], cs, sn);
@@ -327,8 +349,8 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
   const int e = r.ent;
   float x = a.state[e], y = a.state[N + e], vx = a.state[2 * N + e], vy = a.state[3 * N + e];
   float th = a.state[4 * N + e], om = a.state[5 * N + e];
-  const EntParam p = a.ent[e];
-  const int shape = p.sf & 0xff, fl = (p.sf >> 8) & 0xff;
+  const EntParam p = ent_of<SPH>(a, e);
+  const int shape = SPH ? SPHERE : p.sf & 0xff, fl = (p.sf >> 8) & 0xff;
   float cs = 1.0f, sn = 0.0f;
   if (uses_rotation(p.sf)) sincosf(th, &sn, &cs);
   float fx = p.mgx, fy = p.mgy, tq = 0.0f;
@@ -352,19 +374,20 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
     // partners class by class (spheres, boxes, segments), each in partner
     // order: the accumulation order of the exact step; classes absent from
     // the environment are skipped
-    unsigned present = 0;
-    for (int q = r.lo; q < r.hi; ++q) present |= 1u << (__float_as_int(stat[q].w) & 0xff);
-    for (int cls = 0; cls < 3; ++cls) {
+    unsigned present = SPH ? 1u << SPHERE : 0u;
+    if (!SPH)
+      for (int q = r.lo; q < r.hi; ++q) present |= 1u << (__float_as_int(stat[q].w) & 0xff);
+    for (int cls = 0; cls < (SPH ? 1 : 3); ++cls) {
       if (!(present & (1u << cls))) continue;
       for (int q = r.lo; q < r.hi; ++q) {
         if (q == r.slot) continue;
         const int b = q - r.lo;
         const float4 S = stat[q];
-        const int so = __float_as_int(S.w) & 0xff, of = (__float_as_int(S.w) >> 8) & 0xff;
+        const int so = SPH ? SPHERE : __float_as_int(S.w) & 0xff, of = (__float_as_int(S.w) >> 8) & 0xff;
         if (so != cls) continue;
         const float4 P = pose[q];
         if (!(of & COLLIDABLE) || (p.excl != -1 && excluded(p.excl, b))) continue;
-        if (shape == LINE || so == LINE) {
+        if (!SPH && (shape == LINE || so == LINE)) {
           // segments: exact narrow phase (same eligibility as the exact step)
           pair_force<false>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
           continue;
@@ -390,7 +413,7 @@ __global__ void __launch_bounds__(256) k_step_surrogate(SurArgs sa) {
                                so == SPHERE ? S.x : 0.5f * fminf(S.x, so == BOX ? S.y : S.x));
         if (pen > sa.fallback_frac * rr) {
           ++fallbacks;
-          pair_force<false>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
+          pair_force<SPH>(self, p.rho, myloc, P, S, b, w, fx, fy, tq);
           continue;
         }
         // nearest force Eq. (2) can produce: 0, or at least the onset force
@@ -467,23 +490,34 @@ hipError_t launch_pair_features(const float* state, const EntParam* ent, const i
 }
 
 hipError_t launch_candidate_features(const StepArgs& a, int groups, int block, float band,
-                                     float* feat, int32_t* slot_of, int32_t* count, hipStream_t s) {
+                                     float* feat, int32_t* slot_of, int32_t* count,
+                                     bool spheres_only, hipStream_t s) {
   if (groups <= 0) return hipSuccess;
   CandArgs ca{a, band, feat, slot_of, count};
   const size_t shm = (size_t)a.max_stage * (2 * sizeof(float4) + sizeof(float));
-  if (block > 256)
-    hipLaunchKernelGGL(k_cand_features<1024>, dim3(groups), dim3(block), shm, s, ca);
-  else
-    hipLaunchKernelGGL(k_cand_features<256>, dim3(groups), dim3(block), shm, s, ca);
+  if (block > 256) {
+    if (spheres_only)
+      hipLaunchKernelGGL((k_cand_features<1024, true>), dim3(groups), dim3(block), shm, s, ca);
+    else
+      hipLaunchKernelGGL((k_cand_features<1024, false>), dim3(groups), dim3(block), shm, s, ca);
+  } else {
+    if (spheres_only)
+      hipLaunchKernelGGL((k_cand_features<256, true>), dim3(groups), dim3(block), shm, s, ca);
+    else
+      hipLaunchKernelGGL((k_cand_features<256, false>), dim3(groups), dim3(block), shm, s, ca);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_step_surrogate(const StepArgs& a, const float* yhat,
                                  float band, float frac, int32_t* n_fallback, int groups,
-                                 int block, hipStream_t s) {
+                                 int block, bool spheres_only, hipStream_t s) {
   SurArgs sa{a, yhat, band, frac, n_fallback};
   const size_t shm = (size_t)a.max_stage * (2 * sizeof(float4) + sizeof(float));
-  hipLaunchKernelGGL(k_step_surrogate, dim3(groups), dim3(block), shm, s, sa);
+  if (spheres_only)
+    hipLaunchKernelGGL(k_step_surrogate<true>, dim3(groups), dim3(block), shm, s, sa);
+  else
+    hipLaunchKernelGGL(k_step_surrogate<false>, dim3(groups), dim3(block), shm, s, sa);
   return hipGetLastError();
 }
 
