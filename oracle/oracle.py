@@ -77,6 +77,7 @@ def lib():
         L.oracle_rollout_jvp.argtypes = [wp, _f64p, _f64p, _f64p, _f64p, ctypes.c_int]
         _f32p = ctypes.POINTER(ctypes.c_float)
         L.oracle_rollout_fp32.argtypes = [wp, _f32p, _f32p, ctypes.c_int, _f32p]
+        L.oracle_joint_lengths_fp32.argtypes = [wp, _f32p, _f64p]
         L.oracle_pair.argtypes = [ctypes.c_int, _f64p, _f64p, ctypes.c_int, _f64p, _f64p, _f64p]
         L.oracle_pair_distances.argtypes = [wp, _f64p, _f64p, _f64p]
         L.oracle_default_inertia.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -182,6 +183,25 @@ class OracleWorld:
                                    T, _p(tr, _f64p), _p(mask, _u8p))
         return st, mask, tr
 
+    def _world_fp32(self):
+        """The world as the FP32 evaluation sees it: a rest length taken from
+        the initial state is that state's anchor distance evaluated in FP32
+        (each side computes it in its own arithmetic, as the joints reading
+        of Sec. 3 in this project has it), so such a spring starts exactly at
+        rest there too."""
+        if getattr(self, "_s32", None) is None:
+            self._s32 = self.s
+            if self.rest is not None and np.any(np.asarray(self.w.joint_rest) < 0):
+                f32 = ctypes.POINTER(ctypes.c_float)
+                st0 = np.ascontiguousarray(self.w.state0, np.float32)
+                lens = np.zeros(self.rest.shape[0], np.float64)
+                lib().oracle_joint_lengths_fp32(ctypes.byref(self.s), st0.ctypes.data_as(f32),
+                                                _p(lens, _f64p))
+                self._rest32 = np.where(np.asarray(self.w.joint_rest) < 0, lens, self.rest)
+                self._s32 = _World.from_buffer_copy(self.s)
+                self._s32.rest = _p(self._rest32, _f64p)
+        return self._s32
+
     def rollout_fp32(self, state: np.ndarray, actions: np.ndarray, traj: bool = False):
         """The same definition evaluated in FP32 (not a reference: it sizes the
         FP32 rounding allowance of the parity tests). Returns (final state,
@@ -191,7 +211,7 @@ class OracleWorld:
         st = np.ascontiguousarray(state, np.float32).copy()
         act = np.ascontiguousarray(actions, np.float32)
         tr = np.zeros((T + 1, 6, self.N), np.float32) if traj else None
-        lib().oracle_rollout_fp32(ctypes.byref(self.s), st.ctypes.data_as(f32),
+        lib().oracle_rollout_fp32(ctypes.byref(self._world_fp32()), st.ctypes.data_as(f32),
                                   act.ctypes.data_as(f32), T,
                                   None if tr is None else tr.ctypes.data_as(f32))
         return st, tr

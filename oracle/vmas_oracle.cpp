@@ -565,6 +565,16 @@ template <class T> Pose<T> pose_of(const T* x, const T* y, const T* th, int i) {
 // x, y, vx, vy, theta, omega. mask (optional) gets one byte per pair slot,
 // environments in order, pairs (a < b) in lexicographic order of the local
 // indices; forces (optional) gets [3][N] = total force x, y and torque.
+// World anchor points of joint q: P = x + R(theta) anchor for both ends.
+template <class T>
+void joint_points(const oracle_world* w, const T* X, const T* Y, const T* TH, int q, Pose<T>* pa,
+                  Pose<T>* pb, V2<T>* Pa, V2<T>* Pb) {
+  *pa = pose_of(X, Y, TH, w->joint_a[q]);
+  *pb = pose_of(X, Y, TH, w->joint_b[q]);
+  *Pa = add(pa->c, rot(*pa, V2<T>{T(w->anchor_a[2 * q]), T(w->anchor_a[2 * q + 1])}));
+  *Pb = add(pb->c, rot(*pb, V2<T>{T(w->anchor_b[2 * q]), T(w->anchor_b[2 * q + 1])}));
+}
+
 template <class T>
 void step_envs(const oracle_world* w, int e0, int e1, T* st, const T* act, uint8_t* mask,
                T* forces) {
@@ -642,9 +652,9 @@ void step_envs(const oracle_world* w, int e0, int e1, T* st, const T* act, uint8
     for (int t = 0; t < nj; ++t) {
       int q = js[t];
       int ia = w->joint_a[q], ib = w->joint_b[q];
-      Pose<T> pa = pose_of(X, Y, TH, ia), pb = pose_of(X, Y, TH, ib);
-      V2<T> Pa = add(pa.c, rot(pa, V2<T>{T(w->anchor_a[2 * q]), T(w->anchor_a[2 * q + 1])}));
-      V2<T> Pb = add(pb.c, rot(pb, V2<T>{T(w->anchor_b[2 * q]), T(w->anchor_b[2 * q + 1])}));
+      Pose<T> pa, pb;
+      V2<T> Pa, Pb;
+      joint_points(w, X, Y, TH, q, &pa, &pb, &Pa, &Pb);
       V2<T> dl = sub(Pa, Pb);
       T len = norm(dl);
       if (len == T(0)) continue;
@@ -766,6 +776,23 @@ int oracle_rollout_fp32(const oracle_world* w, float* state, const float* action
   for (int t = 0; t < T; ++t) {
     step_envs<float>(w, 0, w->n_envs, state, actions + 2 * A * t, nullptr, nullptr);
     if (traj) std::memcpy(traj + 6 * N * (t + 1), state, sizeof(float) * 6 * N);
+  }
+  return 0;
+}
+
+// Length of every joint at `state` evaluated in FP32 by the step's own
+// expression. A rest length taken from the initial state is computed by each
+// side in its own arithmetic (the joints reading of Sec. 3 used here): the
+// FP32 evaluation takes these, so a spring that starts at rest exerts exactly
+// zero force in it too.
+int oracle_joint_lengths_fp32(const oracle_world* w, const float* state, double* out) {
+  const int64_t N = w->env_offset[w->n_envs];
+  const float *X = state, *Y = state + N, *TH = state + 4 * N;
+  for (int q = 0; q < w->n_joints; ++q) {
+    Pose<float> pa, pb;
+    V2<float> Pa, Pb;
+    joint_points(w, X, Y, TH, q, &pa, &pb, &Pa, &Pb);
+    out[q] = (double)norm(sub(Pa, Pb));
   }
   return 0;
 }

@@ -652,3 +652,39 @@ def test_oracle_jvp_matches_central_differences():
     sm, _, _ = ow.rollout(w.state0.astype(np.float64) - h * vs, acts - h * va, want_mask=False)
     fd = (sp - sm) / (2 * h)
     np.testing.assert_allclose(jv, fd, rtol=1e-5, atol=1e-5 * np.abs(fd).max())
+
+
+# ------------------------------------------- the FP32 evaluation (allowance) --
+
+def _batch_err(f, o, env_offset):
+    from tests import parity as PU
+    return PU.env_err(f, o, env_offset).max(0)
+
+
+def test_fp32_evaluation_is_an_fp32_rounding_of_the_definition():
+    """The oracle's float instantiation, which only sizes the FP32 rounding
+    allowance of the parity tests, must be the FP64 definition (pinned by the
+    tests above) up to FP32 rounding, or it would widen that allowance: one
+    step on the 32-environment sphere configuration and on a mixed-shape
+    batch with joints stays within 2e-6 of the FP64 result (batch-scaled, per
+    field group), 20 sphere steps within 2e-6; spheres never turn; and a
+    spring whose rest length comes from the initial state starts exactly at
+    rest in FP32 as well (its rest length is taken in FP32 by the same
+    expression: the angular velocities of the separated jointed batch after
+    one step are those of the FP64 result to 1e-12)."""
+    for w, T in ((W.spread(32), 1), (W.spread(32), 20), (W.mixed(16, seed=3), 1)):
+        ow = O.OracleWorld(w)
+        acts = w.actions(T)
+        o, _, _ = ow.rollout(w.state0, acts, want_mask=False)
+        f, _ = ow.rollout_fp32(w.state0, acts)
+        err = _batch_err(f, o, w.env_offset)
+        assert err.max() <= 2e-6, (w.name, T, err)
+        if w.name.startswith("spread"):
+            assert not np.any(f[4:6]), w.name
+    w = W.mixed(64, seed=5, half_width=2.0, separated=True)
+    ow = O.OracleWorld(w)
+    acts = w.actions(1)
+    o, _, _ = ow.rollout(w.state0, acts, want_mask=False)
+    f, _ = ow.rollout_fp32(w.state0, acts)
+    assert np.abs(f[5] - o[5]).max() <= 1e-12
+    assert _batch_err(f, o, w.env_offset)[:3].max() <= 2e-6
