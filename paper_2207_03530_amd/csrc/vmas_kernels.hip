@@ -693,6 +693,20 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
   }
   // NB == 64: slots u < nloc other than the lane's own
   const uint64_t valid64 = (nloc >= 64 ? ~0ull : ((1ull << nloc) - 1ull)) & ~(1ull << (myloc & 63));
+  // NB == 64, equal radii: when every partner of every lane of the
+  // wavefront is collidable with the lane's own radius, each partner's
+  // contact distance is the lane's fl((r + r [+ d_min])^2) -- the value the
+  // per-partner sum gives -- and the partners' records need not be read
+  bool eq_r = true;
+  if (NB == 64 && collide)
+    for (int u = 0; u < nloc; ++u) eq_r &= u == myloc || stat[r.lo + u].x == p.rho;
+  const bool uni = NB == 64 && __builtin_amdgcn_ballot_w64(collide && !eq_r) == 0;
+  float dm2u;
+  {
+    float dmin = p.rho + p.rho;
+    if (MD) dmin += w.min_dist;
+    dm2u = __fmul_rn(dmin, dmin);
+  }
   for (int c = 0; c < T; c += KCH) {
     if (c + KCH < T) load_chunk(nxt, c + KCH);
 #pragma unroll
@@ -740,24 +754,42 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
             const float2* pb = ((k & 1) ? pos1 : pos0) + r.lo;  // KCH is even
             const float2* sb = stat + r.lo;
             uint64_t hits = 0;
+            if (uni) {
 #pragma unroll
-            for (int blk = 0; blk < 64; blk += 8) {
-              if (blk < gmaxn) {
-                // the block's reads in flight before its tests
-                float2 P[8], S[8];
+              for (int blk = 0; blk < 64; blk += 8) {
+                if (blk < gmaxn) {
+                  float2 P[8];
 #pragma unroll
-                for (int v = 0; v < 8; ++v) {
-                  P[v] = pb[blk + v];
-                  S[v] = sb[blk + v];
+                  for (int v = 0; v < 8; ++v) P[v] = pb[blk + v];
+                  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                  for (int v = 0; v < 8; ++v) {
+                    const float dx = x - P[v].x, dy = y - P[v].y;
+                    const bool hit = fmaf(dx, dx, __fmul_rn(dy, dy)) <= dm2u;
+                    hits |= (hit ? 1ull : 0ull) << (blk + v);
+                  }
                 }
-                __builtin_amdgcn_sched_barrier(0);
+              }
+            } else {
 #pragma unroll
-                for (int v = 0; v < 8; ++v) {
-                  float dmin = p.rho + S[v].x;
-                  if (MD) dmin += w.min_dist;
-                  const float dx = x - P[v].x, dy = y - P[v].y;
-                  const bool hit = fmaf(dx, dx, __fmul_rn(dy, dy)) <= __fmul_rn(dmin, dmin);
-                  hits |= (hit ? 1ull : 0ull) << (blk + v);
+              for (int blk = 0; blk < 64; blk += 8) {
+                if (blk < gmaxn) {
+                  // the block's reads in flight before its tests
+                  float2 P[8], S[8];
+#pragma unroll
+                  for (int v = 0; v < 8; ++v) {
+                    P[v] = pb[blk + v];
+                    S[v] = sb[blk + v];
+                  }
+                  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                  for (int v = 0; v < 8; ++v) {
+                    float dmin = p.rho + S[v].x;
+                    if (MD) dmin += w.min_dist;
+                    const float dx = x - P[v].x, dy = y - P[v].y;
+                    const bool hit = fmaf(dx, dx, __fmul_rn(dy, dy)) <= __fmul_rn(dmin, dmin);
+                    hits |= (hit ? 1ull : 0ull) << (blk + v);
+                  }
                 }
               }
             }

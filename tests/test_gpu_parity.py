@@ -141,6 +141,43 @@ def test_all_schedules_bitwise_equal():
         assert len(names) >= 2
 
 
+def test_equal_radius_path_bitwise():
+    """Environments of 33..63 spheres of one radius take the 64-partner test
+    without reading the partners' records (their contact distance is the
+    lane's own); the same environments with one far, static, non-colliding
+    sphere appended take the path that reads every partner's radius. The
+    original spheres' states agree bit for bit after 30 steps."""
+    w = W.uneven(160, lo=33, hi=63, radius=0.06, seed=5)
+    n = np.diff(w.env_offset)
+    off2 = np.concatenate([[0], np.cumsum(n + 1)]).astype(np.int32)
+    N2 = int(off2[-1])
+    keep = np.concatenate([np.arange(off2[e], off2[e] + n[e]) for e in range(w.n_envs)])
+    dummy = off2[1:] - 1
+    shape = np.zeros(N2, np.uint8)
+    dims = np.zeros((N2, 2), np.float32)
+    dims[:, 0] = 0.06
+    mass = np.ones(N2, np.float32)
+    flags = np.zeros(N2, np.uint8)
+    flags[keep] = w.flags
+    st = np.zeros((6, N2), np.float32)
+    st[:, keep] = w.state0
+    st[0, dummy] = 50.0
+    st[1, dummy] = 50.0
+    w2 = W.World(env_offset=off2, n_agents=w.n_agents.copy(), shape=shape, dims=dims, mass=mass,
+                 flags=flags, state0=st, seed=w.seed, name="uneven160+dummy")
+    acts = _dev(w.actions(30))
+    outs = []
+    for ww in (w, w2):
+        b = _batch(ww)
+        s = _dev(ww.state0)
+        b.rollout(s, acts)
+        torch.cuda.synchronize()
+        outs.append(s.view(6, -1).cpu().numpy())
+        print(f"{ww.name}: plan {b.schedule_name(b.info().schedule)}")
+    assert np.array_equal(outs[0], outs[1][:, keep])
+    assert np.any(outs[0][:2] != w.state0[:2])
+
+
 def test_determinism_run_twice():
     w = W.mixed(64, seed=4)
     acts = _dev(w.actions(20))
