@@ -91,8 +91,8 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
     __syncthreads();  // the previous step's readers of pose and adj are done
     for (int s = l; s < ns; s += B) {
       const int e = a.stage[s0 + s];
-      float cs, sn;
-      sincosf(state[4 * N + e], &sn, &cs);
+      float cs = 1.0f, sn = 0.0f;  // a sphere's orientation enters no sphere pair
+      if (!SPH) sincosf(state[4 * N + e], &sn, &cs);
       pose[s] = make_float4(state[e], state[N + e], cs, sn);
     }
     // omega itself is not needed: its step is linear (damping and torque)
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
       th = state[4 * N + e];
     }
     float cs = 1.0f, sn = 0.0f;
-    if (act) sincosf(th, &sn, &cs);
+    if (!SPH && act) sincosf(th, &sn, &cs);
     __syncthreads();
 
     // 1. Reverse of the integration.
@@ -192,7 +192,52 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
         oth += f.x.c * ax + f.y.c * ay + ts.c * A_self.z + to.c * A_other.z;
       };
       const float4 A_self = adj[r.slot];
-      if (collide) {
+      if (SPH && collide) {
+        // spheres: the forward's FP32 test of every partner, 8 partners'
+        // reads in flight at a time, into a mask of up to 64 partners; then
+        // the contacts in partner order (no joints in a sphere batch)
+        for (int q0 = r.lo; q0 < r.hi; q0 += 64) {
+          const int cnt = min(64, r.hi - q0);
+          uint64_t hits = 0;
+          for (int b0 = 0; b0 < cnt; b0 += 8) {
+            float4 P[8], S[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+              const int q = min(q0 + b0 + v, r.hi - 1);
+              P[v] = pose[q];
+              S[v] = stat[q];
+            }
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+              const int q = q0 + b0 + v;
+              const int of = (__float_as_int(S[v].w) >> 8) & 0xff;
+              const bool elig = q < r.hi && q != r.slot && (of & COLLIDABLE) &&
+                                (self_dof || (of & (MOVABLE | ROTATABLE)));
+              const float dmin = (p.rho + S[v].z) + w.min_dist;
+              const float dx = x - P[v].x, dy = y - P[v].y;
+              const bool hit = fmaf(dx, dx, __fmul_rn(dy, dy)) <= __fmul_rn(dmin, dmin);
+              hits |= (elig && hit ? 1ull : 0ull) << (b0 + v);
+            }
+          }
+          while (hits) {
+            const int q = q0 + __builtin_ctzll(hits);
+            hits &= hits - 1;
+            const float4 P = pose[q];
+            const float4 S = stat[q];
+            GeoT<D3> other;
+            other.c = V2T<D3>{D3(P.x), D3(P.y)};
+            other.cs = D3(P.z);
+            other.sn = D3(P.w);
+            other.d0 = S.x;
+            other.d1 = S.y;
+            other.shape = SPHERE;
+            V2T<D3> f;
+            D3 ts, to;
+            pair_grad<SPH>(self, p.rho, myloc < q - r.lo, other, S.z, w, &f, &ts, &to);
+            contract(f, ts, to, A_self, adj[q]);
+          }
+        }
+      } else if (collide) {
         GeoT<float> selff;
         selff.c = V2T<float>{x, y};
         selff.cs = cs;
