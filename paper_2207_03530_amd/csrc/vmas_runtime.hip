@@ -123,6 +123,7 @@ struct vmas_batch {
   int n_envs = 0, N = 0, A = 0, J = 0, max_env = 0;
   int64_t P = 0;
   bool spheres_only = true;
+  bool all_move = true;  // every entity moves or turns: every plan gives each a lane
   WorldK w{};
   EntParam* d_ent = nullptr;
   SphRec* d_sph = nullptr;
@@ -880,6 +881,8 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
   b->P = P;
   b->max_env = max_env;
   b->spheres_only = spheres_only;
+  for (int i = 0; i < N; ++i)
+    if (!(desc->flags[i] & (MOVABLE | ROTATABLE))) b->all_move = false;
   b->w.dt = params->dt;
   b->w.damp = 1.0f - params->drag;
   b->w.gx = params->gravity[0];
@@ -1146,7 +1149,10 @@ vmas_status rollout_impl(vmas_batch* b, float* state, const float* actions, uint
   if (t0 < 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "t0 must be >= 0");
   if ((int64_t)T * b->A * 2 > ((int64_t)1 << 40))
     return fail(VMAS_ERR_INVALID_ARGUMENT, "T * A too large");
-  if (traj) HIPCHK(launch_replicate(state, traj, 6 * (int64_t)b->N, T + 1, s));
+  // trajectory slot 0 is the start state; the kernels write slots 1..T of
+  // every entity with a lane, so only entities without one (neither
+  // movable nor rotatable) need their state copied into every slot
+  if (traj) HIPCHK(launch_replicate(state, traj, 6 * (int64_t)b->N, b->all_move ? 1 : T + 1, s));
   if (T == 0) return VMAS_OK;
   if (final_mask) HIPCHK(launch_fill_u8(final_mask, b->P, s));
   StepArgs a = make_args(b, b->plans[b->cur]);
