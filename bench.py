@@ -74,7 +74,7 @@ STATIC_PER_ENTITY = 12
 # box/segment geometry 12 x 20.
 MIXED_FLOP_PER_ENV_STEP = 12600
 # Model FLOP count of the uneven sphere workload: 5 per pair test, 16 per
-# agent update (the survey's count for sphere batches).
+# agent update (a model count for sphere batches).
 UNEVEN_FLOP_PER_PAIR = 5
 UNEVEN_FLOP_PER_AGENT = 16
 
@@ -304,7 +304,7 @@ def main():
     if args.traffic_summary:
         return write_traffic_summary(*args.traffic_summary)
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs a single MI355X (--gpus 1); "
+        print("bench.py measures one GPU only (--gpus 1); "
               "environments are independent and shard by environment range",
               file=sys.stderr)
         sys.exit(2)
