@@ -334,7 +334,9 @@ def test_mixed_separated_hundred_steps():
     so there the exact trajectory itself diverges from its own FP32-size
     perturbation.) 256 environments run free for 100 steps: every step up to
     an environment's first valid mask fork within 1e-3 (conditioned check),
-    and at least 75 % of the environments without a fork for all 100 steps."""
+    and at least 75 % of the environments without a fork for all 100 steps;
+    and the plain per-environment 1e-3 held on as many environments as by the
+    oracle's own definition evaluated in FP32."""
     w = dataclasses.replace(W.mixed(256, seed=4, half_width=2.0, separated=True),
                             joint_stiffness=25.0)
     T = 100
@@ -345,6 +347,21 @@ def test_mixed_separated_hundred_steps():
     _free_run_check(w, ow, gtraj, gmasks, acts, "mixed256 separated T=100", min_full=0.75)
     _teacher_forced_check(w, ow, gtraj, gmasks, acts, "mixed256 separated, teacher-forced",
                           min_plain=0.5)
+    # the plain per-environment bar (1e-3 at all 100 steps, every field group,
+    # no allowance) against the FP64 result: the GPU holds it on at least as
+    # many environments, less 5 %, as the oracle's own definition evaluated
+    # in FP32 does
+    _, _, t64 = ow.rollout(w.state0, acts, traj=True, want_mask=False)
+    _, t32 = ow.rollout_fp32(w.state0, acts, traj=True)
+
+    def plain_all(tr):
+        ok = np.ones(w.n_envs, bool)
+        for t in range(1, T + 1):
+            ok &= PU.env_rel_err_local(tr[t], t64[t], w.env_offset).max(1) <= 1e-3
+        return ok.mean()
+    g_frac, f_frac = plain_all(gtraj), plain_all(t32)
+    print(f"mixed256 separated: plain 1e-3 at all steps, GPU {g_frac:.3f}, oracle in FP32 {f_frac:.3f}")
+    assert g_frac >= f_frac - 0.05
 
 
 SHAPE_CASES = [
