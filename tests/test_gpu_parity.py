@@ -141,13 +141,15 @@ def test_all_schedules_bitwise_equal():
         assert len(names) >= 2
 
 
-def test_equal_radius_path_bitwise():
+@pytest.mark.parametrize("min_dist", [0.0, 0.01])
+def test_equal_radius_path_bitwise(min_dist):
     """Environments of 33..63 spheres of one radius take the 64-partner test
     without reading the partners' records (their contact distance is the
     lane's own); the same environments with one far, static, non-colliding
     sphere appended take the path that reads every partner's radius. The
-    original spheres' states agree bit for bit after 30 steps."""
-    w = W.uneven(160, lo=33, hi=63, radius=0.06, seed=5)
+    original spheres' states agree bit for bit after 30 steps (with and
+    without an extra minimum distance)."""
+    w = dataclasses.replace(W.uneven(160, lo=33, hi=63, radius=0.06, seed=5), min_dist=min_dist)
     n = np.diff(w.env_offset)
     off2 = np.concatenate([[0], np.cumsum(n + 1)]).astype(np.int32)
     N2 = int(off2[-1])
@@ -164,7 +166,7 @@ def test_equal_radius_path_bitwise():
     st[0, dummy] = 50.0
     st[1, dummy] = 50.0
     w2 = W.World(env_offset=off2, n_agents=w.n_agents.copy(), shape=shape, dims=dims, mass=mass,
-                 flags=flags, state0=st, seed=w.seed, name="uneven160+dummy")
+                 flags=flags, state0=st, seed=w.seed, name="uneven160+dummy", min_dist=min_dist)
     acts = _dev(w.actions(30))
     outs = []
     for ww in (w, w2):
