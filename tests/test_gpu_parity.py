@@ -523,7 +523,8 @@ def test_uneven16384_graph_rollout_500_steps():
     environments (up to 64 spheres of r = 0.05 in [-1, 1]^2) are chaotic: the
     FP64 trajectory itself moves by more than tol/10 under a 1e-7 perturbation
     after a median of about 40 steps, so half of the sample is required to
-    stay comparable for 20 steps, every step before a cutoff within 1e-3."""
+    stay comparable for 20 steps, every step before a cutoff within 1e-3;
+    teacher forcing then checks all 500 steps at 1e-5."""
     w = W.uneven(16384, lo=2, hi=64, seed=0)
     T = 500
     b = _batch(w)
@@ -548,8 +549,12 @@ def test_uneven16384_graph_rollout_500_steps():
     ws = W.subset(w, envs)
     print(f"uneven16384 plan {b.schedule_name(q)}, sampled sizes {np.diff(ws.env_offset).min()}.."
           f"{np.diff(ws.env_offset).max()}")
-    _free_run_check(ws, O.OracleWorld(ws), np.stack(trs), np.stack(mks), _actions_of(w, envs, T),
-                    "uneven16384 sample", min_full=0.5, min_steps=20)
+    gtraj, gmasks, sacts = np.stack(trs), np.stack(mks), _actions_of(w, envs, T)
+    ow = O.OracleWorld(ws)
+    _free_run_check(ws, ow, gtraj, gmasks, sacts, "uneven16384 sample", min_full=0.5, min_steps=20)
+    # and every one of the 500 steps from the GPU's own state (teacher
+    # forcing), where the chaos of dense environments does not enter
+    _teacher_forced_check(ws, ow, gtraj, gmasks, sacts, "uneven16384 sample, teacher-forced")
 
 
 @pytest.mark.parametrize("lo,hi,E,r", [(65, 120, 24, 0.05), (300, 300, 2, 0.03)],
