@@ -102,15 +102,17 @@ def kernel_of(schedule: str, spheres_only: bool = True) -> str:
     return "k_rollout_quad" if schedule.startswith("quad") else "k_rollout_sph"
 
 
-def traffic_per_launch(kernel: str, tag: str = "spread30k"):
+def traffic_per_launch(kernel: str, tag: str = "spread30k", schedule: str = None):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary of `kernel` on workload `tag`, if it was taken on the current
-    kernel source; else None."""
+    kernel source and (when given) under the same launch plan; else None."""
     try:
         d = json.load(open(os.path.join(PROFILES, f"{kernel}_{tag}_traffic.json")))
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_sha") != kernel_sha():
+        return None
+    if schedule is not None and d.get("schedule") != schedule:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -398,7 +400,7 @@ def main():
         kernel = "k_step_backward"
     tag = "mixed4096" if mixed else ("uneven16384" if uneven else "spread30k")
     default_size = w.n_envs == (4096 if mixed else 30000) and T == (200 if mixed else 100)
-    traffic = (traffic_per_launch(kernel, tag)
+    traffic = (traffic_per_launch(kernel, tag, batch.schedule_name(plan))
                if not (args.drawn_actions or args.graph) and default_size else None)
     if uneven:
         n = np.diff(w.env_offset).astype(np.int64)

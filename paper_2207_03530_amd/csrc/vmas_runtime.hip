@@ -367,13 +367,15 @@ bool excludes(int32_t excl, int loc) {
 vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8_t>& shape,
                        const std::vector<uint8_t>& flags, int block, bool sorted, Plan& p,
                        bool all_lanes = false, const std::vector<EntParam>* pq_ent = nullptr,
-                       const std::vector<char>* subset = nullptr) {
+                       const std::vector<char>* subset = nullptr, int lane_cap = 0) {
   p.block = block;
   p.sorted = sorted;
   p.all_lanes = all_lanes;
   p.pq = pq_ent != nullptr;
   p.name = std::string(all_lanes ? "adjoint-lane/" : (p.pq ? "pair-queue/" : "entity-lane/")) +
-           std::to_string(block) + (sorted ? "/size-sorted" : "/natural");
+           std::to_string(block) + (sorted ? "/size-sorted" : "/natural") +
+           (lane_cap > 0 ? "/even" : "");
+  const int fill = lane_cap > 0 ? std::min(lane_cap, block) : block;
   const int E = b->n_envs;
   auto has_lane = [&](int i) { return all_lanes || (flags[i] & (MOVABLE | ROTATABLE)) != 0; };
   std::vector<int> active(E, 0);
@@ -396,7 +398,7 @@ vmas_status build_plan(vmas_batch* b, const HostDesc& h, const std::vector<uint8
       p.valid = false;
       return VMAS_OK;
     }
-    if (groups.empty() || lanes + active[e] > block || staged + n > stage_cap) {
+    if (groups.empty() || lanes + active[e] > fill || staged + n > stage_cap) {
       groups.emplace_back();
       lanes = 0;
       staged = 0;
@@ -1009,6 +1011,33 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
         else
           free_plan(p);
       }
+    }
+    // The same plans with the lanes spread evenly over the compute units: a
+    // whole number of workgroups per CU, each filled to an equal share of
+    // the lanes (whole environments), so that no CU runs more environments
+    // than another (4,096 environments of 28 movers: 512 groups of 8 instead
+    // of 456 of 9, two per CU).
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+      n_cu = 0;
+    int64_t L = 0;
+    for (int i = 0; i < N; ++i) L += (flags[i] & (MOVABLE | ROTATABLE)) != 0;
+    for (int bi = 1; bi < 3 && n_cu > 0 && L > 0; ++bi) {
+      const int64_t per = (int64_t)n_cu * blocks[bi];
+      const int64_t G = ((L + per - 1) / per) * n_cu;
+      const int cap = (int)((L + G - 1) / G);
+      if (cap > blocks[bi] - max_env) continue;  // what the plain packing gives
+      Plan p;
+      if ((s = build_plan(b, h, shape, flags, blocks[bi], false, p, false, &ent, nullptr, cap)) !=
+          VMAS_OK) {
+        free_plan(p);
+        free_batch(b);
+        return s;
+      }
+      if (p.valid)
+        b->plans.push_back(p);
+      else
+        free_plan(p);
     }
   }
   for (int ordered = 0; ordered < 2; ++ordered) {

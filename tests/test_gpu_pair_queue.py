@@ -51,7 +51,8 @@ def _plans(b):
     pairs = []
     for nm, q in names.items():
         if nm.startswith("pair-queue/"):
-            ref = "entity-lane/" + nm[len("pair-queue/"):]
+            # an evenly spread plan against the entity-lane plan of its block
+            ref = "entity-lane/" + nm[len("pair-queue/"):].removesuffix("/even")
             assert ref in names, (nm, sorted(names))
             pairs.append((nm, q, names[ref]))
     assert pairs, sorted(names)
