@@ -49,6 +49,21 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
+// m * 2 + [hit] in one add with carry, the lane mask of the test as the
+// carry in (the compiler otherwise builds each bit with a select and an or)
+__device__ __forceinline__ uint32_t shift_in(uint32_t m, bool hit) {
+  uint32_t r;
+  uint64_t carry_out;
+  asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3"
+      : "=v"(r), "=s"(carry_out)
+      : "v"(m), "s"(__builtin_amdgcn_ballot_w64(hit)));
+  return r;
+}
+// The n tests shifted in by shift_in (n in 0..32) as a mask with bit u set
+// for the u-th test.
+__device__ __forceinline__ uint32_t shifted_bits(uint32_t m, int n) {
+  return n > 0 ? __builtin_bitreverse32(m << (32 - n)) : 0u;
+}
 __device__ __forceinline__ float draw_sym(uint64_t key, uint64_t idx) {
   const uint64_t z = mix64(key + (idx + 1ull) * 0x9E3779B97F4A7C15ull);
   const int k = (int)(z >> 40);
@@ -322,18 +337,19 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
               Bp[j] = *reinterpret_cast<const float2*>(cur + ((pw[i0 + j] >> 11) & 0x7ff));
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) pc |= (bp_test(A[j], Bp[j], prad[i0 + j]) ? 1u : 0u) << (i0 + j);
+            for (int j = 0; j < 4; ++j) pc = shift_in(pc, bp_test(A[j], Bp[j], prad[i0 + j]));
           }
         }
-        pc &= pvalid;
+        pc = shifted_bits(pc, min(PPL, (npl + 3) & ~3)) & pvalid;
       } else {
-        for (int k = l, i = 0; k < npairs; k += B, ++i) {
+        int i = 0;
+        for (int k = l; k < npairs; k += B, ++i) {
           const uint32_t pe = pairs[k];
           const int qa = pe & 0x7ff, qb = (pe >> 11) & 0x7ff;
           const float4 Pa = cur[qa], Pb = cur[qb];
-          pc |= (bp_test(make_float2(Pa.x, Pa.y), make_float2(Pb.x, Pb.y), brad[qa] + brad[qb]) ? 1u : 0u)
-                << i;
+          pc = shift_in(pc, bp_test(make_float2(Pa.x, Pa.y), make_float2(Pb.x, Pb.y), brad[qa] + brad[qb]));
         }
+        pc = shifted_bits(pc, i);
       }
       // Sphere pairs: a bit for each of the two lanes.
       for (uint32_t m = pc & pm_ss; m; m &= m - 1) {
@@ -466,8 +482,9 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
           const float4 P = cur[q];
           const float dx = x - P.x, dy = y - P.y;
           const float lim = (rs + brad[q]) + reach;
-          cand |= (dx * dx + dy * dy <= lim * lim ? 1u : 0u) << u;
+          cand = shift_in(cand, dx * dx + dy * dy <= lim * lim);
         }
+        cand = shifted_bits(cand, cnt);
         if (myloc >= base && myloc < base + 32) cand &= ~(1u << (myloc - base));
         if (base == 0) {
           msph = cls_sph0;
@@ -753,7 +770,10 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
             // contact distance comes from the staged radius
             const float2* pb = ((k & 1) ? pos1 : pos0) + r.lo;  // KCH is even
             const float2* sb = stat + r.lo;
-            uint64_t hits = 0;
+            // each test shifted into the low end of a 32-bit word (one
+            // add with carry), the first partner ending in the top bit;
+            // reversed into bit u = partner u below
+            uint32_t mlo = 0u, mhi = 0u;
             if (uni) {
 #pragma unroll
               for (int blk = 0; blk < 64; blk += 8) {
@@ -766,7 +786,8 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
                   for (int v = 0; v < 8; ++v) {
                     const float dx = x - P[v].x, dy = y - P[v].y;
                     const bool hit = fmaf(dx, dx, __fmul_rn(dy, dy)) <= dm2u;
-                    hits |= (hit ? 1ull : 0ull) << (blk + v);
+                    if (blk < 32) mlo = shift_in(mlo, hit);
+                    else mhi = shift_in(mhi, hit);
                   }
                 }
               }
@@ -788,11 +809,16 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
                     if (MD) dmin += w.min_dist;
                     const float dx = x - P[v].x, dy = y - P[v].y;
                     const bool hit = fmaf(dx, dx, __fmul_rn(dy, dy)) <= __fmul_rn(dmin, dmin);
-                    hits |= (hit ? 1ull : 0ull) << (blk + v);
+                    if (blk < 32) mlo = shift_in(mlo, hit);
+                    else mhi = shift_in(mhi, hit);
                   }
                 }
               }
             }
+            // blocks past the group's largest environment were not tested
+            const int nt = min(64, (gmaxn + 7) & ~7);
+            uint64_t hits = ((uint64_t)shifted_bits(mhi, nt - min(32, nt)) << 32) |
+                            shifted_bits(mlo, min(32, nt));
             hits &= valid64;
             while (hits) {
               const int u = __builtin_ctzll(hits);
@@ -821,8 +847,9 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
                   pdx[v] = x - P[v].x;
                   pdy[v] = y - P[v].y;
                   psq[v] = fmaf(pdx[v], pdx[v], __fmul_rn(pdy[v], pdy[v]));
-                  hits |= (psq[v] <= dm2[v] ? 1u : 0u) << v;
+                  hits = shift_in(hits, psq[v] <= dm2[v]);
                 }
+                hits = shifted_bits(hits, NP);
                 while (hits) {
                   const int u = __builtin_ctz(hits);
                   hits &= hits - 1;
@@ -868,11 +895,11 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
 #pragma unroll
                 for (int v = 0; v < 8 && blk + v < NP; ++v) {
                   const float dx = x - P[v].x, dy = y - P[v].y;
-                  const bool hit = fmaf(dx, dx, __fmul_rn(dy, dy)) <= dm2[blk + v];
-                  hits |= (hit ? 1u : 0u) << (blk + v);
+                  hits = shift_in(hits, fmaf(dx, dx, __fmul_rn(dy, dy)) <= dm2[blk + v]);
                 }
               }
             }
+            hits = shifted_bits(hits, gmaxn > 1 ? min(NP, (gmaxn - 1 + 7) & ~7) : 0);
             while (hits) {
               const int u = __builtin_ctz(hits);
               hits &= hits - 1;
@@ -896,8 +923,9 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
                 const float dx = x - P.x, dy = y - P.y;
                 const bool hit = (fmaf(dx, dx, __fmul_rn(dy, dy)) <= __fmul_rn(dmin, dmin)) &
                                  (base + u < nloc);
-                hits |= (hit ? 1u : 0u) << u;
+                hits = shift_in(hits, hit);
               }
+              hits = shifted_bits(hits, cnt);
               if (myloc >= base && myloc < base + 32) hits &= ~(1u << (myloc - base));
               while (hits) {
                 const int u = __builtin_ctz(hits);
