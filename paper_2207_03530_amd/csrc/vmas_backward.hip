@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
         // the contacts in partner order (no joints in a sphere batch)
         for (int q0 = r.lo; q0 < r.hi; q0 += 64) {
           const int cnt = min(64, r.hi - q0);
-          uint64_t hits = 0;
+          uint32_t mlo = 0u, mhi = 0u;  // shift_in masks of partners 0..31, 32..63
           for (int b0 = 0; b0 < cnt; b0 += 8) {
             float4 P[8], S[8];
 #pragma unroll
@@ -216,9 +216,13 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
               const float dmin = (p.rho + S[v].z) + w.min_dist;
               const float dx = x - P[v].x, dy = y - P[v].y;
               const bool hit = fmaf(dx, dx, __fmul_rn(dy, dy)) <= __fmul_rn(dmin, dmin);
-              hits |= (elig && hit ? 1ull : 0ull) << (b0 + v);
+              if (b0 < 32) mlo = shift_in(mlo, elig && hit);
+              else mhi = shift_in(mhi, elig && hit);
             }
           }
+          const int nt = min(64, (cnt + 7) & ~7);
+          uint64_t hits = ((uint64_t)shifted_bits(mhi, nt - min(32, nt)) << 32) |
+                          shifted_bits(mlo, min(32, nt));
           while (hits) {
             const int q = q0 + __builtin_ctzll(hits);
             hits &= hits - 1;

@@ -49,21 +49,6 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
-// m * 2 + [hit] in one add with carry, the lane mask of the test as the
-// carry in (the compiler otherwise builds each bit with a select and an or)
-__device__ __forceinline__ uint32_t shift_in(uint32_t m, bool hit) {
-  uint32_t r;
-  uint64_t carry_out;
-  asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3"
-      : "=v"(r), "=s"(carry_out)
-      : "v"(m), "s"(__builtin_amdgcn_ballot_w64(hit)));
-  return r;
-}
-// The n tests shifted in by shift_in (n in 0..32) as a mask with bit u set
-// for the u-th test.
-__device__ __forceinline__ uint32_t shifted_bits(uint32_t m, int n) {
-  return n > 0 ? __builtin_bitreverse32(m << (32 - n)) : 0u;
-}
 __device__ __forceinline__ float draw_sym(uint64_t key, uint64_t idx) {
   const uint64_t z = mix64(key + (idx + 1ull) * 0x9E3779B97F4A7C15ull);
   const int k = (int)(z >> 40);
