@@ -49,10 +49,24 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
-__device__ __forceinline__ float draw_sym(uint64_t key, uint64_t idx) {
-  const uint64_t z = mix64(key + (idx + 1ull) * 0x9E3779B97F4A7C15ull);
-  const int k = (int)(z >> 40);
+// Draw idx of the counter-based stream of a key: the finaliser of key +
+// (idx + 1) golden, its top 24 bits mapped to [-1, 1).
+constexpr uint64_t GOLDEN = 0x9E3779B97F4A7C15ull;
+__device__ __forceinline__ float sym_of(uint64_t z) {
+  const uint64_t m = mix64(z);
+  const int k = (int)(m >> 40);
   return (float)(k - (1 << 23)) * (1.0f / 8388608.0f);
+}
+// The two action components of action row `row` at step t0 + t are draws
+// 2 ((t0 + t) A + row) and that + 1, so their counters key + (idx + 1)
+// golden are ctr0(row) + t step_ctr and that + golden (mod 2^64): a draw
+// costs an addition instead of a 64-bit product.
+__device__ __forceinline__ uint64_t ctr0(uint64_t key, int64_t t0, int64_t A, int64_t row) {
+  return key + (((uint64_t)t0 * (uint64_t)A + (uint64_t)row) * 2ull + 1ull) * GOLDEN;
+}
+__device__ __forceinline__ uint64_t step_ctr(int64_t A) { return 2ull * (uint64_t)A * GOLDEN; }
+__device__ __forceinline__ float2 draw_action(uint64_t z) {
+  return make_float2(sym_of(z), sym_of(z + GOLDEN));
 }
 
 // Radius of the circle about an entity's centre that holds the whole shape
@@ -201,12 +215,10 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
   // Actions of step t0 + t (prefetched one step ahead).
   float2 an = make_float2(0.0f, 0.0f);
   const bool agent = act && r.agent >= 0;
+  const uint64_t z0 = ctr0(a.key, a.t0, w.A, agent ? r.agent : 0), zs = step_ctr(w.A);
   if (agent && a.T > 0) {
     if (a.actions) an = *reinterpret_cast<const float2*>(a.actions + 2 * (size_t)r.agent);
-    else {
-      const uint64_t base = ((uint64_t)a.t0 * (uint64_t)w.A + (uint64_t)r.agent) * 2ull;
-      an = make_float2(draw_sym(a.key, base), draw_sym(a.key, base + 1));
-    }
+    else an = draw_action(z0);
   }
   __syncthreads();
   // shape classes of the first 32 partners (static for the whole rollout)
@@ -290,11 +302,8 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
     if (agent && t + 1 < a.T) {
       if (a.actions)
         an = *reinterpret_cast<const float2*>(a.actions + 2 * ((size_t)(t + 1) * w.A + r.agent));
-      else {
-        const uint64_t base =
-            ((uint64_t)(a.t0 + t + 1) * (uint64_t)w.A + (uint64_t)r.agent) * 2ull;
-        an = make_float2(draw_sym(a.key, base), draw_sym(a.key, base + 1));
-      }
+      else
+        an = draw_action(z0 + (uint64_t)(t + 1) * zs);
     }
     const bool last = t == a.T - 1;
     uint8_t* mk = (last && a.mask) ? a.mask : nullptr;
@@ -654,6 +663,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
   const size_t A = (size_t)w.A;
   const bool drawn = a.actions == nullptr;  // uniform
   const float2* ap = reinterpret_cast<const float2*>(a.actions) + (agent ? r.agent : 0);
+  const uint64_t z0 = ctr0(a.key, a.t0, w.A, agent ? r.agent : 0), zs = step_ctr(w.A);
   float2 cur[KCH], nxt[KCH];
   auto load_chunk = [&](float2* dst, int c) {
 #pragma unroll
@@ -664,12 +674,8 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
         if (agent && c + k < T) dst[k] = ap[(size_t)(c + k) * A];
     } else {
 #pragma unroll
-      for (int k = 0; k < KCH; ++k) {
-        if (agent && c + k < T) {
-          const uint64_t base = ((uint64_t)(a.t0 + c + k) * (uint64_t)w.A + (uint64_t)r.agent) * 2ull;
-          dst[k] = make_float2(draw_sym(a.key, base), draw_sym(a.key, base + 1));
-        }
-      }
+      for (int k = 0; k < KCH; ++k)
+        if (agent && c + k < T) dst[k] = draw_action(z0 + (uint64_t)(c + k) * zs);
     }
   };
   load_chunk(cur, 0);
@@ -1059,6 +1065,7 @@ __global__ void __launch_bounds__(256) k_rollout_quad(StepArgs a) {
   const int arow = agent ? qw.x + myloc : 0;
   const bool drawn = a.actions == nullptr;  // uniform
   const float2* ap = reinterpret_cast<const float2*>(a.actions) + arow;
+  const uint64_t z0 = ctr0(a.key, a.t0, w.A, arow), zs = step_ctr(w.A);
   float2 cur[KCH], nxt[KCH];
   auto load_chunk = [&](float2* dst, int c) {
 #pragma unroll
@@ -1069,12 +1076,8 @@ __global__ void __launch_bounds__(256) k_rollout_quad(StepArgs a) {
         if (agent && c + k < T) dst[k] = ap[(size_t)(c + k) * A];
     } else {
 #pragma unroll
-      for (int k = 0; k < KCH; ++k) {
-        if (agent && c + k < T) {
-          const uint64_t base = ((uint64_t)(a.t0 + c + k) * (uint64_t)w.A + (uint64_t)arow) * 2ull;
-          dst[k] = make_float2(draw_sym(a.key, base), draw_sym(a.key, base + 1));
-        }
-      }
+      for (int k = 0; k < KCH; ++k)
+        if (agent && c + k < T) dst[k] = draw_action(z0 + (uint64_t)(c + k) * zs);
     }
   };
   load_chunk(cur, 0);
@@ -1238,6 +1241,7 @@ __global__ void __launch_bounds__(64) k_rollout_quad_ord(StepArgs a) {
   const int arow = agent ? agent_row + qp : 0;  // a lane without an action reads row 0
   const bool drawn = a.actions == nullptr;  // uniform
   const float2* ap = reinterpret_cast<const float2*>(a.actions) + arow;
+  const uint64_t z0 = ctr0(a.key, a.t0, a.w.A, arow), zs = step_ctr(a.w.A);
   // Actions of KCH steps per chunk, two chunks in flight (ping-pong, no
   // register copies); rows past the rollout are clamped to its last row
   // (read, never used), so every load is unconditional. The first chunk is
@@ -1250,11 +1254,7 @@ __global__ void __launch_bounds__(64) k_rollout_quad_ord(StepArgs a) {
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < KCH; ++k) {
-        const uint64_t base =
-            ((uint64_t)(a.t0 + min(c + k, T - 1)) * (uint64_t)a.w.A + (uint64_t)arow) * 2ull;
-        dst[k] = make_float2(draw_sym(a.key, base), draw_sym(a.key, base + 1));
-      }
+      for (int k = 0; k < KCH; ++k) dst[k] = draw_action(z0 + (uint64_t)min(c + k, T - 1) * zs);
     }
   };
   float2 bufA[KCH];
