@@ -84,30 +84,70 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
     const float dx = x - P.x, dy = y - P.y;
     return !(dx * dx + dy * dy <= lim * lim);
   };
+  // Sphere batches: the entity of the lane's first staging slot and its
+  // joint range are kept in registers, and the state of step t is loaded
+  // while step t + 1 is worked on (the barriers wait for LDS traffic only,
+  // so the loads stay in flight): the first staging slot's centre and the
+  // lane's own state (omega itself is not needed: its step is linear in
+  // damping and torque). The general kernel, at the edge of its register
+  // budget, loads both at the top of each step.
+  const int e_st = SPH && l < ns ? a.stage[s0 + l] : 0;
+  const int jlo = SPH && act ? a.joff[r.ent] : 0, jhi = SPH && act ? a.joff[r.ent + 1] : 0;
+  float px = 0, py = 0, sx = 0, sy = 0, svx = 0, svy = 0, sth = 0;
+  auto fetch = [&](int t) {
+    const float* st = a.state + (size_t)t * 6 * N;
+    if (l < ns) {
+      px = st[e_st];
+      py = st[N + e_st];
+    }
+    if (act) {
+      const int e = r.ent;
+      sx = st[e];
+      sy = st[N + e];
+      svx = st[2 * N + e];
+      svy = st[3 * N + e];
+      sth = st[4 * N + e];
+    }
+  };
+  if (SPH && a.T > 0) fetch(a.T - 1);
   for (int t = a.T - 1; t >= 0; --t) {
     const float* state = a.state + (size_t)t * 6 * N;
     const float* actions = a.actions ? a.actions + (size_t)t * 2 * w.A : nullptr;
     float* gact = a.gact ? a.gact + (size_t)t * 2 * w.A : nullptr;
-    __syncthreads();  // the previous step's readers of pose and adj are done
-    for (int s = l; s < ns; s += B) {
-      const int e = a.stage[s0 + s];
-      float cs = 1.0f, sn = 0.0f;  // a sphere's orientation enters no sphere pair
-      if (!SPH) sincosf(state[4 * N + e], &sn, &cs);
-      pose[s] = make_float4(state[e], state[N + e], cs, sn);
-    }
-    // omega itself is not needed: its step is linear (damping and torque)
+    lds_barrier();  // the previous step's readers of pose and adj are done
     float x = 0, y = 0, vx = 0, vy = 0, th = 0;
-    if (act) {
-      const int e = r.ent;
-      x = state[e];
-      y = state[N + e];
-      vx = state[2 * N + e];
-      vy = state[3 * N + e];
-      th = state[4 * N + e];
+    if constexpr (SPH) {
+      // a sphere's orientation enters no sphere pair
+      if (l < ns) pose[l] = make_float4(px, py, 1.0f, 0.0f);
+      for (int s = l + B; s < ns; s += B) {
+        const int e = a.stage[s0 + s];
+        pose[s] = make_float4(state[e], state[N + e], 1.0f, 0.0f);
+      }
+      x = sx;
+      y = sy;
+      vx = svx;
+      vy = svy;
+      th = sth;
+      if (t > 0) fetch(t - 1);
+    } else {
+      for (int s = l; s < ns; s += B) {
+        const int e = a.stage[s0 + s];
+        float cs = 1.0f, sn = 0.0f;
+        sincosf(state[4 * N + e], &sn, &cs);
+        pose[s] = make_float4(state[e], state[N + e], cs, sn);
+      }
+      if (act) {
+        const int e = r.ent;
+        x = state[e];
+        y = state[N + e];
+        vx = state[2 * N + e];
+        vy = state[3 * N + e];
+        th = state[4 * N + e];
+      }
     }
     float cs = 1.0f, sn = 0.0f;
     if (!SPH && act) sincosf(th, &sn, &cs);
-    __syncthreads();
+    lds_barrier();
 
     // 1. Reverse of the integration.
     float Fbx = 0.0f, Fby = 0.0f, Tb = 0.0f;
@@ -139,7 +179,7 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
             pair_force<SPH>(self, p.rho, myloc, pose[q], S, q - r.lo, w, fx, fy, tq);
           }
         }
-        for (int jj = a.joff[r.ent]; jj < a.joff[r.ent + 1]; ++jj) {
+        for (int jj = SPH ? jlo : a.joff[r.ent]; jj < (SPH ? jhi : a.joff[r.ent + 1]); ++jj) {
           const JointK J = a.joints[a.jlist[jj]];
           const bool is_a = J.a == r.ent;
           const float4 P = pose[r.lo + ((is_a ? J.b : J.a) - r.first)];
@@ -173,7 +213,7 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
       Tb = wt * p.inv_I * w.dt;
     }
     if (act) adj[r.slot] = make_float4(Fbx, Fby, Tb, 0.0f);
-    __syncthreads();
+    lds_barrier();
 
     // 2. Pose adjoint through the contacts and joints of the entity.
     if (act) {
@@ -273,7 +313,7 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
           contract(f, ts, to, A_self, adj[q]);
         }
       }
-      for (int jj = a.joff[r.ent]; jj < a.joff[r.ent + 1]; ++jj) {
+      for (int jj = SPH ? jlo : a.joff[r.ent]; jj < (SPH ? jhi : a.joff[r.ent + 1]); ++jj) {
         const JointK J = a.joints[a.jlist[jj]];
         const bool is_a = J.a == r.ent;
         const int q = r.lo + ((is_a ? J.b : J.a) - r.first);
