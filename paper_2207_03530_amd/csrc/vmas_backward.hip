@@ -88,12 +88,15 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
   // joint range are kept in registers, and the state of step t is loaded
   // while step t + 1 is worked on (the barriers wait for LDS traffic only,
   // so the loads stay in flight): the first staging slot's centre and the
-  // lane's own state (omega itself is not needed: its step is linear in
-  // damping and torque). The general kernel, at the edge of its register
-  // budget, loads both at the top of each step.
+  // lane's own centre, and its velocity only under a speed cap (the
+  // clamp's adjoint is the one use of it; a sphere's angle and omega enter
+  // nothing, omega's step being linear in damping and torque). Without
+  // speed caps the trajectory may hold positions only. The general kernel,
+  // at the edge of its register budget, loads its state at the top of each
+  // step.
   const int e_st = SPH && l < ns ? a.stage[s0 + l] : 0;
   const int jlo = SPH && act ? a.joff[r.ent] : 0, jhi = SPH && act ? a.joff[r.ent + 1] : 0;
-  float px = 0, py = 0, sx = 0, sy = 0, svx = 0, svy = 0, sth = 0;
+  float px = 0, py = 0, sx = 0, sy = 0, svx = 0, svy = 0;
   auto fetch = [&](int t) {
     const float* st = a.state + (size_t)t * 6 * N;
     if (l < ns) {
@@ -104,9 +107,10 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
       const int e = r.ent;
       sx = st[e];
       sy = st[N + e];
-      svx = st[2 * N + e];
-      svy = st[3 * N + e];
-      sth = st[4 * N + e];
+      if (p.vmax > 0.0f) {
+        svx = st[2 * N + e];
+        svy = st[3 * N + e];
+      }
     }
   };
   if (SPH && a.T > 0) fetch(a.T - 1);
@@ -127,7 +131,6 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
       y = sy;
       vx = svx;
       vy = svy;
-      th = sth;
       if (t > 0) fetch(t - 1);
     } else {
       for (int s = l; s < ns; s += B) {

@@ -126,7 +126,8 @@ struct StepArgs {
                                // force (+0) and a finite 1/I >= 0: a sphere is then
                                // fully described by its SphRec (d0 = rho, d1 = 0,
                                // no joint exclusions, m g = 0; 0 x 1/I = +0)
-  int32_t pad3;
+  int32_t traj_xy;             // 1: the trajectory gets x and y only (the other
+                               // components of its slots are not written)
   WorldK w;
 };
 

@@ -573,10 +573,12 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
       float* o = a.traj + (size_t)(t + 1) * 6 * N;
       o[r.ent] = x;
       o[N + r.ent] = y;
-      o[2 * N + r.ent] = vx;
-      o[3 * N + r.ent] = vy;
-      o[4 * N + r.ent] = th;
-      o[5 * N + r.ent] = om;
+      if (!a.traj_xy) {
+        o[2 * N + r.ent] = vx;
+        o[3 * N + r.ent] = vy;
+        o[4 * N + r.ent] = th;
+        o[5 * N + r.ent] = om;
+      }
     }
   }
   if (act && a.T > 0) {
@@ -954,10 +956,12 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
           float* o = a.traj + (size_t)(t + 1) * 6 * N;
           o[r.ent] = x;
           o[N + r.ent] = y;
-          o[2 * N + r.ent] = vx;
-          o[3 * N + r.ent] = vy;
-          o[4 * N + r.ent] = th;
-          o[5 * N + r.ent] = om;
+          if (!a.traj_xy) {
+            o[2 * N + r.ent] = vx;
+            o[3 * N + r.ent] = vy;
+            o[4 * N + r.ent] = th;
+            o[5 * N + r.ent] = om;
+          }
         }
       }
     }
@@ -1171,10 +1175,12 @@ __global__ void __launch_bounds__(256) k_rollout_quad(StepArgs a) {
           float* out = a.traj + (size_t)(t + 1) * 6 * N;
           out[e] = x;
           out[N + e] = y;
-          out[2 * N + e] = vx;
-          out[3 * N + e] = vy;
-          out[4 * N + e] = th;
-          out[5 * N + e] = om;
+          if (!a.traj_xy) {
+            out[2 * N + e] = vx;
+            out[3 * N + e] = vy;
+            out[4 * N + e] = th;
+            out[5 * N + e] = om;
+          }
         }
       }
     }
@@ -1436,10 +1442,12 @@ __global__ void __launch_bounds__(64) k_rollout_quad_ord(StepArgs a) {
         float* out = a.traj + (size_t)(t + 1) * 6 * N;
         out[e] = x;
         out[N + e] = y;
-        out[2 * N + e] = vx;
-        out[3 * N + e] = vy;
-        out[4 * N + e] = th;
-        out[5 * N + e] = om;
+        if (!a.traj_xy) {
+          out[2 * N + e] = vx;
+          out[3 * N + e] = vy;
+          out[4 * N + e] = th;
+          out[5 * N + e] = om;
+        }
       }
     };
     float2 bufB[KCH];

@@ -124,6 +124,7 @@ struct vmas_batch {
   int64_t P = 0;
   bool spheres_only = true;
   bool all_move = true;  // every entity moves or turns: every plan gives each a lane
+  bool any_vmax = false;  // some entity has a speed cap
   WorldK w{};
   EntParam* d_ent = nullptr;
   SphRec* d_sph = nullptr;
@@ -717,6 +718,7 @@ StepArgs with_call(vmas_batch* b, const Plan& p, const StepArgs& call) {
   a.t0 = call.t0;
   a.T = call.T;
   a.traj = call.traj;
+  a.traj_xy = call.traj_xy;
   a.mask = call.mask;
   a.forces = call.forces;
   return a;
@@ -883,8 +885,10 @@ vmas_status vmas_create_batch(const vmas_world_params* params, const vmas_batch_
   b->P = P;
   b->max_env = max_env;
   b->spheres_only = spheres_only;
-  for (int i = 0; i < N; ++i)
+  for (int i = 0; i < N; ++i) {
     if (!(desc->flags[i] & (MOVABLE | ROTATABLE))) b->all_move = false;
+    if (ent[i].vmax > 0.0f) b->any_vmax = true;
+  }
   b->w.dt = params->dt;
   b->w.damp = 1.0f - params->drag;
   b->w.gx = params->gravity[0];
@@ -1171,8 +1175,10 @@ namespace {
 
 // vmas_rollout without the debug report and check (also the forward replays
 // of the adjoint driver and the autotuner's trials, on library workspaces).
+// traj_xy: the trajectory gets positions only (every entity must have a lane)
 vmas_status rollout_impl(vmas_batch* b, float* state, const float* actions, uint64_t seed,
-                         int32_t t0, int32_t T, float* traj, uint8_t* final_mask, hipStream_t s) {
+                         int32_t t0, int32_t T, float* traj, uint8_t* final_mask, hipStream_t s,
+                         bool traj_xy = false) {
   if (!state) return fail(VMAS_ERR_INVALID_ARGUMENT, "state must not be NULL");
   if (T < 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "T must be >= 0");
   if (t0 < 0) return fail(VMAS_ERR_INVALID_ARGUMENT, "t0 must be >= 0");
@@ -1181,7 +1187,9 @@ vmas_status rollout_impl(vmas_batch* b, float* state, const float* actions, uint
   // trajectory slot 0 is the start state; the kernels write slots 1..T of
   // every entity with a lane, so only entities without one (neither
   // movable nor rotatable) need their state copied into every slot
-  if (traj) HIPCHK(launch_replicate(state, traj, 6 * (int64_t)b->N, b->all_move ? 1 : T + 1, s));
+  if (traj_xy && !b->all_move) return fail(VMAS_ERR_INVALID_ARGUMENT, "positions-only trajectory");
+  if (traj)
+    HIPCHK(launch_replicate(state, traj, (traj_xy ? 2 : 6) * (int64_t)b->N, b->all_move ? 1 : T + 1, s));
   if (T == 0) return VMAS_OK;
   if (final_mask) HIPCHK(launch_fill_u8(final_mask, b->P, s));
   StepArgs a = make_args(b, b->plans[b->cur]);
@@ -1191,6 +1199,7 @@ vmas_status rollout_impl(vmas_batch* b, float* state, const float* actions, uint
   a.t0 = t0;
   a.T = T;
   a.traj = traj;
+  a.traj_xy = traj && traj_xy ? 1 : 0;
   a.mask = final_mask;
   a.forces = nullptr;
   return launch_plan(b, a, s);
@@ -1585,6 +1594,10 @@ vmas_status backward_on(vmas_batch* b, float* ws, const float* state0, const flo
                                   0, 0, k, nullptr, nullptr, s);
     if (st != VMAS_OK) return st;
   }
+  // The sphere reverse step reads only the positions of a step's state when
+  // no entity has a speed cap (the clamp's adjoint needs the velocities):
+  // the replays then write x and y only.
+  const bool xy = b->spheres_only && b->all_move && !b->any_vmax;
   // backward: replay each segment from its checkpoint, then step back through it
   HIPCHK(hipMemcpyAsync(g0, grad_state_T, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
   for (int q = nseg - 1; q >= 0; --q) {
@@ -1594,7 +1607,7 @@ vmas_status backward_on(vmas_batch* b, float* ws, const float* state0, const flo
     float* st_tmp = g1;  // scratch for the rolled state, overwritten below
     HIPCHK(hipMemcpyAsync(st_tmp, seg, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
     vmas_status st = rollout_impl(b, st_tmp, actions ? actions + A2 * (size_t)t0 : nullptr, 0, 0, len,
-                                  seg, nullptr, s);
+                                  seg, nullptr, s, xy);
     if (st != VMAS_OK) return st;
     // the reverse steps of the segment in one launch
     st = adjoint_segment(b, seg, actions ? actions + A2 * (size_t)t0 : nullptr, len, g0, g1,
