@@ -35,9 +35,11 @@ __device__ __forceinline__ float circle_radius(int shape, float d0, float d1) {
   return 0.5f * d0;
 }
 
-// SPH: sphere-only batch (only the sphere pair code is compiled in).
+// SPH: sphere-only batch (only the sphere pair code is compiled in); held to
+// 128 VGPRs, four wavefronts per SIMD (a few bytes of spills: faster than
+// three wavefronts without).
 template <int MAXB, bool SPH>
-__global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
+__global__ void __launch_bounds__(MAXB, SPH ? 4 : 1) k_step_backward(BackArgs a) {
   extern __shared__ float4 lds[];
   const int E = a.max_stage;
   float4* pose = lds;          // x, y, cos, sin
@@ -114,11 +116,32 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
     }
   };
   if (SPH && a.T > 0) fetch(a.T - 1);
+  bool uni = false;  // sphere batches: the equal-radius test (set at the first step)
+  float dm2u = 0.0f;
+  {
+    const float dmu = (p.rho + p.rho) + w.min_dist;
+    dm2u = __fmul_rn(dmu, dmu);
+  }
   for (int t = a.T - 1; t >= 0; --t) {
     const float* state = a.state + (size_t)t * 6 * N;
     const float* actions = a.actions ? a.actions + (size_t)t * 2 * w.A : nullptr;
     float* gact = a.gact ? a.gact + (size_t)t * 2 * w.A : nullptr;
     lds_barrier();  // the previous step's readers of pose and adj are done
+    if (SPH && t == a.T - 1) {
+      // Equal radii (static, once the records are staged): when every
+      // partner of every lane of the wavefront collides, moves and has the
+      // lane's own radius, each contact distance is the lane's
+      // (r + r) + d_min -- the value the per-partner sum gives.
+      bool eq = true;
+      if (collide)
+        for (int q = r.lo; q < r.hi; ++q) {
+          const float4 S = stat[q];
+          const int of = (__float_as_int(S.w) >> 8) & 0xff;
+          eq &= q == r.slot ||
+                (S.z == p.rho && (of & COLLIDABLE) && (of & (MOVABLE | ROTATABLE)));
+        }
+      uni = __builtin_amdgcn_ballot_w64(collide && !eq) == 0;
+    }
     float x = 0, y = 0, vx = 0, vy = 0, th = 0;
     if constexpr (SPH) {
       // a sphere's orientation enters no sphere pair
@@ -242,6 +265,24 @@ __global__ void __launch_bounds__(MAXB) k_step_backward(BackArgs a) {
         for (int q0 = r.lo; q0 < r.hi; q0 += 64) {
           const int cnt = min(64, r.hi - q0);
           uint32_t mlo = 0u, mhi = 0u;  // shift_in masks of partners 0..31, 32..63
+          if (uni) {
+            // every partner collides and moves with the lane's own radius:
+            // the partners' positions are all the test reads
+            for (int b0 = 0; b0 < cnt; b0 += 8) {
+              float2 P[8];
+#pragma unroll
+              for (int v = 0; v < 8; ++v)
+                P[v] = *reinterpret_cast<const float2*>(&pose[min(q0 + b0 + v, r.hi - 1)].x);
+#pragma unroll
+              for (int v = 0; v < 8; ++v) {
+                const int q = q0 + b0 + v;
+                const float dx = x - P[v].x, dy = y - P[v].y;
+                const bool hit = fmaf(dx, dx, __fmul_rn(dy, dy)) <= dm2u;
+                if (b0 < 32) mlo = shift_in(mlo, q < r.hi && q != r.slot && hit);
+                else mhi = shift_in(mhi, q < r.hi && q != r.slot && hit);
+              }
+            }
+          } else
           for (int b0 = 0; b0 < cnt; b0 += 8) {
             float4 P[8], S[8];
 #pragma unroll

@@ -253,6 +253,49 @@ def test_rollout_backward_equals_step_chain(kind):
     assert torch.equal(ga.view(T, -1), ga2)
 
 
+@pytest.mark.parametrize("min_dist", [0.0, 0.01])
+def test_equal_radius_reverse_path_bitwise(min_dist):
+    """Sphere environments whose spheres all collide, move and share one
+    radius take the reverse step's test that reads the partners' positions
+    only, and replays that write positions only; the same environments with
+    one far, static, non-colliding sphere appended take the test that reads
+    every partner's record, and full replays. The original entities'
+    gradients (state and actions) agree bit for bit."""
+    w = dataclasses.replace(W.uneven(96, lo=2, hi=40, radius=0.08, seed=12), min_dist=min_dist)
+    n = np.diff(w.env_offset)
+    off2 = np.concatenate([[0], np.cumsum(n + 1)]).astype(np.int32)
+    N2 = int(off2[-1])
+    keep = np.concatenate([np.arange(off2[e], off2[e] + n[e]) for e in range(w.n_envs)])
+    dummy = off2[1:] - 1
+    dims = np.zeros((N2, 2), np.float32)
+    dims[:, 0] = 0.08
+    flags = np.zeros(N2, np.uint8)
+    flags[keep] = w.flags
+    st = np.zeros((6, N2), np.float32)
+    st[:, keep] = w.state0
+    st[0, dummy] = 50.0
+    st[1, dummy] = 50.0
+    w2 = W.World(env_offset=off2, n_agents=w.n_agents.copy(), shape=np.zeros(N2, np.uint8),
+                 dims=dims, mass=np.ones(N2, np.float32), flags=flags, state0=st, seed=w.seed,
+                 name="uneven96+dummy", min_dist=min_dist)
+    T = 20
+    acts = w.actions(T)
+    gT = np.random.default_rng(3).standard_normal((6, w.n_entities)).astype(np.float32)
+    gT2 = np.zeros((6, N2), np.float32)
+    gT2[:, keep] = gT
+    outs = []
+    for ww, g in ((w, gT), (w2, gT2)):
+        b = _batch(ww)
+        gs = torch.zeros(6 * ww.n_entities, device="cuda:0")
+        ga = torch.zeros(acts.size, device="cuda:0")
+        b.rollout_backward(_dev(ww.state0), _dev(acts), _dev(g), 5, gs, ga)
+        torch.cuda.synchronize()
+        outs.append((gs.view(6, -1).cpu().numpy(), ga.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0][:, keep])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.any(outs[0][0] != gT)  # contacts changed the gradient
+
+
 def test_autograd_rollout_matches_direct_call():
     from paper_2207_03530_amd import autograd as AG
     w = W.mixed(16, n_spheres=6, n_boxes=2, n_lines=3, seed=9)
