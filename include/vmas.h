@@ -245,7 +245,9 @@ vmas_status vmas_rollout_backward_noalloc(vmas_batch* batch, const float* state0
  * or rotates, whole environments per workgroup of <block> lanes, in natural
  * or size order), "pair-queue/<block>/<order>" (batches with boxes or
  * segments, environments of at most 32 entities: every pair tested and
- * evaluated once from LDS queues), "quad/256" (sphere batches with at most 4
+ * evaluated once from LDS queues), "pair-queue/<block>/natural/even" (the
+ * same with a whole number of workgroups per compute unit, each filled to an
+ * equal share of the lanes), "quad/256" (sphere batches with at most 4
  * movers and 4 static collidable entities per environment),
  * "quad-ordered/64" (the same when the movers are the first entities of
  * every environment), "bucketed/<lo>-<hi>:<plan>/..." (sphere batches whose
