@@ -93,14 +93,14 @@ __global__ void __launch_bounds__(MAXB, SPH ? 4 : 1) k_step_backward(BackArgs a)
   // lane's own centre, and its velocity only under a speed cap (the
   // clamp's adjoint is the one use of it; a sphere's angle and omega enter
   // nothing, omega's step being linear in damping and torque). Without
-  // speed caps the trajectory may hold positions only. The general kernel,
+  // speed caps the states may be positions only (stride 2 N). The general kernel,
   // at the edge of its register budget, loads its state at the top of each
   // step.
   const int e_st = SPH && l < ns ? a.stage[s0 + l] : 0;
   const int jlo = SPH && act ? a.joff[r.ent] : 0, jhi = SPH && act ? a.joff[r.ent + 1] : 0;
   float px = 0, py = 0, sx = 0, sy = 0, svx = 0, svy = 0;
   auto fetch = [&](int t) {
-    const float* st = a.state + (size_t)t * 6 * N;
+    const float* st = a.state + (size_t)t * a.stride;
     if (l < ns) {
       px = st[e_st];
       py = st[N + e_st];
@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(MAXB, SPH ? 4 : 1) k_step_backward(BackArgs a)
     dm2u = __fmul_rn(dmu, dmu);
   }
   for (int t = a.T - 1; t >= 0; --t) {
-    const float* state = a.state + (size_t)t * 6 * N;
+    const float* state = a.state + (size_t)t * a.stride;
     const float* actions = a.actions ? a.actions + (size_t)t * 2 * w.A : nullptr;
     float* gact = a.gact ? a.gact + (size_t)t * 2 * w.A : nullptr;
     lds_barrier();  // the previous step's readers of pose and adj are done

@@ -126,8 +126,8 @@ struct StepArgs {
                                // force (+0) and a finite 1/I >= 0: a sphere is then
                                // fully described by its SphRec (d0 = rho, d1 = 0,
                                // no joint exclusions, m g = 0; 0 x 1/I = +0)
-  int32_t traj_xy;             // 1: the trajectory gets x and y only (the other
-                               // components of its slots are not written)
+  int32_t traj_xy;             // 1: the trajectory holds positions only, compact:
+                               // [T+1][2][N] (x, y of every slot)
   WorldK w;
 };
 
@@ -147,7 +147,9 @@ __device__ __forceinline__ void lds_barrier() {
 
 // Arguments of the adjoint kernel (one step backwards).
 struct BackArgs {
-  const float* state;      // [T][6][N] states t0 .. t0 + T - 1
+  const float* state;      // [T][6][N] states t0 .. t0 + T - 1 (sphere batches
+                           // without speed caps: [T][2][N] positions suffice)
+  int64_t stride;          // floats from one step's state to the next (6 N or 2 N)
   const float* actions;    // [T][A][2] actions of the same steps
   const float* gnext;      // [6][N] dL/ds_{t0+T}
   float* gstate;           // [6][N] dL/ds_t0

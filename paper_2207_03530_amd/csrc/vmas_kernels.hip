@@ -570,7 +570,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout(StepArgs a) {
       th = fmaf(om, w.dt, th);
     }
     if (a.traj && act) {
-      float* o = a.traj + (size_t)(t + 1) * 6 * N;
+      float* o = a.traj + (size_t)(t + 1) * (a.traj_xy ? 2 : 6) * N;
       o[r.ent] = x;
       o[N + r.ent] = y;
       if (!a.traj_xy) {
@@ -953,7 +953,7 @@ __global__ void __launch_bounds__(MAXB) k_rollout_sph(StepArgs a) {
           th = fmaf(om, w.dt, th);
         }
         if (OUT && a.traj && act) {
-          float* o = a.traj + (size_t)(t + 1) * 6 * N;
+          float* o = a.traj + (size_t)(t + 1) * (a.traj_xy ? 2 : 6) * N;
           o[r.ent] = x;
           o[N + r.ent] = y;
           if (!a.traj_xy) {
@@ -1172,7 +1172,7 @@ __global__ void __launch_bounds__(256) k_rollout_quad(StepArgs a) {
           th = fmaf(om, w.dt, th);
         }
         if (OUT && a.traj && act) {
-          float* out = a.traj + (size_t)(t + 1) * 6 * N;
+          float* out = a.traj + (size_t)(t + 1) * (a.traj_xy ? 2 : 6) * N;
           out[e] = x;
           out[N + e] = y;
           if (!a.traj_xy) {
@@ -1439,7 +1439,7 @@ __global__ void __launch_bounds__(64) k_rollout_quad_ord(StepArgs a) {
         th = fmaf(om, w.dt, th);
       }
       if (OUT && a.traj && act) {
-        float* out = a.traj + (size_t)(t + 1) * 6 * N;
+        float* out = a.traj + (size_t)(t + 1) * (a.traj_xy ? 2 : 6) * N;
         out[e] = x;
         out[N + e] = y;
         if (!a.traj_xy) {

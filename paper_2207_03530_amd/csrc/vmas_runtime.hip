@@ -1506,11 +1506,15 @@ vmas_status vmas_autotune(vmas_batch* b, const float* state, const float* action
 
 // T reverse steps in one launch: states [T][6][N] (t0 .. t0 + T - 1), their
 // actions [T][A][2], dL/ds_{t0+T} -> dL/ds_t0 and dL/da of every step.
-static vmas_status adjoint_segment(vmas_batch* b, const float* states, const float* actions, int T,
-                                   const float* gnext, float* gstate, float* gact, hipStream_t s) {
+// states: T states, `stride` floats apart (6 N; 2 N for positions only,
+// which the sphere reverse step accepts when no entity has a speed cap).
+static vmas_status adjoint_segment(vmas_batch* b, const float* states, int64_t stride,
+                                   const float* actions, int T, const float* gnext, float* gstate,
+                                   float* gact, hipStream_t s) {
   // Entities without a lane in no group (environments of size 0) keep a zero gradient.
   BackArgs a{};
   a.state = states;
+  a.stride = stride;
   a.actions = actions;
   a.gnext = gnext;
   a.gstate = gstate;
@@ -1546,7 +1550,8 @@ vmas_status vmas_step_backward(vmas_batch* b, const float* state_t, const float*
   DeviceGuard guard(b->device);
   vmas_status st = report_nonfinite(b, (hipStream_t)stream);
   if (st != VMAS_OK) return st;
-  return adjoint_segment(b, state_t, actions_t, 1, grad_state_next, grad_state_t, grad_actions_t,
+  return adjoint_segment(b, state_t, 6 * (int64_t)b->N, actions_t, 1, grad_state_next, grad_state_t,
+                         grad_actions_t,
                          (hipStream_t)stream);
 }
 
@@ -1579,39 +1584,74 @@ vmas_status backward_on(vmas_batch* b, float* ws, const float* state0, const flo
                         float* grad_state0, float* grad_actions, hipStream_t s) {
   const int k = std::min(ckpt_every, T);
   const int nseg = (T + k - 1) / k;
-  const size_t S6 = 6 * (size_t)b->N;
-  float* ckpt = ws;
-  float* seg = ckpt + S6 * nseg;
-  float* g0 = seg + S6 * (k + 1);
-  float* g1 = g0 + S6;
+  const size_t S6 = 6 * (size_t)b->N, S2 = 2 * (size_t)b->N;
   const size_t A2 = 2 * (size_t)b->A;
-  // forward: checkpoints at t = 0, k, 2k, ...
-  HIPCHK(hipMemcpyAsync(ckpt, state0, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
-  for (int q = 1; q < nseg; ++q) {
+  auto act_at = [&](int t) { return actions ? actions + A2 * (size_t)t : nullptr; };
+  // the workspace: room for nseg + k + 1 states, then two gradient buffers
+  const size_t room = S6 * ((size_t)nseg + k + 1);
+  float* g0 = ws + room;
+  float* g1 = g0 + S6;
+  // The sphere reverse step reads only the positions of a step's state when
+  // no entity has a speed cap (the clamp's adjoint needs the velocities).
+  // Positions are 2 N floats a step, so the same room then holds more than
+  // checkpoints: the last segments m .. nseg-1 keep the positions of one
+  // forward launch over their steps and are not replayed; m is the first
+  // segment for which the checkpoints of the segments before it, a compact
+  // replay buffer and the kept positions fit. Otherwise every segment is
+  // replayed from its checkpoint (full states).
+  const bool xy = b->spheres_only && b->all_move && !b->any_vmax;
+  int m = nseg;
+  if (xy)
+    for (int q = 0; q <= nseg; ++q) {
+      const size_t need = (q > 0 ? S6 * q + S2 * ((size_t)k + 1) : 0) +
+                          (q < nseg ? S2 * ((size_t)T - (size_t)q * k + 1) : 0);
+      if (need <= room) {
+        m = q;
+        break;
+      }
+    }
+  const int nck = xy ? m : nseg;      // checkpoints at t = 0, k, .., (nck - 1) k
+  const size_t slot = xy ? S2 : S6;  // one state of a replayed or kept trajectory
+  float* ckpt = ws;
+  float* seg = ckpt + S6 * nck;  // replay of one segment: k + 1 states (when m > 0)
+  float* kept = m > 0 ? seg + slot * ((size_t)k + 1) : ws;  // positions of steps m k .. T
+  if (nck > 0) HIPCHK(hipMemcpyAsync(ckpt, state0, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  for (int q = 1; q < nck; ++q) {
     HIPCHK(hipMemcpyAsync(ckpt + S6 * q, ckpt + S6 * (q - 1), S6 * sizeof(float),
                           hipMemcpyDeviceToDevice, s));
-    vmas_status st = rollout_impl(b, ckpt + S6 * q, actions ? actions + A2 * (size_t)(q - 1) * k : nullptr,
-                                  0, 0, k, nullptr, nullptr, s);
+    vmas_status st = rollout_impl(b, ckpt + S6 * q, act_at((q - 1) * k), 0, 0, k, nullptr, nullptr, s);
     if (st != VMAS_OK) return st;
   }
-  // The sphere reverse step reads only the positions of a step's state when
-  // no entity has a speed cap (the clamp's adjoint needs the velocities):
-  // the replays then write x and y only.
-  const bool xy = b->spheres_only && b->all_move && !b->any_vmax;
-  // backward: replay each segment from its checkpoint, then step back through it
+  if (m < nseg) {
+    // the state at t = m k (in g1, free until the reverse steps), then one
+    // launch over the kept steps that writes their positions
+    if (m == 0) {
+      HIPCHK(hipMemcpyAsync(g1, state0, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+    } else {
+      HIPCHK(hipMemcpyAsync(g1, ckpt + S6 * (m - 1), S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+      vmas_status st = rollout_impl(b, g1, act_at((m - 1) * k), 0, 0, k, nullptr, nullptr, s);
+      if (st != VMAS_OK) return st;
+    }
+    vmas_status st = rollout_impl(b, g1, act_at(m * k), 0, 0, T - m * k, kept, nullptr, s, true);
+    if (st != VMAS_OK) return st;
+  }
+  // backward: each segment's states (kept, or replayed from its checkpoint),
+  // then its reverse steps in one launch
   HIPCHK(hipMemcpyAsync(g0, grad_state_T, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
   for (int q = nseg - 1; q >= 0; --q) {
     const int t0 = q * k, len = std::min(k, T - t0);
-    HIPCHK(hipMemcpyAsync(seg, ckpt + S6 * q, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
-    // seg[0 .. len]: states t0 .. t0 + len (the rollout writes them as a trajectory)
-    float* st_tmp = g1;  // scratch for the rolled state, overwritten below
-    HIPCHK(hipMemcpyAsync(st_tmp, seg, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
-    vmas_status st = rollout_impl(b, st_tmp, actions ? actions + A2 * (size_t)t0 : nullptr, 0, 0, len,
-                                  seg, nullptr, s, xy);
-    if (st != VMAS_OK) return st;
-    // the reverse steps of the segment in one launch
-    st = adjoint_segment(b, seg, actions ? actions + A2 * (size_t)t0 : nullptr, len, g0, g1,
-                         grad_actions ? grad_actions + A2 * (size_t)t0 : nullptr, s);
+    const float* states = seg;
+    if (q >= m) {
+      states = kept + S2 * ((size_t)t0 - (size_t)m * k);
+    } else {
+      // seg[0 .. len]: states t0 .. t0 + len (the rollout writes them as a
+      // trajectory; g1 is the rolled state's scratch, overwritten below)
+      HIPCHK(hipMemcpyAsync(g1, ckpt + S6 * q, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+      vmas_status st = rollout_impl(b, g1, act_at(t0), 0, 0, len, seg, nullptr, s, xy);
+      if (st != VMAS_OK) return st;
+    }
+    vmas_status st = adjoint_segment(b, states, (int64_t)slot, act_at(t0), len, g0, g1,
+                                     grad_actions ? grad_actions + A2 * (size_t)t0 : nullptr, s);
     if (st != VMAS_OK) return st;
     std::swap(g0, g1);
   }

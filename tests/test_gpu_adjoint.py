@@ -200,14 +200,23 @@ def test_rollout_gradient_vs_finite_differences():
     assert compared >= 0.5 * 6 * w.n_envs
 
 
-def test_checkpoint_stride_does_not_change_gradients():
-    w = W.mixed(32, n_spheres=6, n_boxes=2, n_lines=3, seed=2)
-    T = 24
+@pytest.mark.parametrize("kind", ["mixed", "spheres"])
+def test_checkpoint_stride_does_not_change_gradients(kind):
+    """Every checkpoint interval gives the same bits. The sphere batch (every
+    entity moves, no speed cap) keeps the positions of its last segments
+    from one forward launch: all of them at k = 1 and k = T, the last three
+    of five at k = 10 (the first two replayed from checkpoints)."""
+    if kind == "mixed":
+        w = W.mixed(32, n_spheres=6, n_boxes=2, n_lines=3, seed=2)
+        T, ks = 24, (1, 5, 24, 100)
+    else:
+        w = W.uneven(48, lo=2, hi=20, radius=0.08, seed=13)
+        T, ks = 50, (1, 10, 7, 50, 100)
     acts = _dev(w.actions(T))
     b = _batch(w)
     gT = _dev(np.random.default_rng(1).standard_normal((6, w.n_entities)))
     outs = []
-    for k in (1, 5, 24, 100):
+    for k in ks:
         gs = torch.zeros(6 * w.n_entities, device="cuda:0")
         ga = torch.zeros(acts.numel(), device="cuda:0")
         b.rollout_backward(_dev(w.state0), acts, gT, k, gs, ga)
