@@ -1642,23 +1642,24 @@ vmas_status backward_on(vmas_batch* b, float* ws, const float* state0, const flo
     vmas_status st = rollout_impl(b, g1, act_at(m * k), 0, 0, T - m * k, kept, nullptr, s, true);
     if (st != VMAS_OK) return st;
   }
-  // backward: each segment's states (kept, or replayed from its checkpoint),
-  // then its reverse steps in one launch
+  // backward: the reverse steps of all kept steps in one launch, then of
+  // each replayed segment (replayed from its checkpoint) in one launch
+  auto gact_at = [&](int t) { return grad_actions ? grad_actions + A2 * (size_t)t : nullptr; };
   HIPCHK(hipMemcpyAsync(g0, grad_state_T, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
-  for (int q = nseg - 1; q >= 0; --q) {
+  if (m < nseg) {
+    vmas_status st = adjoint_segment(b, kept, (int64_t)S2, act_at(m * k), T - m * k, g0, g1,
+                                     gact_at(m * k), s);
+    if (st != VMAS_OK) return st;
+    std::swap(g0, g1);
+  }
+  for (int q = m - 1; q >= 0; --q) {
     const int t0 = q * k, len = std::min(k, T - t0);
-    const float* states = seg;
-    if (q >= m) {
-      states = kept + S2 * ((size_t)t0 - (size_t)m * k);
-    } else {
-      // seg[0 .. len]: states t0 .. t0 + len (the rollout writes them as a
-      // trajectory; g1 is the rolled state's scratch, overwritten below)
-      HIPCHK(hipMemcpyAsync(g1, ckpt + S6 * q, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
-      vmas_status st = rollout_impl(b, g1, act_at(t0), 0, 0, len, seg, nullptr, s, xy);
-      if (st != VMAS_OK) return st;
-    }
-    vmas_status st = adjoint_segment(b, states, (int64_t)slot, act_at(t0), len, g0, g1,
-                                     grad_actions ? grad_actions + A2 * (size_t)t0 : nullptr, s);
+    // seg[0 .. len]: states t0 .. t0 + len (the rollout writes them as a
+    // trajectory; g1 is the rolled state's scratch, overwritten below)
+    HIPCHK(hipMemcpyAsync(g1, ckpt + S6 * q, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+    vmas_status st = rollout_impl(b, g1, act_at(t0), 0, 0, len, seg, nullptr, s, xy);
+    if (st != VMAS_OK) return st;
+    st = adjoint_segment(b, seg, (int64_t)slot, act_at(t0), len, g0, g1, gact_at(t0), s);
     if (st != VMAS_OK) return st;
     std::swap(g0, g1);
   }
