@@ -1630,13 +1630,15 @@ vmas_status backward_on(vmas_batch* b, float* ws, const float* state0, const flo
     if (st != VMAS_OK) return st;
   }
   if (m < nseg) {
-    // the state at t = m k (in g1, free until the reverse steps), then one
-    // launch over the kept steps that writes their positions
+    // the state at t = m k (in g1, free until the reverse steps): segment
+    // m - 1's launch leaves that segment's positions in the replay buffer,
+    // where its reverse steps find them; then one launch over the kept
+    // steps that writes their positions
     if (m == 0) {
       HIPCHK(hipMemcpyAsync(g1, state0, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
     } else {
       HIPCHK(hipMemcpyAsync(g1, ckpt + S6 * (m - 1), S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
-      vmas_status st = rollout_impl(b, g1, act_at((m - 1) * k), 0, 0, k, nullptr, nullptr, s);
+      vmas_status st = rollout_impl(b, g1, act_at((m - 1) * k), 0, 0, k, seg, nullptr, s, true);
       if (st != VMAS_OK) return st;
     }
     vmas_status st = rollout_impl(b, g1, act_at(m * k), 0, 0, T - m * k, kept, nullptr, s, true);
@@ -1654,11 +1656,14 @@ vmas_status backward_on(vmas_batch* b, float* ws, const float* state0, const flo
   }
   for (int q = m - 1; q >= 0; --q) {
     const int t0 = q * k, len = std::min(k, T - t0);
-    // seg[0 .. len]: states t0 .. t0 + len (the rollout writes them as a
-    // trajectory; g1 is the rolled state's scratch, overwritten below)
-    HIPCHK(hipMemcpyAsync(g1, ckpt + S6 * q, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
-    vmas_status st = rollout_impl(b, g1, act_at(t0), 0, 0, len, seg, nullptr, s, xy);
-    if (st != VMAS_OK) return st;
+    vmas_status st = VMAS_OK;
+    if (!(m < nseg && q == m - 1)) {  // segment m - 1 is already in the replay buffer
+      // seg[0 .. len]: states t0 .. t0 + len (the rollout writes them as a
+      // trajectory; g1 is the rolled state's scratch, overwritten below)
+      HIPCHK(hipMemcpyAsync(g1, ckpt + S6 * q, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+      st = rollout_impl(b, g1, act_at(t0), 0, 0, len, seg, nullptr, s, xy);
+      if (st != VMAS_OK) return st;
+    }
     st = adjoint_segment(b, seg, (int64_t)slot, act_at(t0), len, g0, g1, gact_at(t0), s);
     if (st != VMAS_OK) return st;
     std::swap(g0, g1);
