@@ -1,7 +1,7 @@
 """Host logic of bench.py, without a GPU: the algorithmic byte count of the
-spread workload, the kernel named for each launch plan, and the traffic
+spread workload, the kernel named for each launch plan, the traffic
 summary written from two rocprofv3 counter collections (calibrated by the
-plain copy of known size)."""
+plain copy of known size), and when a summary is reported."""
 import csv
 import json
 import os
@@ -59,3 +59,19 @@ def test_traffic_summary(tmp_path, monkeypatch):
     assert d["fetch_kib_per_dispatch_raw"] == 51000.0
     assert d["hbm_bytes_per_launch"] == 51000.0 * 1024 * 2.0 + 4000.0 * 1024
     assert d["kernel_source_sha"] == bench.kernel_sha()
+
+
+def test_traffic_taken_only_for_the_same_sources_and_plan(tmp_path, monkeypatch):
+    """A traffic summary is reported only for the kernel sources it was taken
+    on and, when a plan is named, for the plan it was taken under."""
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    d = {"kernel": "k_rollout", "schedule": "pair-queue/256/natural/even",
+         "kernel_source_sha": bench.kernel_sha(), "hbm_bytes_per_launch": 123.0}
+    (tmp_path / "k_rollout_mixed4096_traffic.json").write_text(json.dumps(d))
+    assert bench.traffic_per_launch("k_rollout", "mixed4096") == 123.0
+    assert bench.traffic_per_launch("k_rollout", "mixed4096", "pair-queue/256/natural/even") == 123.0
+    assert bench.traffic_per_launch("k_rollout", "mixed4096", "pair-queue/256/natural") is None
+    d["kernel_source_sha"] = "0" * 16
+    (tmp_path / "k_rollout_mixed4096_traffic.json").write_text(json.dumps(d))
+    assert bench.traffic_per_launch("k_rollout", "mixed4096") is None
+    assert bench.traffic_per_launch("k_rollout", "spread30k") is None  # no summary at all
