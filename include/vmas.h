@@ -214,8 +214,9 @@ vmas_status vmas_step_backward(vmas_batch* batch, const float* state_t, const fl
  * segment run in one launch, each computing what vmas_step_backward computes
  * (the same bits). Sphere batches in which every entity moves and none has
  * a speed cap need only positions in the reverse step (a third of a state):
- * in the same workspace the last segments then keep the positions of one
- * forward launch and are not replayed. Every ckpt_every gives the same bits.
+ * in the same workspace a window over the last segments then gets the
+ * positions of one forward launch and is not replayed. Every ckpt_every
+ * gives the same bits.
  *   state0        device float32 [6][N]: initial state
  *   actions       device float32 [T][A][2]
  *   grad_state_T  device float32 [6][N]: dL/d state_T

@@ -1598,75 +1598,86 @@ vmas_status backward_on(vmas_batch* b, float* ws, const float* state0, const flo
   const size_t room = S6 * ((size_t)nseg + k + 1);
   float* g0 = ws + room;
   float* g1 = g0 + S6;
+  auto gact_at = [&](int t) { return grad_actions ? grad_actions + A2 * (size_t)t : nullptr; };
   // The sphere reverse step reads only the positions of a step's state when
   // no entity has a speed cap (the clamp's adjoint needs the velocities).
-  // Positions are 2 N floats a step, so the same room then holds more than
-  // checkpoints: the last segments m .. nseg-1 keep the positions of one
-  // forward launch over their steps and are not replayed; m is the first
-  // segment for which the checkpoints of the segments before it, a compact
-  // replay buffer and the kept positions fit. Otherwise every segment is
-  // replayed from its checkpoint (full states).
   const bool xy = b->spheres_only && b->all_move && !b->any_vmax;
-  int m = nseg;
-  if (xy)
-    for (int q = 0; q <= nseg; ++q) {
-      const size_t need = (q > 0 ? S6 * q + S2 * ((size_t)k + 1) : 0) +
-                          (q < nseg ? S2 * ((size_t)T - (size_t)q * k + 1) : 0);
-      if (need <= room) {
-        m = q;
-        break;
-      }
-    }
-  const int nck = xy ? m : nseg;      // checkpoints at t = 0, k, .., (nck - 1) k
-  const size_t slot = xy ? S2 : S6;  // one state of a replayed or kept trajectory
-  float* ckpt = ws;
-  float* seg = ckpt + S6 * nck;  // replay of one segment: k + 1 states (when m > 0)
-  float* kept = m > 0 ? seg + slot * ((size_t)k + 1) : ws;  // positions of steps m k .. T
-  if (nck > 0) HIPCHK(hipMemcpyAsync(ckpt, state0, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
-  for (int q = 1; q < nck; ++q) {
-    HIPCHK(hipMemcpyAsync(ckpt + S6 * q, ckpt + S6 * (q - 1), S6 * sizeof(float),
-                          hipMemcpyDeviceToDevice, s));
-    vmas_status st = rollout_impl(b, ckpt + S6 * q, act_at((q - 1) * k), 0, 0, k, nullptr, nullptr, s);
-    if (st != VMAS_OK) return st;
-  }
-  if (m < nseg) {
-    // the state at t = m k (in g1, free until the reverse steps): segment
-    // m - 1's launch leaves that segment's positions in the replay buffer,
-    // where its reverse steps find them; then one launch over the kept
-    // steps that writes their positions
-    if (m == 0) {
-      HIPCHK(hipMemcpyAsync(g1, state0, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
-    } else {
-      HIPCHK(hipMemcpyAsync(g1, ckpt + S6 * (m - 1), S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
-      vmas_status st = rollout_impl(b, g1, act_at((m - 1) * k), 0, 0, k, seg, nullptr, s, true);
+  if (!xy) {
+    // checkpoints at t = 0, k, 2k, ..., then each segment replayed from its
+    // checkpoint (full states) and stepped back through in one launch
+    float* ckpt = ws;
+    float* seg = ckpt + S6 * nseg;
+    HIPCHK(hipMemcpyAsync(ckpt, state0, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+    for (int q = 1; q < nseg; ++q) {
+      HIPCHK(hipMemcpyAsync(ckpt + S6 * q, ckpt + S6 * (q - 1), S6 * sizeof(float),
+                            hipMemcpyDeviceToDevice, s));
+      vmas_status st = rollout_impl(b, ckpt + S6 * q, act_at((q - 1) * k), 0, 0, k, nullptr, nullptr, s);
       if (st != VMAS_OK) return st;
     }
-    vmas_status st = rollout_impl(b, g1, act_at(m * k), 0, 0, T - m * k, kept, nullptr, s, true);
-    if (st != VMAS_OK) return st;
-  }
-  // backward: the reverse steps of all kept steps in one launch, then of
-  // each replayed segment (replayed from its checkpoint) in one launch
-  auto gact_at = [&](int t) { return grad_actions ? grad_actions + A2 * (size_t)t : nullptr; };
-  HIPCHK(hipMemcpyAsync(g0, grad_state_T, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
-  if (m < nseg) {
-    vmas_status st = adjoint_segment(b, kept, (int64_t)S2, act_at(m * k), T - m * k, g0, g1,
-                                     gact_at(m * k), s);
-    if (st != VMAS_OK) return st;
-    std::swap(g0, g1);
-  }
-  for (int q = m - 1; q >= 0; --q) {
-    const int t0 = q * k, len = std::min(k, T - t0);
-    vmas_status st = VMAS_OK;
-    if (!(m < nseg && q == m - 1)) {  // segment m - 1 is already in the replay buffer
+    HIPCHK(hipMemcpyAsync(g0, grad_state_T, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+    for (int q = nseg - 1; q >= 0; --q) {
+      const int t0 = q * k, len = std::min(k, T - t0);
       // seg[0 .. len]: states t0 .. t0 + len (the rollout writes them as a
       // trajectory; g1 is the rolled state's scratch, overwritten below)
       HIPCHK(hipMemcpyAsync(g1, ckpt + S6 * q, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
-      st = rollout_impl(b, g1, act_at(t0), 0, 0, len, seg, nullptr, s, xy);
+      vmas_status st = rollout_impl(b, g1, act_at(t0), 0, 0, len, seg, nullptr, s);
+      if (st != VMAS_OK) return st;
+      st = adjoint_segment(b, seg, (int64_t)S6, act_at(t0), len, g0, g1, gact_at(t0), s);
+      if (st != VMAS_OK) return st;
+      std::swap(g0, g1);
+    }
+  } else {
+    // Positions are 2 N floats a step, so the same room holds more than
+    // checkpoints. A window of the last segments w .. nseg-1 gets the
+    // positions of all its steps from one forward launch, and its reverse
+    // steps run in one launch; segments 0 .. w-1 are replayed from their
+    // checkpoints (0 is state0 itself, 1 .. w-1 are stored) into the first
+    // k + 1 slots of the window, free by then. w is the first segment for
+    // which the stored checkpoints and the window fit (w = nseg: no window,
+    // every segment replayed).
+    int w = nseg;
+    for (int q = 0; q <= nseg; ++q) {
+      const size_t ck = S6 * (size_t)std::max(std::min(q, nseg) - 1, 0);
+      const size_t slots = q == nseg ? (size_t)k + 1
+                                     : (q == 0 ? (size_t)T + 1
+                                               : std::max((size_t)k + 1, (size_t)T - (size_t)q * k + 1));
+      if (ck + S2 * slots <= room) {
+        w = q;
+        break;
+      }
+    }
+    float* ckpt = ws;  // the state at j k (j = 1 .. w-1) at ckpt + S6 (j - 1)
+    float* win = ckpt + S6 * (size_t)std::max(w - 1, 0);
+    auto ck = [&](int j) -> const float* { return j == 0 ? state0 : ckpt + S6 * (size_t)(j - 1); };
+    for (int j = 1; j < w; ++j) {
+      HIPCHK(hipMemcpyAsync(ckpt + S6 * (j - 1), ck(j - 1), S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+      vmas_status st = rollout_impl(b, ckpt + S6 * (j - 1), act_at((j - 1) * k), 0, 0, k, nullptr, nullptr, s);
       if (st != VMAS_OK) return st;
     }
-    st = adjoint_segment(b, seg, (int64_t)slot, act_at(t0), len, g0, g1, gact_at(t0), s);
-    if (st != VMAS_OK) return st;
-    std::swap(g0, g1);
+    HIPCHK(hipMemcpyAsync(g0, grad_state_T, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (w < nseg) {
+      // the state at w k in g1 (free until the reverse steps), then the
+      // window's forward launch and its reverse steps
+      HIPCHK(hipMemcpyAsync(g1, ck(std::max(w - 1, 0)), S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+      if (w > 0) {
+        vmas_status st = rollout_impl(b, g1, act_at((w - 1) * k), 0, 0, k, nullptr, nullptr, s);
+        if (st != VMAS_OK) return st;
+      }
+      vmas_status st = rollout_impl(b, g1, act_at(w * k), 0, 0, T - w * k, win, nullptr, s, true);
+      if (st != VMAS_OK) return st;
+      st = adjoint_segment(b, win, (int64_t)S2, act_at(w * k), T - w * k, g0, g1, gact_at(w * k), s);
+      if (st != VMAS_OK) return st;
+      std::swap(g0, g1);
+    }
+    for (int q = std::min(w, nseg) - 1; q >= 0; --q) {
+      const int t0 = q * k, len = std::min(k, T - t0);
+      HIPCHK(hipMemcpyAsync(g1, ck(q), S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+      vmas_status st = rollout_impl(b, g1, act_at(t0), 0, 0, len, win, nullptr, s, true);
+      if (st != VMAS_OK) return st;
+      st = adjoint_segment(b, win, (int64_t)S2, act_at(t0), len, g0, g1, gact_at(t0), s);
+      if (st != VMAS_OK) return st;
+      std::swap(g0, g1);
+    }
   }
   if (grad_state0)
     HIPCHK(hipMemcpyAsync(grad_state0, g0, S6 * sizeof(float), hipMemcpyDeviceToDevice, s));
